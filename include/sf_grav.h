@@ -1,0 +1,202 @@
+/*
+ * sf_grav.h -- softened self-gravity (accelerations, potentials and their
+ * adjoint) for gas cells with adaptive softening plus sink particles, on one
+ * AMD Instinct MI355X (gfx950).  C ABI of libsfgrav.so.
+ *
+ * The operation (arXiv 2010.11254, Sec. 2.2 "Gravity"): the field g = -grad Phi
+ * and the potential Phi at the location of every gas cell and sink particle,
+ *     a_i   =  G sum_{j != i} m_j F(r_ij, h_ij) (x_j - x_i)
+ *     phi_i = -G sum_{j != i} m_j P(r_ij, h_ij)
+ * with the softened law of Sec. 2.2.1: pairs closer than h_ij = max(h_i, h_j)
+ * use the force of a unit mass smoothed by the M4 cubic spline of compact
+ * support h_ij (the kernel of the Sec. 2.1 footnote); beyond h_ij the law is
+ * exactly Newtonian.  The larger radius is used in both directions of every
+ * pair, so all interactions are antisymmetric.  P(0, h) = 2.8/h, i.e. the
+ * Plummer-equivalent softening is h/2.8 (Sec. 2.3.1).
+ *
+ * Two evaluation paths:
+ *   - tree   : Barnes-Hut octree (Sec. 2.2) over Morton-sorted particles,
+ *              monopole or quadrupole nodes, opening angle theta = L/r
+ *              (fiducial 0.5), walked by groups of up to 64 targets;
+ *   - direct : all pairs (the theta -> 0 limit of the tree).
+ * Sink targets always receive the sink-sink part of their field as an exact
+ * FP64 direct sum; their gas part comes from the same path as gas targets.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors).  `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream); every kernel is enqueued on it, in order.  The caller keeps
+ *     the buffers alive until the stream has finished the work.
+ *   - pos is row-major n x 3 (x0,y0,z0,x1,...), mass and soft have n entries.
+ *     All caller arrays of one call share the dtype `dt` (SF_F32 or SF_F64).
+ *     Particles [0, n_gas) are gas, [n_gas, n) are sinks.
+ *   - soft is the compact-support radius h (> 0): the law is Newtonian for
+ *     r >= max(h_i, h_j).
+ *   - Outputs are written (never accumulated) in the caller's dtype and
+ *     particle order.
+ *   - Every call returns an sf_status and never aborts or prints.  Argument
+ *     checks happen before anything is enqueued.  HIP failures map to
+ *     SF_E_DEVICE, allocation failures to SF_E_NOMEM (no partial handle is
+ *     leaked).  sf_grav_last_error() gives a message for the calling thread.
+ *   - The library allocates its device scratch with stream-ordered
+ *     allocation on `stream`.
+ */
+#ifndef SF_GRAV_H
+#define SF_GRAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sf_grav_tree_s *sf_grav_tree; /* opaque, library owned */
+
+typedef enum {
+    SF_OK = 0,
+    SF_E_INVALID = 1,     /* bad argument or option (nothing was enqueued)   */
+    SF_E_NOMEM = 2,       /* device or host allocation failed                 */
+    SF_E_DEVICE = 3,      /* a HIP call failed                                */
+    SF_E_STATE = 4,       /* handle does not match the call (n, dtype, ...)   */
+    SF_E_UNSUPPORTED = 5, /* option combination not implemented               */
+    SF_E_INTERNAL = 6     /* a kernel hit a fixed capacity (see message)      */
+} sf_status;
+
+typedef enum { SF_F32 = 0, SF_F64 = 1 } sf_dtype;
+
+/* Arithmetic form of the interaction kernels.
+ *   SF_FP32C: FP32 pair arithmetic on coordinates relative to the target
+ *             group's (or tile's) centre, per-target compensated (two-sum)
+ *             accumulation, FP64 node moments; output = round(hi + lo).
+ *   SF_FP32 : absolute FP32 coordinates, plain FP32 accumulation.
+ *   SF_FP64 : FP64 throughout.
+ * Node moments are always accumulated in FP64 and the sink-sink part is
+ * always FP64, whatever the form. */
+typedef enum { SF_FP32C = 0, SF_FP32 = 1, SF_FP64 = 2 } sf_form;
+
+typedef struct {
+    uint32_t struct_size; /* = sizeof(sf_grav_opts); ABI check              */
+    int32_t form;         /* sf_form, default SF_FP32C                       */
+    double G;             /* gravitational constant, default 1              */
+    double theta;         /* opening angle theta = L/r, >= 0, default 0.5   */
+    int32_t order;        /* node expansion: 0 monopole, 2 quadrupole; def 2 */
+    int32_t leaf_cap;     /* a cell holding more is split, 1..64, default 16 */
+    int32_t group_cap;    /* max targets per walk group, 1..64, default 64  */
+    int32_t validate;     /* 1: check finite inputs, h > 0, m >= 0 (one pass) */
+    int64_t n_gas;        /* particles [0,n_gas) are gas; default -1 = all   */
+    int32_t collect_stats;/* 1: record per-group interaction counts          */
+    int32_t reserved;
+} sf_grav_opts;
+
+/* Fill *o with the defaults above (struct_size set).  Never fails. */
+void sf_grav_opts_default(sf_grav_opts *o);
+
+/* Build the octree for the tree path (Sec. 2.2: recursive subdivision into
+ * octants).  Steps on `stream`: bounding box, 63-bit Morton keys (21 bits per
+ * axis, FP64 quantisation), stable LSD radix sort (ties keep input order),
+ * gather into sorted SoA, topology (a cell is split while it holds more than
+ * leaf_cap particles and is above level 21), FP64 moments (mass, centre of
+ * mass, traceless quadrupole, max softening; a second set over gas only, used
+ * for sink targets), and target groups.  One device->host read of the node
+ * and group counts synchronises `stream` once.
+ * The handle keeps its own sorted copy of pos/mass/soft: later calls on the
+ * handle use the values captured here.  Release with sf_grav_tree_free.
+ * Errors: SF_E_INVALID (NULL pointers, n < 1, n > 2^30, bad options),
+ * SF_E_NOMEM, SF_E_DEVICE. */
+sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft,
+                             int64_t n, sf_dtype dt, const sf_grav_opts *o,
+                             void *stream, sf_grav_tree *out);
+
+/* Accelerations (n x 3) and potentials (n; may be NULL) of every particle.
+ * tree != NULL: tree path on the handle's particles; n and dt must equal the
+ *   handle's (else SF_E_STATE); pos/mass/soft may be NULL (ignored).
+ *   theta, order, form, G come from *o; leaf_cap/group_cap from the build.
+ * tree == NULL: direct path over pos/mass/soft (all pairs, no tree kept).
+ * Errors: SF_E_INVALID, SF_E_STATE, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */
+sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass,
+                        const void *soft, int64_t n, sf_dtype dt,
+                        const sf_grav_opts *o, void *acc, void *pot, void *stream);
+
+/* Adjoint: given upstream gradients g_acc (n x 3) and g_pot (n, or NULL =
+ * zero) of a scalar loss L, write dL/dpos (n x 3), dL/dmass (n), dL/dsoft (n);
+ * any of the three outputs may be NULL.  For the tree path this is the exact
+ * derivative of the tree approximation with its opening decisions held fixed
+ * (the interaction lists are recomputed, not stored); it flows through node
+ * mass, centre of mass and quadrupole.  A pair's softening derivative goes to
+ * the particle with the larger radius (half to each on a tie).
+ * Same path selection and errors as sf_grav_accel. */
+sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
+                                 const void *mass, const void *soft, int64_t n,
+                                 sf_dtype dt, const sf_grav_opts *o,
+                                 const void *g_acc, const void *g_pot,
+                                 void *g_pos, void *g_mass, void *g_soft,
+                                 void *stream);
+
+/* Free a handle (synchronises the stream it was built on).  NULL is a no-op. */
+sf_status sf_grav_tree_free(sf_grav_tree tree);
+
+/* Sizes of a built tree. */
+typedef struct {
+    uint32_t struct_size;  /* = sizeof(sf_grav_tree_info) */
+    int32_t max_level;
+    int64_t n;
+    int64_t n_gas;
+    int64_t n_nodes;
+    int64_t n_groups;
+    int64_t n_leaves;
+} sf_grav_tree_info;
+
+sf_status sf_grav_get_tree_info(sf_grav_tree tree, sf_grav_tree_info *info);
+
+/* Copy one of the handle's arrays to host memory (synchronises the stream).
+ * `bytes` must equal the array's size exactly (count x element size).
+ *   SF_EXPORT_KEYS        uint64 [n]       sorted Morton keys
+ *   SF_EXPORT_ORDER       int32  [n]       sorted position -> input index
+ *   SF_EXPORT_NODE_LEVEL  int32  [n_nodes] node arrays, breadth-first:
+ *   SF_EXPORT_NODE_FIRST  int32  [n_nodes]   level 0, 1, ... ; within a level
+ *   SF_EXPORT_NODE_COUNT  int32  [n_nodes]   in particle order; children of a
+ *   SF_EXPORT_NODE_PARENT int32  [n_nodes]   node are contiguous (-1: none)
+ *   SF_EXPORT_NODE_CHILD  int32  [n_nodes] first child index (-1 for leaves)
+ *   SF_EXPORT_NODE_NCHILD int32  [n_nodes]
+ *   SF_EXPORT_GROUP_FIRST int32  [n_groups] target groups in particle order
+ *   SF_EXPORT_GROUP_COUNT int32  [n_groups]
+ *   SF_EXPORT_NODE_MASS   double [n_nodes] node mass (all particles)
+ *   SF_EXPORT_NODE_COM    double [n_nodes x 3] centre of mass
+ *   SF_EXPORT_NODE_QUAD   double [n_nodes x 6] Qxx Qyy Qzz Qxy Qxz Qyz
+ *   SF_EXPORT_GROUP_NPC   int32  [n_groups] accepted nodes of the last
+ *   SF_EXPORT_GROUP_NPP   int32  [n_groups]   accel with collect_stats=1, and
+ *                                             opened-leaf particles
+ * Errors: SF_E_INVALID (unknown id, NULL, wrong size), SF_E_STATE (stats not
+ * collected), SF_E_DEVICE. */
+typedef enum {
+    SF_EXPORT_KEYS = 0,
+    SF_EXPORT_ORDER = 1,
+    SF_EXPORT_NODE_LEVEL = 2,
+    SF_EXPORT_NODE_FIRST = 3,
+    SF_EXPORT_NODE_COUNT = 4,
+    SF_EXPORT_NODE_PARENT = 5,
+    SF_EXPORT_NODE_CHILD = 6,
+    SF_EXPORT_NODE_NCHILD = 7,
+    SF_EXPORT_GROUP_FIRST = 8,
+    SF_EXPORT_GROUP_COUNT = 9,
+    SF_EXPORT_NODE_MASS = 10,
+    SF_EXPORT_NODE_COM = 11,
+    SF_EXPORT_NODE_QUAD = 12,
+    SF_EXPORT_GROUP_NPC = 13,
+    SF_EXPORT_GROUP_NPP = 14
+} sf_export_id;
+
+sf_status sf_grav_tree_export(sf_grav_tree tree, int32_t what, void *host_dst,
+                              size_t bytes);
+
+/* Static text for a status code. */
+const char *sf_grav_strerror(sf_status s);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *sf_grav_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SF_GRAV_H */

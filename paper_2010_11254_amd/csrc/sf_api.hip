@@ -1,0 +1,351 @@
+// sf_api.hip -- the C ABI of libsfgrav.so: argument checks, handle life
+// cycle, path selection.  Every entry point returns an sf_status; nothing
+// here aborts or prints.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "sf_build.h"
+#include "sf_prims.h"
+
+namespace {
+thread_local char g_msg[512] = "";
+}
+
+sf_status sf_fail(sf_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+namespace sf {
+
+sf_status DevArena::alloc(void **p, size_t bytes, bool temp) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e != hipSuccess || *p == nullptr) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return sf_fail(SF_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes,
+                       hipGetErrorString(e));
+    }
+    (temp ? tmp : keep).push_back(*p);
+    return SF_OK;
+}
+
+void DevArena::free_tmp() {
+    for (void *p : tmp) hipFreeAsync(p, s);
+    tmp.clear();
+}
+
+void DevArena::free_keep() {
+    for (void *p : keep) hipFreeAsync(p, s);
+    keep.clear();
+}
+
+}  // namespace sf
+
+using sf::DevArena;
+
+static sf_status check_opts(const sf_grav_opts *o, int64_t n, bool need_tree_caps) {
+    if (!o) return sf_fail(SF_E_INVALID, "opts is NULL");
+    if (o->struct_size != sizeof(sf_grav_opts))
+        return sf_fail(SF_E_INVALID, "opts.struct_size %u != %zu", o->struct_size, sizeof(sf_grav_opts));
+    if (o->form != SF_FP32C && o->form != SF_FP32 && o->form != SF_FP64)
+        return sf_fail(SF_E_INVALID, "opts.form %d unknown", o->form);
+    if (!(o->theta >= 0.0) || !(o->theta < 1e30))
+        return sf_fail(SF_E_INVALID, "opts.theta must be finite and >= 0");
+    if (o->order != 0 && o->order != 2) return sf_fail(SF_E_INVALID, "opts.order must be 0 or 2");
+    if (need_tree_caps) {
+        if (o->leaf_cap < 1 || o->leaf_cap > 64)
+            return sf_fail(SF_E_INVALID, "opts.leaf_cap must be in [1, 64]");
+        if (o->group_cap < 1 || o->group_cap > 64)
+            return sf_fail(SF_E_INVALID, "opts.group_cap must be in [1, 64]");
+    }
+    if (!(o->G == o->G) || o->G > 1e300 || o->G < -1e300)
+        return sf_fail(SF_E_INVALID, "opts.G must be finite");
+    const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
+    if (ng > n) return sf_fail(SF_E_INVALID, "opts.n_gas %lld > n %lld", (long long)ng, (long long)n);
+    return SF_OK;
+}
+
+static const int64_t kMaxN = 1ll << 25;
+
+static sf_status check_arrays(const void *pos, const void *mass, const void *soft, int64_t n,
+                              sf_dtype dt) {
+    if (dt != SF_F32 && dt != SF_F64) return sf_fail(SF_E_INVALID, "dtype %d unknown", (int)dt);
+    if (n < 1) return sf_fail(SF_E_INVALID, "n must be >= 1 (got %lld)", (long long)n);
+    if (n > kMaxN)
+        return sf_fail(SF_E_UNSUPPORTED, "n = %lld exceeds the supported maximum %lld",
+                       (long long)n, (long long)kMaxN);
+    if (!pos || !mass || !soft) return sf_fail(SF_E_INVALID, "pos, mass and soft must be non-NULL");
+    return SF_OK;
+}
+
+static void free_handle_memory(sf_grav_tree_s *t) {
+    if (!t) return;
+    if (t->stream || true) hipStreamSynchronize(t->stream);
+    for (void *p : t->allocs) hipFree(p);
+    t->allocs.clear();
+}
+
+extern "C" {
+
+void sf_grav_opts_default(sf_grav_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(sf_grav_opts);
+    o->form = SF_FP32C;
+    o->G = 1.0;
+    o->theta = 0.5;
+    o->order = 2;
+    o->leaf_cap = 16;
+    o->group_cap = 64;
+    o->validate = 0;
+    o->n_gas = -1;
+    o->collect_stats = 0;
+}
+
+const char *sf_grav_strerror(sf_status s) {
+    switch (s) {
+        case SF_OK: return "ok";
+        case SF_E_INVALID: return "invalid argument";
+        case SF_E_NOMEM: return "out of memory";
+        case SF_E_DEVICE: return "device error";
+        case SF_E_STATE: return "handle does not match the call";
+        case SF_E_UNSUPPORTED: return "unsupported";
+        case SF_E_INTERNAL: return "internal capacity exceeded";
+    }
+    return "unknown status";
+}
+
+const char *sf_grav_last_error(void) { return g_msg; }
+
+// Build everything for the tree path into a fresh handle.
+static sf_status build_all(sf_grav_tree_s *t, const void *pos, const void *mass, const void *soft,
+                           const sf_grav_opts *o, DevArena &ar) {
+    sf_status st = sf::build_sorted(pos, mass, soft, t->n, t->n_gas, t->dt, false, o->validate != 0,
+                                    t, ar);
+    if (st != SF_OK) return st;
+    SF_HIP(hipMemcpyAsync(&t->hframe, t->frame, sizeof(sf::Frame), hipMemcpyDeviceToHost, t->stream));
+    st = sf::build_topology(t, ar);   // synchronises the stream once
+    if (st != SF_OK) return st;
+    if (o->validate && t->hframe.bad)
+        return sf_fail(SF_E_INVALID, "inputs contain non-finite values, h <= 0 or m < 0");
+    if (t->n_nodes >= (1ll << 27))
+        return sf_fail(SF_E_UNSUPPORTED, "tree has %lld nodes (limit 2^27)", (long long)t->n_nodes);
+    st = sf::build_moments(t, ar);
+    if (st != SF_OK) return st;
+    return sf::build_groups(t, ar);
+}
+
+sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft, int64_t n,
+                             sf_dtype dt, const sf_grav_opts *o, void *stream, sf_grav_tree *out) {
+    g_msg[0] = 0;
+    if (!out) return sf_fail(SF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    sf_status st = check_arrays(pos, mass, soft, n, dt);
+    if (st != SF_OK) return st;
+    st = check_opts(o, n, true);
+    if (st != SF_OK) return st;
+    sf_grav_tree_s *t = new (std::nothrow) sf_grav_tree_s();
+    if (!t) return sf_fail(SF_E_NOMEM, "host allocation failed");
+    t->stream = (hipStream_t)stream;
+    t->n = n;
+    t->n_gas = o->n_gas < 0 ? n : o->n_gas;
+    t->n_sink = n - t->n_gas;
+    t->dt = dt;
+    t->leaf_cap = o->leaf_cap;
+    t->group_cap = o->group_cap;
+    hipGetDevice(&t->device);
+    {
+        DevArena ar(t->stream);
+        st = build_all(t, pos, mass, soft, o, ar);
+        if (st != SF_OK) {
+            hipStreamSynchronize(t->stream);
+            ar.free_keep();
+            ar.free_tmp();
+            hipStreamSynchronize(t->stream);
+            delete t;
+            return st;
+        }
+        t->allocs.insert(t->allocs.end(), ar.keep.begin(), ar.keep.end());
+        ar.keep.clear();
+    }
+    *out = t;
+    return SF_OK;
+}
+
+static sf_status eval_opts(const sf_grav_opts *o, sf::EvalOpts &e) {
+    e.form = o->form;
+    e.order = o->order;
+    e.G = o->G;
+    e.theta = o->theta;
+    e.stats = o->collect_stats != 0;
+    return SF_OK;
+}
+
+sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, const void *soft,
+                        int64_t n, sf_dtype dt, const sf_grav_opts *o, void *acc, void *pot,
+                        void *stream) {
+    g_msg[0] = 0;
+    if (!acc) return sf_fail(SF_E_INVALID, "acc is NULL");
+    sf::EvalOpts e;
+    if (tree) {
+        sf_status st = check_opts(o, n, false);
+        if (st != SF_OK) return st;
+        if (tree->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+        if (n != tree->n || dt != tree->dt)
+            return sf_fail(SF_E_STATE, "n/dtype (%lld, %d) differ from the handle's (%lld, %d)",
+                           (long long)n, (int)dt, (long long)tree->n, (int)tree->dt);
+        eval_opts(o, e);
+        hipStream_t prev = tree->stream;
+        tree->stream = (hipStream_t)stream;
+        DevArena ar(tree->stream);
+        st = sf::tree_accel(tree, e, acc, pot, ar);
+        if (st != SF_OK) {
+            tree->stream = prev;
+            return st;
+        }
+        return SF_OK;
+    }
+    sf_status st = check_arrays(pos, mass, soft, n, dt);
+    if (st != SF_OK) return st;
+    st = check_opts(o, n, false);
+    if (st != SF_OK) return st;
+    eval_opts(o, e);
+    sf_grav_tree_s t;
+    t.stream = (hipStream_t)stream;
+    t.direct_only = true;
+    {
+        DevArena ar(t.stream);
+        const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
+        st = sf::build_sorted(pos, mass, soft, n, ng, dt, true, o->validate != 0, &t, ar);
+        if (st == SF_OK && o->validate) {
+            sf::Frame hf;
+            hipError_t he = hipMemcpyAsync(&hf, t.frame, sizeof(hf), hipMemcpyDeviceToHost, t.stream);
+            if (he == hipSuccess) he = hipStreamSynchronize(t.stream);
+            if (he != hipSuccess) st = sf_fail(SF_E_DEVICE, "%s", hipGetErrorString(he));
+            else if (hf.bad) st = sf_fail(SF_E_INVALID, "inputs contain non-finite values, h <= 0 or m < 0");
+        }
+        if (st == SF_OK) st = sf::direct_accel(&t, e, acc, pot, ar);
+        // the handle's own arrays are released once the stream reaches here
+        ar.free_keep();
+    }
+    return st;
+}
+
+sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void *mass,
+                                 const void *soft, int64_t n, sf_dtype dt, const sf_grav_opts *o,
+                                 const void *g_acc, const void *g_pot, void *g_pos, void *g_mass,
+                                 void *g_soft, void *stream) {
+    g_msg[0] = 0;
+    if (!g_acc) return sf_fail(SF_E_INVALID, "g_acc is NULL");
+    sf::EvalOpts e;
+    if (tree) {
+        sf_status st = check_opts(o, n, false);
+        if (st != SF_OK) return st;
+        if (tree->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+        if (n != tree->n || dt != tree->dt)
+            return sf_fail(SF_E_STATE, "n/dtype differ from the handle's");
+        eval_opts(o, e);
+        tree->stream = (hipStream_t)stream;
+        DevArena ar(tree->stream);
+        return sf::tree_backward(tree, e, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
+    }
+    sf_status st = check_arrays(pos, mass, soft, n, dt);
+    if (st != SF_OK) return st;
+    st = check_opts(o, n, false);
+    if (st != SF_OK) return st;
+    eval_opts(o, e);
+    sf_grav_tree_s t;
+    t.stream = (hipStream_t)stream;
+    t.direct_only = true;
+    {
+        DevArena ar(t.stream);
+        const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
+        st = sf::build_sorted(pos, mass, soft, n, ng, dt, true, false, &t, ar);
+        if (st == SF_OK) st = sf::direct_backward(&t, e, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
+        ar.free_keep();
+    }
+    return st;
+}
+
+sf_status sf_grav_tree_free(sf_grav_tree tree) {
+    if (!tree) return SF_OK;
+    free_handle_memory(tree);
+    delete tree;
+    return SF_OK;
+}
+
+sf_status sf_grav_get_tree_info(sf_grav_tree t, sf_grav_tree_info *info) {
+    g_msg[0] = 0;
+    if (!t || !info) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (info->struct_size != sizeof(sf_grav_tree_info))
+        return sf_fail(SF_E_INVALID, "info.struct_size mismatch");
+    if (t->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    uint32_t st[2] = {0, 0};
+    int32_t ng = 0;
+    SF_HIP(hipMemcpyAsync(st, t->info_dev, sizeof(st), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipMemcpyAsync(&ng, t->n_groups_dev, sizeof(ng), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipStreamSynchronize(t->stream));
+    t->n_groups = ng;
+    t->max_level = (int)st[0];
+    t->n_leaves = st[1];
+    info->max_level = t->max_level;
+    info->n = t->n;
+    info->n_gas = t->n_gas;
+    info->n_nodes = t->n_nodes;
+    info->n_groups = t->n_groups;
+    info->n_leaves = t->n_leaves;
+    return SF_OK;
+}
+
+sf_status sf_grav_tree_export(sf_grav_tree t, int32_t what, void *host_dst, size_t bytes) {
+    g_msg[0] = 0;
+    if (!t || !host_dst) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (t->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    int32_t ng = 0;
+    SF_HIP(hipMemcpyAsync(&ng, t->n_groups_dev, sizeof(ng), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipStreamSynchronize(t->stream));
+    t->n_groups = ng;
+    const void *src = nullptr;
+    size_t need = 0;
+    const size_t nn = (size_t)t->n_nodes, n = (size_t)t->n, g = (size_t)ng;
+    switch (what) {
+        case SF_EXPORT_KEYS: src = t->keys; need = n * 8; break;
+        case SF_EXPORT_ORDER: src = t->order; need = n * 4; break;
+        case SF_EXPORT_NODE_LEVEL: src = t->nlevel; need = nn * 4; break;
+        case SF_EXPORT_NODE_FIRST: src = t->nfirst; need = nn * 4; break;
+        case SF_EXPORT_NODE_COUNT: src = t->ncount; need = nn * 4; break;
+        case SF_EXPORT_NODE_PARENT: src = t->nparent; need = nn * 4; break;
+        case SF_EXPORT_NODE_CHILD: src = t->nchild; need = nn * 4; break;
+        case SF_EXPORT_NODE_NCHILD: src = t->nnchild; need = nn * 4; break;
+        case SF_EXPORT_GROUP_FIRST: src = t->gfirst; need = g * 4; break;
+        case SF_EXPORT_GROUP_COUNT: src = t->gcount; need = g * 4; break;
+        case SF_EXPORT_NODE_MASS: src = t->M[0]; need = nn * 8; break;
+        case SF_EXPORT_NODE_COM: src = t->com[0]; need = nn * 24; break;
+        case SF_EXPORT_NODE_QUAD: src = t->Q[0]; need = nn * 48; break;
+        case SF_EXPORT_GROUP_NPC:
+        case SF_EXPORT_GROUP_NPP:
+            if (!t->have_stats) return sf_fail(SF_E_STATE, "no statistics collected");
+            src = what == SF_EXPORT_GROUP_NPC ? (const void *)t->gnpc : (const void *)t->gnpp;
+            need = g * 4;
+            break;
+        default: return sf_fail(SF_E_INVALID, "unknown export id %d", what);
+    }
+    if (bytes != need)
+        return sf_fail(SF_E_INVALID, "export %d needs %zu bytes, got %zu", what, need, bytes);
+    if (need == 0) return SF_OK;
+    SF_HIP(hipMemcpyAsync(host_dst, src, need, hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipStreamSynchronize(t->stream));
+    return SF_OK;
+}
+
+}  // extern "C"

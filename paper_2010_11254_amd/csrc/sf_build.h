@@ -1,0 +1,80 @@
+// sf_build.h -- host-side pieces shared by the library's translation units:
+// error reporting, a device-allocation arena and the build/eval entry points.
+#pragma once
+#include <vector>
+
+#include "sf_internal.h"
+
+// Record a failure message for sf_grav_last_error() and return the status.
+sf_status sf_fail(sf_status st, const char *fmt, ...);
+
+namespace sf {
+
+// Stream-ordered device allocations.  `keep` allocations belong to a tree
+// handle; `tmp` ones are released when the arena is destroyed (at the end of
+// a call).  On failure every allocation made so far can be released.
+struct DevArena {
+    hipStream_t s = nullptr;
+    std::vector<void *> keep, tmp;
+    explicit DevArena(hipStream_t st) : s(st) {}
+    ~DevArena() { free_tmp(); }
+    sf_status alloc(void **p, size_t bytes, bool temp);
+    void free_tmp();
+    void free_keep();
+};
+
+}  // namespace sf
+
+#define SF_ALLOC(ar, p, count)                                                                  \
+    do {                                                                                        \
+        sf_status _st = (ar).alloc((void **)&(p), sizeof(*(p)) * (size_t)(count), false);     \
+        if (_st != SF_OK) return _st;                                                           \
+    } while (0)
+#define SF_ALLOC_TMP(ar, p, count)                                                              \
+    do {                                                                                        \
+        sf_status _st = (ar).alloc((void **)&(p), sizeof(*(p)) * (size_t)(count), true);      \
+        if (_st != SF_OK) return _st;                                                           \
+    } while (0)
+#define SF_HIP(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t _e = (expr);                                                                 \
+        if (_e != hipSuccess)                                                                   \
+            return sf_fail(SF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));         \
+    } while (0)
+
+namespace sf {
+
+// A1-A4: bounding box, keys, radix sort, sorted SoA, sink positions.
+sf_status build_sorted(const void *pos, const void *mass, const void *soft, int64_t n,
+                       int64_t n_gas, sf_dtype dt, bool type_major, bool validate,
+                       sf_grav_tree_s *t, DevArena &ar);
+sf_status build_topology(sf_grav_tree_s *t, DevArena &ar);   // A5 (one stream sync)
+sf_status build_moments(sf_grav_tree_s *t, DevArena &ar);    // A6
+sf_status build_groups(sf_grav_tree_s *t, DevArena &ar);     // A7
+
+struct EvalOpts {
+    int form;
+    int order;
+    double G;
+    double theta;
+    bool stats;
+};
+
+// A8-A10, A12: tree walk for gas targets, sink walk + FP64 sink-sink.
+sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
+// A11: direct path on a handle built with type-major keys (no topology).
+sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
+// A13: adjoints.
+sf_status tree_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
+                        const void *g_pot, void *g_pos, void *g_mass, void *g_soft,
+                        DevArena &ar);
+sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
+                          const void *g_pot, void *g_pos, void *g_mass, void *g_soft,
+                          DevArena &ar);
+
+// FP64 sink-sink direct sum into acc4 (4 doubles per sink: ax ay az phi).
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4);
+
+int device_cu_count();
+
+}  // namespace sf

@@ -1,0 +1,701 @@
+// sf_build.hip -- octree construction on gfx950 (paper Sec. 2.2: the domain is
+// subdivided recursively into octants).
+//
+//   bounding box -> 63-bit Morton keys -> stable radix sort -> sorted SoA
+//   -> topology (all levels at once from key prefixes) -> FP64 moments
+//   (bottom-up, last-arriving child combines) -> target groups.
+//
+// Topology without a level loop: for a sorted position s let c(s) be the
+// number of leading octal digits s shares with s-1.  Position s starts a cell
+// at every level l > c(s).  The cell of s at level l holds more than leaf_cap
+// particles iff some window of leaf_cap+1 consecutive positions around s
+// shares the level-l prefix, so the leaf level of s is
+//     lambda(s) = min(21, 1 + max_{t in [s-cap, s]} lcp(key[t], key[t+cap])),
+// and s starts one node at each level in (c(s), lambda(s)].  Nodes are
+// emitted in depth-first order (by first particle, then level), then a stable
+// counting pass by level yields the breadth-first array; per-node fields come
+// from binary searches.
+#include "sf_build.h"
+#include "sf_prims.h"
+
+namespace sf {
+
+// ---------------------------------------------------------------- A1 bbox
+
+constexpr int kBoxBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bbox_partial(const T *__restrict__ pos,
+                                                      const T *__restrict__ mass,
+                                                      const T *__restrict__ soft, int64_t n,
+                                                      int validate, double *__restrict__ part,
+                                                      Frame *frame) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = (double)pos[3 * i + d];
+            lo[d] = fmin(lo[d], v);
+            hi[d] = fmax(hi[d], v);
+            if (validate && !isfinite(v)) bad = 1;
+        }
+        if (validate) {
+            double m = (double)mass[i], h = (double)soft[i];
+            if (!(m >= 0.0) || !isfinite(m) || !(h > 0.0) || !isfinite(h)) bad = 1;
+        }
+    }
+    __shared__ double sh[6][256];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    if (validate && bad) atomicAdd(&frame->bad, 1);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + w]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Root cube: lo = per-axis minimum; side = largest extent (1 if zero);
+// scale = 2^21 / side (correctly rounded FP64 division).
+__global__ void k_bbox_final(const double *__restrict__ part, int nblocks, Frame *frame) {
+    if (threadIdx.x != 0) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nblocks; ++b)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], part[b * 6 + d]);
+            hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+        }
+    double side = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double e = dsub(hi[d], lo[d]);
+        side = e > side ? e : side;
+        frame->lo[d] = lo[d];
+        frame->hi[d] = hi[d];
+    }
+    if (side == 0.0) side = 1.0;
+    frame->side = side;
+    frame->scale = 2097152.0 / side;
+}
+
+// ---------------------------------------------------------------- A2 keys
+
+// q_d = floor((x_d - lo_d) * scale) in FP64 (separate subtract and multiply),
+// clamped to [0, 2^21 - 1]; x supplies the most significant bit of each
+// 3-bit digit.  type_major sets bit 63 for sinks (gas first, then sinks).
+template <typename T>
+__global__ void k_keys(const T *__restrict__ pos, int64_t n, int64_t n_gas,
+                       const Frame *__restrict__ frame, int type_major, uint64_t *__restrict__ keys,
+                       uint32_t *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t q[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double v = dmul(dsub((double)pos[3 * i + d], frame->lo[d]), frame->scale);
+        v = floor(v);
+        v = v < 0.0 ? 0.0 : (v > 2097151.0 ? 2097151.0 : v);
+        q[d] = (uint64_t)v;
+    }
+    uint64_t k = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    if (type_major && i >= n_gas) k |= 1ull << 63;
+    keys[i] = k;
+    vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------- A4 permute
+
+template <typename T>
+__global__ void k_permute(const T *__restrict__ pos, const T *__restrict__ mass,
+                          const T *__restrict__ soft, const uint32_t *__restrict__ order, int64_t n,
+                          T *__restrict__ xs, T *__restrict__ ys, T *__restrict__ zs,
+                          T *__restrict__ ms, T *__restrict__ hs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = order[s];
+    xs[s] = pos[3 * i];
+    ys[s] = pos[3 * i + 1];
+    zs[s] = pos[3 * i + 2];
+    ms[s] = mass[i];
+    hs[s] = soft[i];
+}
+
+__global__ void k_sink_flags(const int32_t *__restrict__ order, int64_t n, int64_t n_gas,
+                             uint32_t *__restrict__ flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) flag[s] = order[s] >= n_gas ? 1u : 0u;
+}
+
+__global__ void k_sink_write(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ idx,
+                             int64_t n, int32_t *__restrict__ sink_pos) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n && flag[s]) sink_pos[idx[s]] = (int32_t)s;
+}
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T>
+static sf_status sort_stage(const void *pos, const void *mass, const void *soft, int64_t n,
+                            int64_t n_gas, bool type_major, bool validate, sf_grav_tree_s *t,
+                            DevArena &ar) {
+    hipStream_t s = t->stream;
+    SF_ALLOC(ar, t->frame, 1);
+    SF_HIP(hipMemsetAsync(t->frame, 0, sizeof(Frame), s));
+    double *part = nullptr;
+    SF_ALLOC_TMP(ar, part, kBoxBlocks * 6);
+    int bb = (int)std::min<int64_t>(kBoxBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_bbox_partial<T>, dim3(bb), dim3(256), 0, s, (const T *)pos,
+                       (const T *)mass, (const T *)soft, n, validate ? 1 : 0, part, t->frame);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, bb, t->frame);
+
+    uint64_t *ktmp = nullptr;
+    uint32_t *vtmp = nullptr, *scr = nullptr;
+    SF_ALLOC(ar, t->keys, n);
+    SF_ALLOC(ar, t->order, n);
+    SF_ALLOC_TMP(ar, ktmp, n);
+    SF_ALLOC_TMP(ar, vtmp, n);
+    SF_ALLOC_TMP(ar, scr, radix_scratch_words(n, 8));
+    hipLaunchKernelGGL(k_keys<T>, dim3(nblk(n)), dim3(256), 0, s, (const T *)pos, n, n_gas,
+                       t->frame, type_major ? 1 : 0, t->keys, (uint32_t *)t->order);
+    radix_sort_u64(t->keys, (uint32_t *)t->order, ktmp, vtmp, n, 8, scr, s);
+
+    T *xs, *ys, *zs, *ms, *hs;
+    SF_ALLOC(ar, xs, n);
+    SF_ALLOC(ar, ys, n);
+    SF_ALLOC(ar, zs, n);
+    SF_ALLOC(ar, ms, n);
+    SF_ALLOC(ar, hs, n);
+    t->xs = xs; t->ys = ys; t->zs = zs; t->ms = ms; t->hs = hs;
+    hipLaunchKernelGGL(k_permute<T>, dim3(nblk(n)), dim3(256), 0, s, (const T *)pos,
+                       (const T *)mass, (const T *)soft, (const uint32_t *)t->order, n, xs, ys, zs,
+                       ms, hs);
+    // sinks in sorted order
+    const int64_t n_sink = n - n_gas;
+    if (n_sink > 0) {
+        SF_ALLOC(ar, t->sink_pos, n_sink);
+        uint32_t *flag = (uint32_t *)vtmp, *idx = nullptr, *sscr = nullptr;
+        SF_ALLOC_TMP(ar, idx, n);
+        SF_ALLOC_TMP(ar, sscr, scan_scratch_words(n));
+        hipLaunchKernelGGL(k_sink_flags, dim3(nblk(n)), dim3(256), 0, s, t->order, n, n_gas, flag);
+        scan_u32(flag, idx, n, sscr, nullptr, s);
+        hipLaunchKernelGGL(k_sink_write, dim3(nblk(n)), dim3(256), 0, s, flag, idx, n, t->sink_pos);
+    }
+    SF_HIP(hipGetLastError());
+    return SF_OK;
+}
+
+sf_status build_sorted(const void *pos, const void *mass, const void *soft, int64_t n,
+                       int64_t n_gas, sf_dtype dt, bool type_major, bool validate,
+                       sf_grav_tree_s *t, DevArena &ar) {
+    t->n = n;
+    t->n_gas = n_gas;
+    t->n_sink = n - n_gas;
+    t->dt = dt;
+    if (dt == SF_F32) return sort_stage<float>(pos, mass, soft, n, n_gas, type_major, validate, t, ar);
+    return sort_stage<double>(pos, mass, soft, n, n_gas, type_major, validate, t, ar);
+}
+
+// ---------------------------------------------------------------- A5 topology
+
+__global__ void k_topo_lcp(const uint64_t *__restrict__ keys, int64_t n, int cap,
+                           uint8_t *__restrict__ lcp, uint8_t *__restrict__ win) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint64_t k = keys[s];
+    lcp[s] = s > 0 ? (uint8_t)lcp_digits(keys[s - 1], k) : 0;
+    if (s + cap < n) win[s] = (uint8_t)lcp_digits(k, keys[s + cap]);
+}
+
+// Leaf level lambda(s), node count of s, level histogram.
+__global__ __launch_bounds__(256) void k_topo_count(const uint8_t *__restrict__ lcp,
+                                                    const uint8_t *__restrict__ win, int64_t n,
+                                                    int cap, uint8_t *__restrict__ lam,
+                                                    uint32_t *__restrict__ nn,
+                                                    uint32_t *__restrict__ levhist) {
+    __shared__ uint32_t sh[kLevels + 1];
+    if (threadIdx.x <= kLevels) sh[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        int64_t t0 = s - cap > 0 ? s - cap : 0;
+        int64_t t1 = s < n - 1 - cap ? s : n - 1 - cap;
+        int mx = -1;
+        for (int64_t t = t0; t <= t1; ++t) mx = max(mx, (int)win[t]);
+        int L = mx < 0 ? 0 : min(kLevels, mx + 1);
+        int lo = s == 0 ? 0 : (int)lcp[s] + 1;
+        lam[s] = (uint8_t)L;
+        int cnt = L >= lo ? L - lo + 1 : 0;
+        nn[s] = (uint32_t)cnt;
+        for (int l = lo; l <= L; ++l) atomicAdd(&sh[l], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x <= kLevels && sh[threadIdx.x]) atomicAdd(&levhist[threadIdx.x], sh[threadIdx.x]);
+}
+
+// level_off[0..22] (exclusive prefix of the level histogram) and the 256-entry
+// digit-offset table for the counting pass by level.
+__global__ void k_topo_levoff(const uint32_t *__restrict__ levhist, uint32_t *__restrict__ level_off,
+                              uint32_t *__restrict__ digit_off) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int l = 0; l <= kLevels; ++l) {
+        level_off[l] = run;
+        digit_off[l] = run;
+        run += levhist[l];
+    }
+    level_off[kLevels + 1] = run;
+    for (int d = kLevels + 1; d < 256; ++d) digit_off[d] = run;
+}
+
+// Depth-first emission: packed node = (first << 8) | level.
+__global__ void k_topo_emit(const uint8_t *__restrict__ lcp, const uint8_t *__restrict__ lam,
+                            const uint32_t *__restrict__ dfs_off, int64_t n,
+                            uint64_t *__restrict__ packed) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int lo = s == 0 ? 0 : (int)lcp[s] + 1;
+    int L = lam[s];
+    uint32_t o = dfs_off[s];
+    for (int l = lo; l <= L; ++l) packed[o + (l - lo)] = ((uint64_t)s << 8) | (uint64_t)l;
+}
+
+// first index in [a, b) of the packed array whose first particle is >= s
+__device__ __forceinline__ int64_t lower_first(const uint64_t *__restrict__ p, int64_t a, int64_t b,
+                                               uint64_t s) {
+    while (a < b) {
+        int64_t m = (a + b) >> 1;
+        if ((p[m] >> 8) < s) a = m + 1; else b = m;
+    }
+    return a;
+}
+
+__global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nodes,
+                              const uint64_t *__restrict__ keys, int64_t n, int cap,
+                              const uint32_t *__restrict__ level_off, const Frame *__restrict__ frame,
+                              int32_t *__restrict__ nlevel, int32_t *__restrict__ nfirst,
+                              int32_t *__restrict__ ncount, int32_t *__restrict__ nparent,
+                              int32_t *__restrict__ nchild, int32_t *__restrict__ nnchild,
+                              double *__restrict__ clo, double *__restrict__ chi,
+                              uint32_t *__restrict__ stats /* [0]=max level, [1]=leaves */) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    const uint64_t pk = packed[k];
+    const int l = (int)(pk & 255);
+    const int64_t s = (int64_t)(pk >> 8);
+    // end of the cell: first key beyond the largest key with this prefix
+    const uint64_t kmax = keys[s] | ((l == 0) ? ~0ull >> 1 : ((1ull << (3 * (kLevels - l))) - 1));
+    int64_t a = s + 1, b = n;
+    while (a < b) {
+        int64_t m = (a + b) >> 1;
+        if (keys[m] <= kmax) a = m + 1; else b = m;
+    }
+    const int64_t end = a;
+    const int64_t cnt = end - s;
+    nlevel[k] = l;
+    nfirst[k] = (int32_t)s;
+    ncount[k] = (int32_t)cnt;
+    // parent: last node of level l-1 whose first particle is <= s
+    if (l > 0) {
+        int64_t p = lower_first(packed, level_off[l - 1], level_off[l], (uint64_t)s + 1) - 1;
+        nparent[k] = (int32_t)p;
+    } else {
+        nparent[k] = -1;
+    }
+    const bool leaf = cnt <= cap || l == kLevels;
+    if (!leaf) {
+        int64_t c0 = lower_first(packed, level_off[l + 1], level_off[l + 2], (uint64_t)s);
+        int64_t c1 = lower_first(packed, c0, level_off[l + 2], (uint64_t)end);
+        nchild[k] = (int32_t)c0;
+        nnchild[k] = (int32_t)(c1 - c0);
+    } else {
+        nchild[k] = -1;
+        nnchild[k] = 0;
+        atomicAdd(&stats[1], 1u);
+    }
+    atomicMax(&stats[0], (uint32_t)l);
+    // cube: lo + ix * cell, lo + (ix + 1) * cell with cell = side * 2^-l
+    const uint64_t pre = l == 0 ? 0ull : (keys[s] >> (3 * (kLevels - l)));
+    const double cell = ldexp(frame->side, -l);
+    const uint32_t ij[3] = {compact3(pre >> 2), compact3(pre >> 1), compact3(pre)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        clo[3 * k + d] = dadd(frame->lo[d], dmul((double)ij[d], cell));
+        chi[3 * k + d] = dadd(frame->lo[d], dmul((double)(ij[d] + 1), cell));
+    }
+}
+
+sf_status build_topology(sf_grav_tree_s *t, DevArena &ar) {
+    hipStream_t s = t->stream;
+    const int64_t n = t->n;
+    const int cap = t->leaf_cap;
+    uint8_t *lcp, *win, *lam;
+    uint32_t *nn, *dfs, *levhist, *misc, *scr, *pscr;
+    SF_ALLOC_TMP(ar, lcp, n);
+    SF_ALLOC_TMP(ar, win, n);
+    SF_ALLOC_TMP(ar, lam, n);
+    SF_ALLOC_TMP(ar, nn, n);
+    SF_ALLOC_TMP(ar, dfs, n);
+    // misc: [0..22] levhist, [24..47] level_off, [48..303] digit_off,
+    //       [304] total nodes, [305] max level, [306] leaves
+    SF_ALLOC_TMP(ar, misc, 320);
+    levhist = misc;
+    SF_HIP(hipMemsetAsync(misc, 0, 320 * sizeof(uint32_t), s));
+    SF_ALLOC_TMP(ar, scr, scan_scratch_words(n));
+    hipLaunchKernelGGL(k_topo_lcp, dim3(nblk(n)), dim3(256), 0, s, t->keys, n, cap, lcp, win);
+    hipLaunchKernelGGL(k_topo_count, dim3(nblk(n)), dim3(256), 0, s, lcp, win, n, cap, lam, nn,
+                       levhist);
+    scan_u32(nn, dfs, n, scr, misc + 304, s);
+    hipLaunchKernelGGL(k_topo_levoff, dim3(1), dim3(64), 0, s, levhist, misc + 24, misc + 48);
+    uint32_t total = 0;
+    SF_HIP(hipMemcpyAsync(&total, misc + 304, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipStreamSynchronize(s));
+    const int64_t nn_total = total;
+    t->n_nodes = nn_total;
+    uint64_t *pdfs, *pbfs;
+    SF_ALLOC_TMP(ar, pdfs, nn_total);
+    SF_ALLOC_TMP(ar, pbfs, nn_total);
+    SF_ALLOC_TMP(ar, pscr, radix_pass_scratch_words(nn_total));
+    hipLaunchKernelGGL(k_topo_emit, dim3(nblk(n)), dim3(256), 0, s, lcp, lam, dfs, n, pdfs);
+    radix_pass_u64(pdfs, pbfs, nn_total, 0, misc + 48, pscr, s);
+    SF_ALLOC(ar, t->info_dev, 8);
+    SF_ALLOC(ar, t->nlevel, nn_total);
+    SF_ALLOC(ar, t->nfirst, nn_total);
+    SF_ALLOC(ar, t->ncount, nn_total);
+    SF_ALLOC(ar, t->nparent, nn_total);
+    SF_ALLOC(ar, t->nchild, nn_total);
+    SF_ALLOC(ar, t->nnchild, nn_total);
+    SF_ALLOC(ar, t->clo, 3 * nn_total);
+    SF_ALLOC(ar, t->chi, 3 * nn_total);
+    hipLaunchKernelGGL(k_topo_fields, dim3(nblk(nn_total)), dim3(256), 0, s, pbfs, nn_total,
+                       t->keys, n, cap, misc + 24, t->frame, t->nlevel, t->nfirst, t->ncount,
+                       t->nparent, t->nchild, t->nnchild, t->clo, t->chi, misc + 305);
+    SF_HIP(hipGetLastError());
+    SF_HIP(hipMemcpyAsync(t->info_dev, misc + 305, 2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    return SF_OK;
+}
+
+// ---------------------------------------------------------------- A6 moments
+
+// Raw moments of a node about its cube centre g, per set (0 all, 1 gas):
+//   M, D = sum m (x - g), S = sum m (x - g)(x - g)^T (xx yy zz xy xz yz), hmax.
+struct RawMom {
+    double M, D[3], S[6], h;
+};
+
+__device__ __forceinline__ void raw_zero(RawMom &r) {
+    r.M = 0.0;
+    r.h = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) r.D[d] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) r.S[d] = 0.0;
+}
+
+__device__ __forceinline__ void raw_add_point(RawMom &r, double m, double y0, double y1, double y2,
+                                              double h) {
+    r.M += m;
+    r.D[0] += m * y0;
+    r.D[1] += m * y1;
+    r.D[2] += m * y2;
+    r.S[0] += m * y0 * y0;
+    r.S[1] += m * y1 * y1;
+    r.S[2] += m * y2 * y2;
+    r.S[3] += m * y0 * y1;
+    r.S[4] += m * y0 * y2;
+    r.S[5] += m * y1 * y2;
+    r.h = fmax(r.h, h);
+}
+
+// raw layout per set: 11 doubles per node (M, D0..2, S0..5, h)
+__device__ __forceinline__ void raw_store(double *raw, int64_t k, const RawMom &r) {
+    double *p = raw + 11 * k;
+    p[0] = r.M;
+    for (int d = 0; d < 3; ++d) p[1 + d] = r.D[d];
+    for (int d = 0; d < 6; ++d) p[4 + d] = r.S[d];
+    p[10] = r.h;
+}
+
+__device__ __forceinline__ void raw_load_dev(const double *raw, int64_t k, RawMom &r) {
+    const double *p = raw + 11 * k;
+    r.M = ld_dev(p);
+    for (int d = 0; d < 3; ++d) r.D[d] = ld_dev(p + 1 + d);
+    for (int d = 0; d < 6; ++d) r.S[d] = ld_dev(p + 4 + d);
+    r.h = ld_dev(p + 10);
+}
+
+// Shift child moments from its centre gc to the parent centre g and add.
+__device__ __forceinline__ void raw_add_child(RawMom &p, const RawMom &c, const double dl[3]) {
+    p.M += c.M;
+    p.D[0] += c.D[0] + c.M * dl[0];
+    p.D[1] += c.D[1] + c.M * dl[1];
+    p.D[2] += c.D[2] + c.M * dl[2];
+    p.S[0] += c.S[0] + 2.0 * c.D[0] * dl[0] + c.M * dl[0] * dl[0];
+    p.S[1] += c.S[1] + 2.0 * c.D[1] * dl[1] + c.M * dl[1] * dl[1];
+    p.S[2] += c.S[2] + 2.0 * c.D[2] * dl[2] + c.M * dl[2] * dl[2];
+    p.S[3] += c.S[3] + c.D[0] * dl[1] + c.D[1] * dl[0] + c.M * dl[0] * dl[1];
+    p.S[4] += c.S[4] + c.D[0] * dl[2] + c.D[2] * dl[0] + c.M * dl[0] * dl[2];
+    p.S[5] += c.S[5] + c.D[1] * dl[2] + c.D[2] * dl[1] + c.M * dl[1] * dl[2];
+    p.h = fmax(p.h, c.h);
+}
+
+__device__ __forceinline__ void centre(const double *clo, const double *chi, int64_t k, double g[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[d] = 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
+}
+
+template <typename T>
+__global__ void k_moments(int64_t n_nodes, const int32_t *__restrict__ nfirst,
+                          const int32_t *__restrict__ ncount, const int32_t *__restrict__ nparent,
+                          const int32_t *__restrict__ nchild, const int32_t *__restrict__ nnchild,
+                          const double *__restrict__ clo, const double *__restrict__ chi,
+                          const T *__restrict__ xs, const T *__restrict__ ys,
+                          const T *__restrict__ zs, const T *__restrict__ ms,
+                          const T *__restrict__ hs, const int32_t *__restrict__ order,
+                          int64_t n_gas, double *raw0, double *raw1, uint32_t *arrive) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes || nnchild[k] != 0) return;
+    double g[3];
+    centre(clo, chi, k, g);
+    RawMom ra, rg;
+    raw_zero(ra);
+    raw_zero(rg);
+    const int64_t f = nfirst[k], c = ncount[k];
+    for (int64_t p = f; p < f + c; ++p) {
+        const double m = (double)ms[p], h = (double)hs[p];
+        const double y0 = (double)xs[p] - g[0], y1 = (double)ys[p] - g[1], y2 = (double)zs[p] - g[2];
+        raw_add_point(ra, m, y0, y1, y2, h);
+        if (order[p] < n_gas) raw_add_point(rg, m, y0, y1, y2, h);
+    }
+    raw_store(raw0, k, ra);
+    raw_store(raw1, k, rg);
+    // climb: the last child to arrive combines its parent from all children
+    int64_t cur = k;
+    while (true) {
+        const int64_t par = nparent[cur];
+        if (par < 0) break;
+        __threadfence();
+        const uint32_t old = atomicAdd(&arrive[par], 1u);
+        if ((int)old != nnchild[par] - 1) break;
+        __threadfence();
+        double gp[3];
+        centre(clo, chi, par, gp);
+        raw_zero(ra);
+        raw_zero(rg);
+        const int64_t c0 = nchild[par], c1 = c0 + nnchild[par];
+        for (int64_t ch = c0; ch < c1; ++ch) {
+            double gc[3], dl[3];
+            centre(clo, chi, ch, gc);
+            for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
+            RawMom cm;
+            raw_load_dev(raw0, ch, cm);
+            raw_add_child(ra, cm, dl);
+            raw_load_dev(raw1, ch, cm);
+            raw_add_child(rg, cm, dl);
+        }
+        raw_store(raw0, par, ra);
+        raw_store(raw1, par, rg);
+        cur = par;
+    }
+}
+
+// Final per-node moments: com = g + D/M, S_com = S - D D^T / M,
+// Q = 3 S_com - tr(S_com) I.  Nodes with M = 0 keep com = g, Q = 0.
+__global__ void k_moments_final(int64_t n_nodes, const double *__restrict__ clo,
+                                const double *__restrict__ chi, const double *__restrict__ raw,
+                                double *__restrict__ M, double *__restrict__ com,
+                                double *__restrict__ Q, double *__restrict__ hmax) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    double g[3];
+    centre(clo, chi, k, g);
+    const double *p = raw + 11 * k;
+    const double m = p[0];
+    M[k] = m;
+    hmax[k] = p[10];
+    if (m > 0.0) {
+        const double c0 = p[1] / m, c1 = p[2] / m, c2 = p[3] / m;
+        com[3 * k] = g[0] + c0;
+        com[3 * k + 1] = g[1] + c1;
+        com[3 * k + 2] = g[2] + c2;
+        const double sxx = p[4] - p[1] * c0, syy = p[5] - p[2] * c1, szz = p[6] - p[3] * c2;
+        const double sxy = p[7] - p[1] * c1, sxz = p[8] - p[1] * c2, syz = p[9] - p[2] * c2;
+        const double tr = sxx + syy + szz;
+        Q[6 * k] = 3.0 * sxx - tr;
+        Q[6 * k + 1] = 3.0 * syy - tr;
+        Q[6 * k + 2] = 3.0 * szz - tr;
+        Q[6 * k + 3] = 3.0 * sxy;
+        Q[6 * k + 4] = 3.0 * sxz;
+        Q[6 * k + 5] = 3.0 * syz;
+    } else {
+        for (int d = 0; d < 3; ++d) com[3 * k + d] = g[d];
+        for (int d = 0; d < 6; ++d) Q[6 * k + d] = 0.0;
+    }
+}
+
+sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
+    hipStream_t s = t->stream;
+    const int64_t nn = t->n_nodes;
+    double *raw0, *raw1;
+    uint32_t *arrive;
+    SF_ALLOC_TMP(ar, raw0, 11 * nn);
+    SF_ALLOC_TMP(ar, raw1, 11 * nn);
+    SF_ALLOC_TMP(ar, arrive, nn);
+    fill_u32(arrive, nn, 0u, s);
+    for (int set = 0; set < 2; ++set) {
+        SF_ALLOC(ar, t->M[set], nn);
+        SF_ALLOC(ar, t->com[set], 3 * nn);
+        SF_ALLOC(ar, t->Q[set], 6 * nn);
+        SF_ALLOC(ar, t->hmax[set], nn);
+    }
+    if (t->dt == SF_F32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, t->nfirst,
+                           t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
+                           (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
+                           (const float *)t->ms, (const float *)t->hs, t->order, t->n_gas, raw0,
+                           raw1, arrive);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, t->nfirst,
+                           t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
+                           (const double *)t->xs, (const double *)t->ys, (const double *)t->zs,
+                           (const double *)t->ms, (const double *)t->hs, t->order, t->n_gas, raw0,
+                           raw1, arrive);
+    double *raws[2] = {raw0, raw1};
+    for (int set = 0; set < 2; ++set)
+        hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,
+                           raws[set], t->M[set], t->com[set], t->Q[set], t->hmax[set]);
+    SF_HIP(hipGetLastError());
+    return SF_OK;
+}
+
+// ---------------------------------------------------------------- A7 groups
+
+// Group starts: a node holding at most group_cap particles is one group;
+// consecutive such children of a split node are packed greedily while the
+// run stays within group_cap; an over-full leaf is cut into slices.
+__global__ void k_grp_mark(int64_t n_nodes, const int32_t *__restrict__ nfirst,
+                           const int32_t *__restrict__ ncount, const int32_t *__restrict__ nchild,
+                           const int32_t *__restrict__ nnchild, int gcap,
+                           uint32_t *__restrict__ mark) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    const int64_t f = nfirst[k], c = ncount[k];
+    if (k == 0 && c <= gcap) mark[0] = 1u;
+    if (c <= gcap) return;
+    if (nnchild[k] == 0) {
+        for (int64_t s = f; s < f + c; s += gcap) mark[s] = 1u;
+        return;
+    }
+    int64_t run = 0;
+    const int64_t c0 = nchild[k], c1 = c0 + nnchild[k];
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const int64_t cc = ncount[ch];
+        if (cc > gcap) {
+            run = 0;
+            continue;
+        }
+        if (run + cc > gcap) run = 0;
+        if (run == 0) mark[nfirst[ch]] = 1u;
+        run += cc;
+    }
+}
+
+__global__ void k_grp_write(const uint32_t *__restrict__ mark, const uint32_t *__restrict__ idx,
+                            int64_t n, int32_t *__restrict__ gfirst) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n && mark[s]) gfirst[idx[s]] = (int32_t)s;
+}
+
+// One wave per group: count, bounding box, max softening and centre.  The
+// centre is the box midpoint, rounded to the input precision.
+template <typename T>
+__global__ __launch_bounds__(64) void k_grp_info(const int32_t *__restrict__ n_groups_dev, int64_t n,
+                                                 int32_t *__restrict__ gfirst,
+                                                 int32_t *__restrict__ gcount,
+                                                 const T *__restrict__ xs, const T *__restrict__ ys,
+                                                 const T *__restrict__ zs, const T *__restrict__ hs,
+                                                 double *__restrict__ gbox,
+                                                 double *__restrict__ ghmax,
+                                                 double *__restrict__ gcen) {
+    const int64_t ng = *n_groups_dev;
+    const int lane = threadIdx.x;
+    for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const int64_t f = gfirst[g];
+        const int64_t e = (g + 1 < ng) ? gfirst[g + 1] : n;
+        const int64_t c = e - f;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double hm = 0.0;
+        if (lane < c) {
+            const int64_t p = f + lane;
+            double v[3] = {(double)xs[p], (double)ys[p], (double)zs[p]};
+            for (int d = 0; d < 3; ++d) { lo[d] = v[d]; hi[d] = v[d]; }
+            hm = (double)hs[p];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
+                hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
+            }
+            hm = fmax(hm, __shfl_xor(hm, off, 64));
+        }
+        if (lane == 0) {
+            gcount[g] = (int32_t)c;
+            for (int d = 0; d < 3; ++d) {
+                gbox[6 * g + d] = lo[d];
+                gbox[6 * g + 3 + d] = hi[d];
+                gcen[3 * g + d] = (double)(T)(0.5 * (lo[d] + hi[d]));
+            }
+            ghmax[g] = hm;
+        }
+    }
+}
+
+sf_status build_groups(sf_grav_tree_s *t, DevArena &ar) {
+    hipStream_t s = t->stream;
+    const int64_t n = t->n, nn = t->n_nodes;
+    const int gcap = t->group_cap;
+    // every group is a node, a run starting at a distinct child node, or a
+    // slice of an over-full leaf
+    const int64_t cap_groups = 2 * nn + (n + gcap - 1) / gcap + 1;
+    t->groups_cap = cap_groups;
+    uint32_t *mark, *idx, *scr;
+    SF_ALLOC_TMP(ar, mark, n);
+    SF_ALLOC_TMP(ar, idx, n);
+    SF_ALLOC_TMP(ar, scr, scan_scratch_words(n));
+    SF_ALLOC(ar, t->n_groups_dev, 1);
+    SF_ALLOC(ar, t->gfirst, cap_groups);
+    SF_ALLOC(ar, t->gcount, cap_groups);
+    SF_ALLOC(ar, t->gbox, 6 * cap_groups);
+    SF_ALLOC(ar, t->ghmax, cap_groups);
+    SF_ALLOC(ar, t->gcen, 3 * cap_groups);
+    fill_u32(mark, n, 0u, s);
+    hipLaunchKernelGGL(k_grp_mark, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst, t->ncount,
+                       t->nchild, t->nnchild, gcap, mark);
+    scan_u32(mark, idx, n, scr, (uint32_t *)t->n_groups_dev, s);
+    hipLaunchKernelGGL(k_grp_write, dim3(nblk(n)), dim3(256), 0, s, mark, idx, n, t->gfirst);
+    const int blocks = 4096;
+    if (t->dt == SF_F32)
+        hipLaunchKernelGGL(k_grp_info<float>, dim3(blocks), dim3(64), 0, s, t->n_groups_dev, n,
+                           t->gfirst, t->gcount, (const float *)t->xs, (const float *)t->ys,
+                           (const float *)t->zs, (const float *)t->hs, t->gbox, t->ghmax, t->gcen);
+    else
+        hipLaunchKernelGGL(k_grp_info<double>, dim3(blocks), dim3(64), 0, s, t->n_groups_dev, n,
+                           t->gfirst, t->gcount, (const double *)t->xs, (const double *)t->ys,
+                           (const double *)t->zs, (const double *)t->hs, t->gbox, t->ghmax,
+                           t->gcen);
+    SF_HIP(hipGetLastError());
+    return SF_OK;
+}
+
+}  // namespace sf

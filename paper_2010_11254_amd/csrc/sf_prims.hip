@@ -1,0 +1,297 @@
+// sf_prims.hip -- device-wide primitives for the tree build on gfx950:
+// fill, exclusive scan (single pass, decoupled look-back) and a stable LSD
+// radix sort of 64-bit keys with 32-bit values (onesweep-style: one
+// histogram pass for all digits, then one chained-scan scatter per digit).
+#include "sf_prims.h"
+
+namespace sf {
+
+// ---------------------------------------------------------------- fill
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------- scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Wave-level inclusive scan of 32-bit values (64 lanes).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Look back over earlier tiles' status words until an inclusive prefix is
+// found.  Tiles are taken from an atomic counter in start order, so every
+// earlier tile belongs to a workgroup that has already started and will
+// publish; the wait ends.
+__device__ __forceinline__ uint32_t look_back(uint32_t *status, int64_t tile, int stride, int slot) {
+    uint32_t prefix = 0;
+    int64_t t = tile - 1;
+    while (t >= 0) {
+        uint32_t v;
+        do {
+            v = ld_dev_u32(&status[t * stride + slot]);
+        } while ((v & ~kValMask) == 0);
+        prefix += v & kValMask;
+        if (v & kFlagPre) break;
+        --t;
+    }
+    return prefix;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_u32(const uint32_t *__restrict__ in,
+                                                           uint32_t *__restrict__ out, int64_t n,
+                                                           uint32_t *status, uint32_t *tile_ctr,
+                                                           uint32_t *total) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    __shared__ uint32_t s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n) ? in[i] : 0u;
+        sum += v[k];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) s_wave[wid] = incl;
+    __syncthreads();
+    uint32_t wave_off = 0, tile_sum = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wid) wave_off += s_wave[w];
+        tile_sum += s_wave[w];
+    }
+    if (threadIdx.x == 0) {
+        if (tile == 0) {
+            st_dev_u32(&status[0], kFlagPre | tile_sum);
+            s_prefix = 0;
+        } else {
+            st_dev_u32(&status[tile], kFlagAgg | tile_sum);
+            uint32_t p = look_back(status, tile, 1, 0);
+            st_dev_u32(&status[tile], kFlagPre | ((p + tile_sum) & kValMask));
+            s_prefix = p;
+        }
+        int64_t tiles = (n + kScanTile - 1) / kScanTile;
+        if (tile == tiles - 1 && total) *total = s_prefix + tile_sum;
+    }
+    __syncthreads();
+    uint32_t run = s_prefix + wave_off + incl - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}
+
+int64_t scan_scratch_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+void scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *scratch, uint32_t *total,
+              hipStream_t s) {
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 0) {
+        if (total) hipMemsetAsync(total, 0, sizeof(uint32_t), s);
+        return;
+    }
+    fill_u32(scratch, tiles + 1, 0u, s);
+    hipLaunchKernelGGL(k_scan_u32, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n,
+                       scratch + 1, scratch, total);
+}
+
+// ---------------------------------------------------------------- radix sort
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsWaves = kRsThreads / 64;
+constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 keys per tile
+
+// Histograms of all eight 8-bit digits in one read of the keys.
+__global__ __launch_bounds__(256) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                 uint32_t *__restrict__ hist, int passes) {
+    __shared__ uint32_t sh[8][256];
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&sh[0][0])[i] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (8 * p)) & 255], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) {
+        uint32_t c = (&sh[0][0])[i];
+        if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+// Exclusive scan of each pass's 256 digit counts (one block, one wave per pass).
+__global__ void k_rs_offsets(uint32_t *hist, int passes) {
+    const int p = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (p >= passes) return;
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = hist[p * 256 + lane * 4 + k];
+        s += c[k];
+    }
+    uint32_t incl = wave_incl_scan(s);
+    uint32_t run = incl - s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        hist[p * 256 + lane * 4 + k] = run;
+        run += c[k];
+    }
+}
+
+// One stable scatter pass by the digit (key >> shift) & 255.  Within a tile,
+// wave w owns the contiguous segment [w*1024, (w+1)*1024) read in rounds of
+// 64 consecutive keys, so (round, lane) order is input order; ranks among
+// equal digits come from ballots, per-wave running counts live in LDS.
+template <bool kHasVal>
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ digit_off,
+    uint32_t *status, uint32_t *tile_ctr) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_cnt[kRsWaves][256];
+    __shared__ uint32_t s_base[256];
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t seg = tile * kRsTile + (int64_t)wid * (64 * kRsItems);
+    const uint64_t lt = lane_mask_lt();
+
+    uint64_t key[kRsItems];
+    uint32_t val[kRsItems];
+    uint32_t rank[kRsItems];
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t i = seg + r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? kin[i] : 0ull;
+        if (kHasVal) val[r] = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t before = s_cnt[wid][d];
+        rank[r] = before + popc64(m & lt);
+        // the lowest lane of each digit class bumps the running count; the
+        // reads above were issued by the same wave first, so they see the
+        // value from before this round.
+        if (valid && (m & lt) == 0) s_cnt[wid][d] = before + popc64(m);
+        if (!valid) rank[r] = 0xffffffffu;
+    }
+    __syncthreads();
+    // one thread per digit: per-wave exclusive offsets, tile total, look-back
+    {
+        const int d = threadIdx.x;
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w) {
+            uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = tot;
+            tot += c;
+        }
+        uint32_t prefix = 0;
+        if (tile == 0) {
+            st_dev_u32(&status[d], kFlagPre | tot);
+        } else {
+            st_dev_u32(&status[tile * 256 + d], kFlagAgg | tot);
+            prefix = look_back(status, tile, 256, d);
+            st_dev_u32(&status[tile * 256 + d], kFlagPre | ((prefix + tot) & kValMask));
+        }
+        s_base[d] = digit_off[d] + prefix;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsItems; ++r) {
+        if (rank[r] == 0xffffffffu) continue;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        const uint32_t pos = s_base[d] + s_cnt[wid][d] + rank[r];
+        kout[pos] = key[r];
+        if (kHasVal) vout[pos] = val[r];
+    }
+}
+
+int64_t radix_scratch_words(int64_t n, int passes) {
+    int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    return (int64_t)passes * 256 + (int64_t)passes * (tiles * 256 + 1);
+}
+
+// Sort (keys, vals) by the low `passes` bytes of the key; the result ends in
+// (keys, vals) -- an even pass count ping-pongs back, an odd count copies.
+int radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_tmp, uint32_t *vals_tmp,
+                   int64_t n, int passes, uint32_t *scratch, hipStream_t s) {
+    if (n <= 1) return 0;
+    const int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    uint32_t *hist = scratch;
+    uint32_t *status = scratch + passes * 256;
+    fill_u32(scratch, radix_scratch_words(n, passes), 0u, s);
+    int64_t hb = (n + 255) / 256;
+    if (hb > 2048) hb = 2048;
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)hb), dim3(256), 0, s, keys, n, hist, passes);
+    hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(64 * 8), 0, s, hist, passes);
+    uint64_t *ka = keys, *kb = keys_tmp;
+    uint32_t *va = vals, *vb = vals_tmp;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t *st = status + (int64_t)p * (tiles * 256 + 1);
+        if (vals)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)tiles), dim3(kRsThreads), 0, s, ka,
+                               va, kb, vb, n, 8 * p, hist + p * 256, st + 1, st);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)tiles), dim3(kRsThreads), 0, s,
+                               ka, nullptr, kb, nullptr, n, 8 * p, hist + p * 256, st + 1, st);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        if (vals) hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    }
+    return 0;
+}
+
+// Single stable pass by an 8-bit field at `shift`, with precomputed digit
+// offsets (exclusive prefix of the digit counts); keys only.
+void radix_pass_u64(const uint64_t *kin, uint64_t *kout, int64_t n, int shift,
+                    const uint32_t *digit_off, uint32_t *scratch, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t tiles = (n + kRsTile - 1) / kRsTile;
+    fill_u32(scratch, tiles * 256 + 1, 0u, s);
+    hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)tiles), dim3(kRsThreads), 0, s, kin,
+                       nullptr, kout, nullptr, n, shift, digit_off, scratch + 1, scratch);
+}
+
+int64_t radix_pass_scratch_words(int64_t n) { return (n + kRsTile - 1) / kRsTile * 256 + 1; }
+
+}  // namespace sf

@@ -1,0 +1,717 @@
+// sf_walk.hip -- Barnes-Hut group walk and interaction evaluation on gfx950
+// (paper Sec. 2.2: node multipoles unless the opening criterion opens the
+// node; Sec. 2.2.1: softened pairs r < max(h_i, h_j), Newtonian beyond).
+//
+// One wavefront per walk task.  A task is either a target group (up to 64
+// Morton-consecutive particles, one target per lane, node moments over all
+// particles) or one sink target (node moments over gas only, lanes spread
+// over the sources, sink sources skipped -- sinks see other sinks through the
+// FP64 sink-sink sum).
+//
+// Walk: an LDS stack of child ranges (<= 8 nodes each).  Each step pops whole
+// entries from the top, up to 64 nodes, one node per lane, and tests each
+// against the task's bounding box in FP64 with separately rounded operations.
+// A node is opened when (a) L^2 > theta^2 r^2 with r the distance from its
+// centre of mass to the box, (b) its cube meets the box or it holds one of
+// the task's particles, or (c) the cube-box gap is below the larger maximum
+// softening.  Accepted nodes go to a ring of multipole interactions, opened
+// leaves to a ring of particle ranges, opened inner nodes push their child
+// range.  Children are pushed in reverse lane order, so levels never decrease
+// from bottom to top of the stack; a new level-L entry is only pushed when a
+// level L-1 node is popped, which pops every level-L entry above it first,
+// so at most 64 entries per level are ever stored: 22 * 64 bounds the stack.
+// Interactions are evaluated in batches of 64 as the rings fill.
+#include "sf_build.h"
+#include "sf_math.h"
+#include "sf_prims.h"
+
+namespace sf {
+
+constexpr int kStack = 22 * 64 + 64;
+
+struct WalkNodes {
+    int64_t n_nodes;
+    const int32_t *nlevel, *nfirst, *ncount, *nchild, *nnchild;
+    const double *clo, *chi;
+    const double *M, *com, *Q, *hmax;   // the moment set used by this walk
+    double side;                         // root cube side (cell = side 2^-level)
+    double th2;                          // theta^2
+};
+
+struct WalkLds {
+    uint32_t stack[kStack];
+    int32_t pc[128];
+    int32_t ppf[128];
+    int32_t ppc[128];
+    int32_t slot[64];
+};
+
+template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h; int32_t idx, pad0, pad1, pad2; };
+template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz, pad0, pad1, pad2; };
+
+// Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
+template <typename R>
+__device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R ti2, R ti, bool self,
+                                     R &bx, R &by, R &bz, R &bp) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ri = rsq(r2);
+    R P = ri;
+    R F = ri * ri * ri;
+    const R hh2 = hj2 > ti2 ? hj2 : ti2;
+    if (r2 < hh2) {
+        soft_FP<R>(r2, hj > ti ? hj : ti, F, P);
+        if (self) { F = R(0); P = R(0); }
+    }
+    const R mF = m * F;
+    bx += mF * dx;
+    by += mF * dy;
+    bz += mF * dz;
+    bp -= m * P;
+}
+
+// Multipole term: r = target - centre of mass.
+template <typename R, int ORDER>
+__device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz, R qyz,
+                                          R &bx, R &by, R &bz, R &bp) {
+    const R r2 = rx * rx + ry * ry + rz * rz;
+    const R ri = rsq(r2);
+    const R ri2 = ri * ri;
+    const R Mri = M * ri;
+    if (ORDER == 0) {
+        const R c = -Mri * ri2;
+        bx += c * rx;
+        by += c * ry;
+        bz += c * rz;
+        bp -= Mri;
+    } else {
+        const R qzz = -(qxx + qyy);
+        const R qx = qxx * rx + qxy * ry + qxz * rz;
+        const R qy = qxy * rx + qyy * ry + qyz * rz;
+        const R qz = qxz * rx + qyz * ry + qzz * rz;
+        const R rqr = qx * rx + qy * ry + qz * rz;
+        const R ri5 = ri2 * ri2 * ri;
+        const R t = R(0.5) * rqr * ri5;
+        bp -= Mri + t;
+        const R c = -(Mri + R(5) * t) * ri2;
+        bx += c * rx + ri5 * qx;
+        by += c * ry + ri5 * qy;
+        bz += c * rz + ri5 * qz;
+    }
+}
+
+// ---------------------------------------------------------------- common args
+
+template <typename T>
+struct WalkArgs {
+    WalkNodes nd;
+    const T *xs, *ys, *zs, *ms, *hs;
+    const int32_t *order;
+    int64_t n, n_gas;
+    // tasks
+    const int32_t *n_groups_dev;
+    const int32_t *gfirst, *gcount;
+    const double *gbox, *ghmax, *gcen;
+    const int32_t *sink_pos;
+    int64_t n_sink;
+    const double *ss;          // sink-sink sums (4 per sink), may be null
+    int32_t *task_ctr;
+    int32_t *err;
+    int32_t *gnpc, *gnpp;      // stats (group mode), may be null
+    T *acc, *pot;
+    double G;
+};
+
+// ---------------------------------------------------------------- walk core
+
+// Test one node against the task box; returns 0 skip, 1 accept, 2 open leaf,
+// 3 open inner.  All FP64 steps are separately rounded (no contraction).
+__device__ __forceinline__ int classify(const WalkNodes &nd, int node, const double blo[3],
+                                        const double bhi[3], double hg, int64_t gf, int64_t gl) {
+    const double M = nd.M[node];
+    if (!(M > 0.0)) return 0;
+    const int64_t f = nd.nfirst[node], c = nd.ncount[node];
+    bool open = (f < gl) && (gf < f + c);
+    double lo[3], hi[3], cm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = nd.clo[3 * node + d];
+        hi[d] = nd.chi[3 * node + d];
+        cm[d] = nd.com[3 * node + d];
+    }
+    const bool meets = lo[0] <= bhi[0] && blo[0] <= hi[0] && lo[1] <= bhi[1] && blo[1] <= hi[1] &&
+                       lo[2] <= bhi[2] && blo[2] <= hi[2];
+    double g[3], e[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        g[d] = fmax(fmax(dsub(lo[d], bhi[d]), dsub(blo[d], hi[d])), 0.0);
+        e[d] = fmax(fmax(dsub(blo[d], cm[d]), dsub(cm[d], bhi[d])), 0.0);
+    }
+    const double dbb2 = dadd(dadd(dmul(g[0], g[0]), dmul(g[1], g[1])), dmul(g[2], g[2]));
+    const double hm = fmax(nd.hmax[node], hg);
+    const bool soft = dbb2 < dmul(hm, hm);
+    const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
+    const double L = ldexp(nd.side, -nd.nlevel[node]);
+    const bool angle = dmul(L, L) > dmul(nd.th2, r2);
+    open = open || meets || soft || angle;
+    if (!open) return 1;
+    return nd.nnchild[node] == 0 ? 2 : 3;
+}
+
+// Next task index for the whole wave, as a scalar (SGPR) value: lane 0 takes
+// it from the counter and readfirstlane broadcasts it.  Keeping every loop
+// bound of the walk in scalar registers makes all loop exits scalar
+// branches; a task index broadcast through a vector register let the
+// compiler structure the task loop as a divergent loop.
+__device__ __forceinline__ int next_task(int32_t *ctr) {
+    int g = 0;
+    if ((threadIdx.x & 63) == 0) g = atomicAdd(ctr, 1);
+    return __builtin_amdgcn_readfirstlane(g);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Walk one task.  Ev supplies pc_batch(L, head, nb) and pp_batch(L, nb).
+template <class Ev>
+__device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double blo[3],
+                          const double bhi[3], double hg, int64_t gf, int64_t gl, int32_t *err,
+                          uint32_t &n_pc, uint32_t &n_pp) {
+    const int lane = threadIdx.x;
+    const uint64_t lt = lane_mask_lt();
+    uint32_t sp = 1;
+    if (lane == 0) L.stack[0] = 1u;   // root (node 0), one node
+    uint32_t pc_h = 0, pc_t = 0, pp_h = 0, pp_t = 0, pp_pend = 0;
+    n_pc = 0;
+    n_pp = 0;
+    __syncthreads();
+    // Every node is popped at most once per task, so a task takes at most
+    // n_nodes steps; the bound makes termination unconditional.
+    int64_t steps = 0;
+    while (sp > 0) {
+        if (++steps > nd.n_nodes + 1) {
+            if (lane == 0) atomicOr(err, 2);
+            break;
+        }
+        // pop whole entries from the top, at most 64 nodes
+        const int ei = (int)sp - 1 - lane;
+        const uint32_t ent = ei >= 0 ? L.stack[ei] : 0u;
+        const uint32_t cnt = ent & 15u;
+        const uint32_t incl = wave_scan_incl(cnt);
+        const bool take = ei >= 0 && incl <= 64u;
+        const uint32_t ntake = (uint32_t)popc64(__ballot(take));
+        const uint32_t nnodes = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ntake - 1);
+        if (take)
+            for (uint32_t o = 0; o < cnt; ++o) L.slot[incl - cnt + o] = (int32_t)((ent >> 4) + o);
+        sp -= ntake;
+        __syncthreads();
+        const int node = lane < (int)nnodes ? L.slot[lane] : -1;
+        int cls = 0;
+        if (node >= 0) cls = classify(nd, node, blo, bhi, hg, gf, gl);
+        const uint64_t macc = __ballot(cls == 1), mleaf = __ballot(cls == 2), mint = __ballot(cls == 3);
+        if (cls == 1) L.pc[(pc_t + popc64(macc & lt)) & 127] = node;
+        pc_t += (uint32_t)popc64(macc);
+        uint32_t lc = 0;
+        if (cls == 2) {
+            const uint32_t q = (pp_t + popc64(mleaf & lt)) & 127;
+            lc = (uint32_t)nd.ncount[node];
+            L.ppf[q] = nd.nfirst[node];
+            L.ppc[q] = (int32_t)lc;
+        }
+        pp_t += (uint32_t)popc64(mleaf);
+        pp_pend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lc));
+        const uint32_t npush = (uint32_t)popc64(mint);
+        if (sp + npush > (uint32_t)kStack) {   // cannot happen (see header); stop safely
+            if (lane == 0) atomicOr(err, 1);
+            break;
+        }
+        if (cls == 3) {
+            const uint32_t r = (uint32_t)popc64(mint & lt);
+            L.stack[sp + npush - 1 - r] =
+                ((uint32_t)nd.nchild[node] << 4) | (uint32_t)nd.nnchild[node];
+        }
+        sp += npush;
+        __syncthreads();
+        while (pc_t - pc_h >= 64u) {
+            ev.pc_batch(L, pc_h, 64);
+            pc_h += 64;
+            n_pc += 64;
+        }
+        while (pp_pend >= 64u) {
+            // gather 64 particle indices from the front ranges
+            uint32_t k = 0;
+            int guard = 0;
+            while (k < 64u) {
+                if (++guard > 130 || pp_h == pp_t) {   // ring holds <= 128 ranges
+                    if (lane == 0) atomicOr(err, 4);
+                    break;
+                }
+                const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
+                const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
+                const uint32_t tk = (uint32_t)c < 64u - k ? (uint32_t)c : 64u - k;
+                if ((uint32_t)lane < tk) L.slot[k + lane] = f + lane;
+                k += tk;
+                __syncthreads();
+                if (tk < (uint32_t)c) {
+                    if (lane == 0) {
+                        L.ppf[pp_h & 127] = f + (int32_t)tk;
+                        L.ppc[pp_h & 127] = c - (int32_t)tk;
+                    }
+                } else {
+                    ++pp_h;
+                }
+                __syncthreads();
+            }
+            if (k < 64u) {
+                pp_pend = 0;
+                break;
+            }
+            ev.pp_batch(L, 64);
+            pp_pend -= 64;
+            n_pp += 64;
+        }
+    }
+    if (pc_t > pc_h) {
+        ev.pc_batch(L, pc_h, pc_t - pc_h);
+        n_pc += pc_t - pc_h;
+    }
+    if (pp_pend > 0) {
+        uint32_t k = 0;
+        while (pp_h != pp_t) {
+            const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
+            const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
+            if (c < 1 || k + (uint32_t)c > 64u) {   // fewer than 64 particles remain
+                if (lane == 0) atomicOr(err, 8);
+                break;
+            }
+            if ((int32_t)lane < c) L.slot[k + lane] = f + lane;
+            k += (uint32_t)c;
+            ++pp_h;
+        }
+        __syncthreads();
+        ev.pp_batch(L, k);
+        n_pp += k;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- group mode
+
+template <typename T, int FORM, int ORDER>
+struct GroupEval {
+    using R = typename FormT<FORM>::R;
+    const WalkArgs<T> *a;
+    PPStage<R> *spp;
+    PCStage<R> *spc;
+    double cen[3];
+    R tx, ty, tz, th, th2;
+    int32_t tidx;
+    Acc<FORM> ax, ay, az, ap;
+
+    __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        const int lane = threadIdx.x;
+        if ((uint32_t)lane < nb) {
+            const int node = L.pc[(head + lane) & 127];
+            const WalkNodes &nd = a->nd;
+            PCStage<R> s;
+            s.x = dto_frame<FORM>(nd.com[3 * node], cen[0]);
+            s.y = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
+            s.z = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            s.M = (R)nd.M[node];
+            if (ORDER == 2) {
+                s.qxx = (R)nd.Q[6 * node];
+                s.qyy = (R)nd.Q[6 * node + 1];
+                s.qxy = (R)nd.Q[6 * node + 3];
+                s.qxz = (R)nd.Q[6 * node + 4];
+                s.qyz = (R)nd.Q[6 * node + 5];
+            }
+            spc[lane] = s;
+        }
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        for (uint32_t j = 0; j < nb; ++j) {
+            const PCStage<R> s = spc[j];
+            multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
+                                s.qyz, bx, by, bz, bp);
+        }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        const int lane = threadIdx.x;
+        if ((uint32_t)lane < nb) {
+            const int p = L.slot[lane];
+            PPStage<R> s;
+            s.x = to_frame<FORM>(a->xs[p], cen[0]);
+            s.y = to_frame<FORM>(a->ys[p], cen[1]);
+            s.z = to_frame<FORM>(a->zs[p], cen[2]);
+            s.m = (R)a->ms[p];
+            s.h = (R)a->hs[p];
+            s.h2 = s.h * s.h;
+            s.idx = p;
+            spp[lane] = s;
+        }
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        for (uint32_t j = 0; j < nb; ++j) {
+            const PPStage<R> s = spp[j];
+            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx, by,
+                    bz, bp);
+        }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+};
+
+template <typename T, int FORM, int ORDER, bool STATS>
+__global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
+    using R = typename FormT<FORM>::R;
+    __shared__ WalkLds L;
+    __shared__ PPStage<R> spp[64];
+    __shared__ PCStage<R> spc[64];
+    const int lane = threadIdx.x;
+    const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
+    GroupEval<T, FORM, ORDER> ev;
+    ev.a = &a;
+    ev.spp = spp;
+    ev.spc = spc;
+    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+        const int64_t gf = a.gfirst[g], gc = a.gcount[g];
+        double blo[3], bhi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = a.gbox[6 * g + d];
+            bhi[d] = a.gbox[6 * g + 3 + d];
+            ev.cen[d] = a.gcen[3 * g + d];
+        }
+        const double hg = a.ghmax[g];
+        const bool has = lane < gc;
+        const int64_t i = gf + (has ? lane : 0);
+        const bool active = has && a.order[i] < a.n_gas;
+        uint32_t npc = 0, npp = 0;
+        if (__ballot(active) != 0ull) {   // groups of sinks only are left to the sink walk
+            ev.tx = to_frame<FORM>(a.xs[i], ev.cen[0]);
+            ev.ty = to_frame<FORM>(a.ys[i], ev.cen[1]);
+            ev.tz = to_frame<FORM>(a.zs[i], ev.cen[2]);
+            ev.th = (R)a.hs[i];
+            ev.th2 = ev.th * ev.th;
+            ev.tidx = has ? (int32_t)i : -1;
+            ev.ax.zero();
+            ev.ay.zero();
+            ev.az.zero();
+            ev.ap.zero();
+            walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
+            if (active) {
+                const int64_t o = a.order[i];
+                a.acc[3 * o] = (T)(a.G * ev.ax.value());
+                a.acc[3 * o + 1] = (T)(a.G * ev.ay.value());
+                a.acc[3 * o + 2] = (T)(a.G * ev.az.value());
+                if (a.pot) a.pot[o] = (T)(a.G * ev.ap.value());
+            }
+        }
+        if (STATS && lane == 0) {
+            a.gnpc[g] = (int32_t)npc;
+            a.gnpp[g] = (int32_t)npp;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- sink mode
+
+template <typename T, int FORM, int ORDER>
+struct SinkEval {
+    using R = typename FormT<FORM>::R;
+    const WalkArgs<T> *a;
+    double cen[3];
+    R th, th2;
+    int32_t tidx;
+    Acc<FORM> ax, ay, az, ap;   // per lane partial sums
+
+    __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        const int lane = threadIdx.x;
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        if ((uint32_t)lane < nb) {
+            const int node = L.pc[(head + lane) & 127];
+            const WalkNodes &nd = a->nd;
+            // target at the frame origin (FP32C) or at its own coordinates
+            const R cx = dto_frame<FORM>(nd.com[3 * node], cen[0]);
+            const R cy = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
+            const R cz = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
+            const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
+            const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
+            R qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
+            if (ORDER == 2) {
+                qxx = (R)nd.Q[6 * node];
+                qyy = (R)nd.Q[6 * node + 1];
+                qxy = (R)nd.Q[6 * node + 3];
+                qxz = (R)nd.Q[6 * node + 4];
+                qyz = (R)nd.Q[6 * node + 5];
+            }
+            multipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.M[node], qxx, qyy, qxy, qxz, qyz,
+                                bx, by, bz, bp);
+        }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+    }
+
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        const int lane = threadIdx.x;
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        if ((uint32_t)lane < nb) {
+            const int p = L.slot[lane];
+            if (a->order[p] < a->n_gas) {
+                const R sx = to_frame<FORM>(a->xs[p], cen[0]);
+                const R sy = to_frame<FORM>(a->ys[p], cen[1]);
+                const R sz = to_frame<FORM>(a->zs[p], cen[2]);
+                const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
+                const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
+                const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
+                const R h = (R)a->hs[p];
+                pair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, p == tidx, bx,
+                        by, bz, bp);
+            }
+        }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+};
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int FORM, int ORDER>
+__global__ __launch_bounds__(64) void k_walk_sinks(WalkArgs<T> a) {
+    __shared__ WalkLds L;
+    const int lane = threadIdx.x;
+    SinkEval<T, FORM, ORDER> ev;
+    ev.a = &a;
+    for (int k = next_task(a.task_ctr); k < a.n_sink; k = next_task(a.task_ctr)) {
+        const int64_t p = a.sink_pos[k];
+        double b[3];
+        b[0] = (double)a.xs[p];
+        b[1] = (double)a.ys[p];
+        b[2] = (double)a.zs[p];
+        for (int d = 0; d < 3; ++d) ev.cen[d] = b[d];
+        ev.th = (typename FormT<FORM>::R)a.hs[p];
+        ev.th2 = ev.th * ev.th;
+        ev.tidx = (int32_t)p;
+        ev.ax.zero();
+        ev.ay.zero();
+        ev.az.zero();
+        ev.ap.zero();
+        uint32_t npc, npp;
+        walk_task(a.nd, L, ev, b, b, (double)a.hs[p], p, p + 1, a.err, npc, npp);
+        double s[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
+        for (int d = 0; d < 4; ++d) s[d] = wave_sum_f64(s[d]);
+        if (lane == 0) {
+            if (a.ss)
+                for (int d = 0; d < 4; ++d) s[d] += a.ss[4 * k + d];
+            const int64_t o = a.order[p];
+            a.acc[3 * o] = (T)(a.G * s[0]);
+            a.acc[3 * o + 1] = (T)(a.G * s[1]);
+            a.acc[3 * o + 2] = (T)(a.G * s[2]);
+            if (a.pot) a.pot[o] = (T)(a.G * s[3]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- sink-sink
+
+// FP64 direct sum over sink pairs; one wave per sink target, lanes stride the
+// sources; results unscaled by G.
+template <typename T>
+__global__ __launch_bounds__(64) void k_sink_sink(const int32_t *__restrict__ sink_pos,
+                                                  int64_t n_sink, const T *__restrict__ xs,
+                                                  const T *__restrict__ ys, const T *__restrict__ zs,
+                                                  const T *__restrict__ ms, const T *__restrict__ hs,
+                                                  double *__restrict__ ss) {
+    const int lane = threadIdx.x;
+    for (int64_t k = blockIdx.x; k < n_sink; k += gridDim.x) {
+        const int64_t p = sink_pos[k];
+        const double tx = xs[p], ty = ys[p], tz = zs[p], th = hs[p];
+        double bx = 0, by = 0, bz = 0, bp = 0;
+        for (int64_t j = lane; j < n_sink; j += 64) {
+            if (j == k) continue;
+            const int64_t q = sink_pos[j];
+            const double h = (double)hs[q];
+            pair<double>((double)xs[q] - tx, (double)ys[q] - ty, (double)zs[q] - tz, (double)ms[q],
+                         h * h, h, th * th, th, false, bx, by, bz, bp);
+        }
+        bx = wave_sum_f64(bx);
+        by = wave_sum_f64(by);
+        bz = wave_sum_f64(bz);
+        bp = wave_sum_f64(bp);
+        if (lane == 0) {
+            ss[4 * k] = bx;
+            ss[4 * k + 1] = by;
+            ss[4 * k + 2] = bz;
+            ss[4 * k + 3] = bp;
+        }
+    }
+}
+
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss) {
+    (void)G;
+    if (t->n_sink <= 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
+    if (t->dt == SF_F32)
+        hipLaunchKernelGGL(k_sink_sink<float>, dim3(blocks), dim3(64), 0, t->stream, t->sink_pos,
+                           t->n_sink, (const float *)t->xs, (const float *)t->ys,
+                           (const float *)t->zs, (const float *)t->ms, (const float *)t->hs, ss);
+    else
+        hipLaunchKernelGGL(k_sink_sink<double>, dim3(blocks), dim3(64), 0, t->stream, t->sink_pos,
+                           t->n_sink, (const double *)t->xs, (const double *)t->ys,
+                           (const double *)t->zs, (const double *)t->ms, (const double *)t->hs, ss);
+}
+
+// ---------------------------------------------------------------- launch
+
+int device_cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+template <typename T>
+static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void *acc, void *pot,
+                             int32_t *ctr, double *ss) {
+    WalkArgs<T> a{};
+    a.nd.n_nodes = t->n_nodes;
+    a.nd.nlevel = t->nlevel;
+    a.nd.nfirst = t->nfirst;
+    a.nd.ncount = t->ncount;
+    a.nd.nchild = t->nchild;
+    a.nd.nnchild = t->nnchild;
+    a.nd.clo = t->clo;
+    a.nd.chi = t->chi;
+    a.nd.M = t->M[set];
+    a.nd.com = t->com[set];
+    a.nd.Q = t->Q[set];
+    a.nd.hmax = t->hmax[set];
+    a.nd.side = t->hframe.side;
+    a.nd.th2 = o.theta * o.theta;
+    a.xs = (const T *)t->xs;
+    a.ys = (const T *)t->ys;
+    a.zs = (const T *)t->zs;
+    a.ms = (const T *)t->ms;
+    a.hs = (const T *)t->hs;
+    a.order = t->order;
+    a.n = t->n;
+    a.n_gas = t->n_gas;
+    a.n_groups_dev = t->n_groups_dev;
+    a.gfirst = t->gfirst;
+    a.gcount = t->gcount;
+    a.gbox = t->gbox;
+    a.ghmax = t->ghmax;
+    a.gcen = t->gcen;
+    a.sink_pos = t->sink_pos;
+    a.n_sink = t->n_sink;
+    a.ss = ss;
+    a.task_ctr = ctr;
+    a.err = ctr + 2;
+    a.gnpc = t->gnpc;
+    a.gnpp = t->gnpp;
+    a.acc = (T *)acc;
+    a.pot = (T *)pot;
+    a.G = o.G;
+    return a;
+}
+
+template <typename T, int FORM, int ORDER>
+static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, int32_t *ctr,
+                         double *ss) {
+    const unsigned grid = (unsigned)(device_cu_count() * 16);
+    WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss);
+    if (o.stats)
+        hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, true>), dim3(grid), dim3(64), 0, t->stream, ag);
+    else
+        hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, false>), dim3(grid), dim3(64), 0, t->stream, ag);
+    if (t->n_sink > 0) {
+        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + 1, ss);
+        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
+        hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
+    }
+}
+
+template <typename T>
+static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
+                           int32_t *ctr, double *ss) {
+#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss)
+    if (o.order == 0) {
+        if (o.form == SF_FP32C) SF_W(SF_FP32C, 0);
+        else if (o.form == SF_FP32) SF_W(SF_FP32, 0);
+        else SF_W(SF_FP64, 0);
+    } else {
+        if (o.form == SF_FP32C) SF_W(SF_FP32C, 2);
+        else if (o.form == SF_FP32) SF_W(SF_FP32, 2);
+        else SF_W(SF_FP64, 2);
+    }
+#undef SF_W
+}
+
+sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
+    int32_t *ctr = nullptr;
+    double *ss = nullptr;
+    SF_ALLOC_TMP(ar, ctr, 4);
+    fill_u32((uint32_t *)ctr, 4, 0u, t->stream);
+    if (t->n_sink > 0) {
+        SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
+        sink_sink_accel(t, o.G, ss);
+    }
+    if (o.stats) {
+        if (!t->gnpc) {
+            DevArena keep(t->stream);
+            SF_ALLOC(keep, t->gnpc, t->groups_cap);
+            SF_ALLOC(keep, t->gnpp, t->groups_cap);
+            for (void *p : keep.keep) t->allocs.push_back(p);
+            keep.keep.clear();
+        }
+        fill_u32((uint32_t *)t->gnpc, t->groups_cap, 0u, t->stream);
+        fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
+        t->have_stats = true;
+    }
+    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss);
+    else dispatch_walks<double>(t, o, acc, pot, ctr, ss);
+    SF_HIP(hipGetLastError());
+    int32_t herr = 0;
+    SF_HIP(hipMemcpyAsync(&herr, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipStreamSynchronize(t->stream));
+    if (herr)
+        return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);
+    return SF_OK;
+}
+
+}  // namespace sf
