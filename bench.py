@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark: softened-gravity accelerations/s at 4M particles, FP32C vs FP64.
+
+Workload (precision study): 4,194,304 gas cells drawn as 512 Plummer clumps
+(scale radii log-uniform in [1e-4, 0.05], 70% of the mass) on a uniform
+background, softening = radius enclosing the 32 nearest neighbours, plus 2048
+close sink binaries (separations 1e-5..1e-3, sink softening 1e-4), FP32 inputs,
+seed 2.  One step = one full force evaluation on the GPU through the C ABI:
+tree build (box, keys, radix sort, gather, topology, moments, groups), group
+walk with quadrupole nodes at theta = 0.5, FP64 sink-sink sum, sink walk and
+output scatter.  value = particles / step time (accelerations per second).
+
+Reported beside it: the same step in the FP64 form, the median and p99
+relative force error of both forms against the FP64 CPU oracle (direct sum) on
+a random target subsample, the walk kernel's roofline (algorithmic FLOP per
+launch / launch time from HIP events on the library's stream), and the oracle
+itself timed on the host cores over that subsample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FLOP per interaction (FMA = 2, rsqrt = 1), counted from the
+# evaluation code: particle pair 20, quadrupole node 54, monopole node 20.
+FLOP_PP = 20
+FLOP_PC = {0: 20, 2: 54}
+PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (published, packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_11254_amd import _lib as L
+    from synth import precision_cloud, subsample
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    n_gas = max(4096, int(round((1 << 22) * args.scale)))
+    n_bin = max(16, int(round(2048 * args.scale)))
+    t0 = time.time()
+    ps = precision_cloud(n_gas, n_bin, seed=2)
+    log(f"workload: {ps.n} particles ({ps.n_gas} gas, {ps.n_sink} sinks), "
+        f"generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda", 0)
+    x, m, h = (torch.as_tensor(v).to(dev) for v in (ps.x, ps.m, ps.h))
+    acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
+
+    def opts(form, timing=False, stats=False):
+        return L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=16, group_cap=64,
+                           n_gas=ps.n_gas, timing=timing, collect_stats=stats)
+
+    def step(o):
+        t = L.sf_grav_build_tree(x, m, h, o)
+        L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
+        return t
+
+    def timed(form, steps, warmup):
+        o = opts(form, timing=True)
+        for _ in range(warmup):
+            L.sf_grav_tree_free(step(o))
+        torch.cuda.synchronize()
+        walk_ms, phase = [], {}
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            t = step(o)
+            tm = L.sf_grav_get_timings(t)
+            walk_ms.append(tm["walk"])
+            for k, v in tm.items():
+                if v is not None:
+                    phase.setdefault(k, []).append(v)
+            L.sf_grav_tree_free(t)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t_start) / steps
+        return wall, float(np.mean(walk_ms)), {k: float(np.mean(v)) for k, v in phase.items()}
+
+    # interaction counts of one evaluation (untimed), for the FLOP count
+    t = step(opts("fp32c", stats=True))
+    torch.cuda.synchronize()
+    gf = L.sf_grav_tree_export(t, "group_first").numpy().astype(np.int64)
+    gc = L.sf_grav_tree_export(t, "group_count").numpy().astype(np.int64)
+    npc = L.sf_grav_tree_export(t, "group_npc").numpy().astype(np.int64)
+    npp = L.sf_grav_tree_export(t, "group_npp").numpy().astype(np.int64)
+    order = L.sf_grav_tree_export(t, "order").numpy()
+    info = L.sf_grav_get_tree_info(t)
+    L.sf_grav_tree_free(t)
+    is_gas_sorted = (order < ps.n_gas).astype(np.int64)
+    csum = np.concatenate([[0], np.cumsum(is_gas_sorted)])
+    active = csum[gf + gc] - csum[gf]
+    n_pc = int((active * npc).sum())
+    n_pp = int((active * npp).sum())
+    walk_flop = FLOP_PP * n_pp + FLOP_PC[2] * n_pc
+    log(f"tree: {info['n_nodes']} nodes, {info['n_groups']} groups, max level {info['max_level']}; "
+        f"interactions/target: {n_pc / ps.n_gas:.0f} node + {n_pp / ps.n_gas:.0f} particle")
+
+    wall32, walk32, ph32 = timed("fp32c", args.steps, args.warmup)
+    out32 = acc.double().cpu().numpy()
+    log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
+        + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
+    res = {}
+    if not args.no_fp64:
+        k64 = max(2, args.steps // 3)
+        wall64, walk64, ph64 = timed("fp64", k64, 1)
+        out64 = acc.double().cpu().numpy()
+        res["fp64"] = {"ms_per_step": wall64 * 1e3, "value": ps.n / wall64,
+                       "walk_ms": walk64, "phases_ms": ph64}
+        log(f"fp64: {wall64 * 1e3:.2f} ms/step, walk kernel {walk64:.2f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import direct as odirect
+        xd, md, hd = (np.asarray(v, dtype=np.float64) for v in (ps.x, ps.m, ps.h))
+        probe = subsample(ps.n, 256, seed=2)
+        t0 = time.perf_counter()
+        odirect.direct(xd, md, hd, targets=probe)
+        rate = probe.size / (time.perf_counter() - t0)
+        k = int(min(65536, max(512, rate * args.cpu_seconds)))
+        sample = subsample(ps.n, k, seed=2)
+        t0 = time.perf_counter()
+        ar, pr = odirect.direct(xd, md, hd, targets=sample)
+        tcpu = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": sample.size / tcpu, "unit": "accels/s", "cores": cores, "kind": "oracle",
+               "sample": f"{sample.size} random targets x all {ps.n} sources, FP64 direct sum, "
+                         f"{tcpu:.1f}s"}
+        log(f"oracle: {sample.size} targets in {tcpu:.1f}s on {cores} threads")
+
+        def errs(out):
+            e = np.linalg.norm(out[sample] - ar, axis=1) / np.linalg.norm(ar, axis=1)
+            return float(np.median(e)), float(np.quantile(e, 0.99))
+        res["err_fp32c"] = errs(out32)
+        if "fp64" in res:
+            res["err_fp64"] = errs(out64)
+
+    achieved = walk_flop / (walk32 * 1e-3) / 1e12
+    line = {
+        "metric": "softened-gravity accels/sec at 4M particles (FP32c vs FP64); p99 force err",
+        "value": ps.n / wall32,
+        "unit": "accels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "precision4m: 4,194,304 clustered gas + 2048 sink binaries",
+                   "n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "inputs": "fp32",
+                   "path": "tree", "theta": args.theta, "order": "quadrupole",
+                   "form": "fp32c", "leaf_cap": 16, "group_cap": 64, "seed": 2},
+        "roofline": {"bound": "alu", "kernel": "k_walk_groups", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                     "traffic": None,
+                     "walk_ms": walk32, "flop_per_launch": walk_flop,
+                     "interactions_per_s": (n_pc + n_pp) / (walk32 * 1e-3),
+                     "n_pc": n_pc, "n_pp": n_pp},
+        "cpu_baseline": cpu,
+        "phases_ms": ph32,
+    }
+    if "fp64" in res:
+        line["fp64"] = res["fp64"]
+        line["fp32c_over_fp64"] = res["fp64"]["ms_per_step"] / (wall32 * 1e3)
+    if "err_fp32c" in res:
+        line["rel_err_fp32c"] = {"median": res["err_fp32c"][0], "p99": res["err_fp32c"][1]}
+        if "err_fp64" in res:
+            line["rel_err_fp64"] = {"median": res["err_fp64"][0], "p99": res["err_fp64"][1]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

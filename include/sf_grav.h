@@ -86,7 +86,7 @@ typedef struct {
     int32_t validate;     /* 1: check finite inputs, h > 0, m >= 0 (one pass) */
     int64_t n_gas;        /* particles [0,n_gas) are gas; default -1 = all   */
     int32_t collect_stats;/* 1: record per-group interaction counts          */
-    int32_t reserved;
+    int32_t timing;       /* 1: record hipEvents around each phase (tree)    */
 } sf_grav_opts;
 
 /* Fill *o with the defaults above (struct_size set).  Never fails. */
@@ -189,6 +189,23 @@ typedef enum {
 
 sf_status sf_grav_tree_export(sf_grav_tree tree, int32_t what, void *host_dst,
                               size_t bytes);
+
+/* Phase timers of the last build / accel / backward on a handle, recorded
+ * with hipEvents on the call's stream when opts.timing = 1 (milliseconds;
+ * -1 for a phase that did not run).  Synchronises the stream.
+ *   build:    [0] sort (box, keys, radix sort, gather)  [1] topology
+ *             [2] moments  [3] groups
+ *   accel:    [4] sink-sink FP64  [5] group walk  [6] sink walk
+ *   backward: [7] sink-sink FP64  [8] group walk  [9] sink walk
+ *             [10] push-down and output
+ * Errors: SF_E_INVALID (NULL, struct_size), SF_E_DEVICE. */
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(sf_grav_timings) */
+    int32_t n_phases;       /* = 11 */
+    double ms[16];
+} sf_grav_timings;
+
+sf_status sf_grav_get_timings(sf_grav_tree tree, sf_grav_timings *out);
 
 /* Static text for a status code. */
 const char *sf_grav_strerror(sf_status s);

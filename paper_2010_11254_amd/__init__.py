@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     sf_grav_accel,
     sf_grav_accel_backward,
     sf_grav_build_tree,
+    sf_grav_get_timings,
     sf_grav_get_tree_info,
     sf_grav_tree_export,
     sf_grav_tree_free,

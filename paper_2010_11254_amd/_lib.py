@@ -44,8 +44,17 @@ class sf_grav_opts(ctypes.Structure):
         ("struct_size", ctypes.c_uint32), ("form", ctypes.c_int32), ("G", ctypes.c_double),
         ("theta", ctypes.c_double), ("order", ctypes.c_int32), ("leaf_cap", ctypes.c_int32),
         ("group_cap", ctypes.c_int32), ("validate", ctypes.c_int32), ("n_gas", ctypes.c_int64),
-        ("collect_stats", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("collect_stats", ctypes.c_int32), ("timing", ctypes.c_int32),
     ]
+
+
+class sf_grav_timings(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_phases", ctypes.c_int32),
+                ("ms", ctypes.c_double * 16)]
+
+
+PHASES = ("sort", "topology", "moments", "groups", "sinksink", "walk", "sinkwalk",
+          "b_sinksink", "b_walk", "b_sinkwalk", "b_pushdown")
 
 
 class sf_grav_tree_info(ctypes.Structure):
@@ -59,7 +68,8 @@ class sf_grav_tree_info(ctypes.Structure):
 _lib = None
 EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_accel_backward", "sf_grav_tree_free", "sf_grav_get_tree_info",
-            "sf_grav_tree_export", "sf_grav_strerror", "sf_grav_last_error")
+            "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
+            "sf_grav_last_error")
 
 
 def lib():
@@ -82,12 +92,14 @@ def lib():
     L.sf_grav_tree_free.argtypes = [vp]
     L.sf_grav_get_tree_info.argtypes = [vp, ctypes.POINTER(sf_grav_tree_info)]
     L.sf_grav_tree_export.argtypes = [vp, i32, vp, ctypes.c_size_t]
+    L.sf_grav_get_timings.argtypes = [vp, ctypes.POINTER(sf_grav_timings)]
     L.sf_grav_strerror.argtypes = [i32]
     L.sf_grav_strerror.restype = ctypes.c_char_p
     L.sf_grav_last_error.argtypes = []
     L.sf_grav_last_error.restype = ctypes.c_char_p
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
-                 "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export"):
+                 "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
+                 "sf_grav_get_timings"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -101,13 +113,14 @@ def _check(status, where):
 
 
 def make_opts(form="fp32c", G=1.0, theta=0.5, order=2, leaf_cap=16, group_cap=64,
-              validate=False, n_gas=-1, collect_stats=False):
+              validate=False, n_gas=-1, collect_stats=False, timing=False):
     o = sf_grav_opts()
     lib().sf_grav_opts_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.G, o.theta, o.order = float(G), float(theta), int(order)
     o.leaf_cap, o.group_cap = int(leaf_cap), int(group_cap)
     o.validate, o.n_gas, o.collect_stats = int(bool(validate)), int(n_gas), int(bool(collect_stats))
+    o.timing = int(bool(timing))
     return o
 
 
@@ -225,6 +238,14 @@ def sf_grav_get_tree_info(tree):
     return {k: getattr(info, k) for k, _ in sf_grav_tree_info._fields_ if k != "struct_size"}
 
 
+def sf_grav_get_timings(tree):
+    """Phase times (ms) of the handle's last build/accel/backward; None if not run."""
+    t = sf_grav_timings()
+    t.struct_size = ctypes.sizeof(sf_grav_timings)
+    _check(lib().sf_grav_get_timings(tree.handle, ctypes.byref(t)), "sf_grav_get_timings")
+    return {name: (t.ms[i] if t.ms[i] >= 0 else None) for i, name in enumerate(PHASES)}
+
+
 def sf_grav_tree_export(tree, what):
     """Copy one of the handle's arrays to a new host tensor."""
     wid, dtype, size_kind = EXPORTS[what]
@@ -232,6 +253,8 @@ def sf_grav_tree_export(tree, what):
     count = {1: info["n"], 0: info["n_nodes"], 2: info["n_groups"]}[size_kind]
     width = {"node_com": 3, "node_quad": 6}.get(what, 1)
     out = torch.empty((count * width,), dtype=dtype)
+    if out.numel() == 0:
+        return out.view(count, width) if width > 1 else out
     nbytes = out.numel() * out.element_size()
     _check(lib().sf_grav_tree_export(tree.handle, wid, ctypes.c_void_p(out.data_ptr()), nbytes),
            "sf_grav_tree_export")

@@ -49,6 +49,27 @@ void DevArena::free_keep() {
     keep.clear();
 }
 
+void phase_begin(sf_grav_tree_s *t, int ph) {
+    if (!t->timing) return;
+    if (!t->ev0[ph]) {
+        if (hipEventCreate(&t->ev0[ph]) != hipSuccess || hipEventCreate(&t->ev1[ph]) != hipSuccess) {
+            t->ev0[ph] = nullptr;
+            return;
+        }
+    }
+    (void)hipEventRecord(t->ev0[ph], t->stream);
+}
+
+void phase_end(sf_grav_tree_s *t, int ph) {
+    if (!t->timing || !t->ev0[ph]) return;
+    (void)hipEventRecord(t->ev1[ph], t->stream);
+    t->ev_used[ph] = true;
+}
+
+static void phase_reset(sf_grav_tree_s *t, int lo, int hi) {
+    for (int p = lo; p < hi; ++p) t->ev_used[p] = false;
+}
+
 }  // namespace sf
 
 using sf::DevArena;
@@ -90,9 +111,14 @@ static sf_status check_arrays(const void *pos, const void *mass, const void *sof
 
 static void free_handle_memory(sf_grav_tree_s *t) {
     if (!t) return;
-    if (t->stream || true) hipStreamSynchronize(t->stream);
-    for (void *p : t->allocs) hipFree(p);
+    (void)hipStreamSynchronize(t->stream);
+    for (void *p : t->allocs) (void)hipFree(p);
     t->allocs.clear();
+    for (int p = 0; p < sf_grav_tree_s::kPhases; ++p) {
+        if (t->ev0[p]) (void)hipEventDestroy(t->ev0[p]);
+        if (t->ev1[p]) (void)hipEventDestroy(t->ev1[p]);
+        t->ev0[p] = t->ev1[p] = nullptr;
+    }
 }
 
 extern "C" {
@@ -110,6 +136,7 @@ void sf_grav_opts_default(sf_grav_opts *o) {
     o->validate = 0;
     o->n_gas = -1;
     o->collect_stats = 0;
+    o->timing = 0;
 }
 
 const char *sf_grav_strerror(sf_status s) {
@@ -130,19 +157,30 @@ const char *sf_grav_last_error(void) { return g_msg; }
 // Build everything for the tree path into a fresh handle.
 static sf_status build_all(sf_grav_tree_s *t, const void *pos, const void *mass, const void *soft,
                            const sf_grav_opts *o, DevArena &ar) {
+    t->timing = o->timing != 0;
+    sf::phase_reset(t, 0, sf_grav_tree_s::kPhases);
+    sf::phase_begin(t, 0);
     sf_status st = sf::build_sorted(pos, mass, soft, t->n, t->n_gas, t->dt, false, o->validate != 0,
                                     t, ar);
     if (st != SF_OK) return st;
+    sf::phase_end(t, 0);
     SF_HIP(hipMemcpyAsync(&t->hframe, t->frame, sizeof(sf::Frame), hipMemcpyDeviceToHost, t->stream));
+    sf::phase_begin(t, 1);
     st = sf::build_topology(t, ar);   // synchronises the stream once
     if (st != SF_OK) return st;
+    sf::phase_end(t, 1);
     if (o->validate && t->hframe.bad)
         return sf_fail(SF_E_INVALID, "inputs contain non-finite values, h <= 0 or m < 0");
     if (t->n_nodes >= (1ll << 27))
         return sf_fail(SF_E_UNSUPPORTED, "tree has %lld nodes (limit 2^27)", (long long)t->n_nodes);
+    sf::phase_begin(t, 2);
     st = sf::build_moments(t, ar);
     if (st != SF_OK) return st;
-    return sf::build_groups(t, ar);
+    sf::phase_end(t, 2);
+    sf::phase_begin(t, 3);
+    st = sf::build_groups(t, ar);
+    sf::phase_end(t, 3);
+    return st;
 }
 
 sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft, int64_t n,
@@ -207,6 +245,8 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, co
         eval_opts(o, e);
         hipStream_t prev = tree->stream;
         tree->stream = (hipStream_t)stream;
+        tree->timing = o->timing != 0;
+        sf::phase_reset(tree, 4, 7);
         DevArena ar(tree->stream);
         st = sf::tree_accel(tree, e, acc, pot, ar);
         if (st != SF_OK) {
@@ -256,6 +296,8 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void 
             return sf_fail(SF_E_STATE, "n/dtype differ from the handle's");
         eval_opts(o, e);
         tree->stream = (hipStream_t)stream;
+        tree->timing = o->timing != 0;
+        sf::phase_reset(tree, 7, 11);
         DevArena ar(tree->stream);
         return sf::tree_backward(tree, e, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
     }
@@ -275,6 +317,23 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void 
         ar.free_keep();
     }
     return st;
+}
+
+sf_status sf_grav_get_timings(sf_grav_tree t, sf_grav_timings *out) {
+    g_msg[0] = 0;
+    if (!t || !out) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (out->struct_size != sizeof(sf_grav_timings))
+        return sf_fail(SF_E_INVALID, "timings.struct_size mismatch");
+    out->n_phases = sf_grav_tree_s::kPhases;
+    for (int p = 0; p < 16; ++p) out->ms[p] = -1.0;
+    for (int p = 0; p < sf_grav_tree_s::kPhases; ++p) {
+        if (!t->ev_used[p]) continue;
+        SF_HIP(hipEventSynchronize(t->ev1[p]));
+        float ms = 0.f;
+        SF_HIP(hipEventElapsedTime(&ms, t->ev0[p], t->ev1[p]));
+        out->ms[p] = ms;
+    }
+    return SF_OK;
 }
 
 sf_status sf_grav_tree_free(sf_grav_tree tree) {

@@ -77,4 +77,8 @@ void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4);
 
 int device_cu_count();
 
+// Phase timer helpers: no-ops unless t->timing.
+void phase_begin(sf_grav_tree_s *t, int ph);
+void phase_end(sf_grav_tree_s *t, int ph);
+
 }  // namespace sf

@@ -157,5 +157,10 @@ struct sf_grav_tree_s {
     void *tsrc = nullptr;                             // packed source records
 
     bool direct_only = false;                         // built by the direct path
+    // phase timers (opts.timing)
+    static constexpr int kPhases = 11;
+    hipEvent_t ev0[kPhases] = {}, ev1[kPhases] = {};
+    bool ev_used[kPhases] = {};
+    bool timing = false;
     std::vector<void *> allocs;                       // device memory owned here
 };

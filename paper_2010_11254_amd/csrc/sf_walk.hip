@@ -655,14 +655,18 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
                          double *ss) {
     const unsigned grid = (unsigned)(device_cu_count() * 16);
     WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss);
+    phase_begin(t, 5);
     if (o.stats)
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, true>), dim3(grid), dim3(64), 0, t->stream, ag);
     else
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, false>), dim3(grid), dim3(64), 0, t->stream, ag);
+    phase_end(t, 5);
     if (t->n_sink > 0) {
         WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + 1, ss);
         const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
+        phase_begin(t, 6);
         hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
+        phase_end(t, 6);
     }
 }
 
@@ -689,7 +693,9 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     fill_u32((uint32_t *)ctr, 4, 0u, t->stream);
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
+        phase_begin(t, 4);
         sink_sink_accel(t, o.G, ss);
+        phase_end(t, 4);
     }
     if (o.stats) {
         if (!t->gnpc) {
