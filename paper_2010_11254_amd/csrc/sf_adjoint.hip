@@ -18,6 +18,7 @@
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_walk.h"
 
 namespace sf {
 
@@ -310,11 +311,622 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
 #undef SF_B
 }
 
+// ---------------------------------------------------------------- tree adjoint
+//
+// The tree result is a sum over the frozen interaction lists of pair terms
+// (target i, particle j) and node terms (target i, node n with mass M, centre
+// of mass c, traceless quadrupole Q).  Its gradient has three parts:
+//   * target side: d/dx_i, d/dh_i of the target's own terms (gathered by the
+//     lane that owns the target, as in the forward walk);
+//   * source side: d/dx_j, d/dm_j, d/dh_j of pair terms (pass 2 of each batch:
+//     lanes own the sources and loop over the group's targets, then one FP64
+//     atomic add per source and value);
+//   * node side: d/dM, d/dc, d/dQ of node terms (pass 2 for nodes), later
+//     pushed down to every particle of the node through M = sum m,
+//     c = sum m x / M, Q = sum m (3 y y^T - |y|^2 I), y = x - c.
+// Opening decisions are held fixed, so this is the exact derivative of the
+// tree approximation as evaluated.
+
+// Pair (target i, source j), d = x_j - x_i: S = dT/dx_j (target gets -S),
+// Tm = dT/dm_j, Th = dT/dh_ij, share_i = part of Th owned by the target.
+template <typename R>
+__device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2, R hi, R gax,
+                                      R gay, R gaz, R gp, bool self, R &Sx, R &Sy, R &Sz, R &Tm,
+                                      R &Th, R &share_i) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ri = rsq(r2);
+    const R ri2 = ri * ri;
+    R F = ri * ri2, P = ri, FrR = R(-3) * F * ri2, dFh = R(0), dPh = R(0);
+    const R hh2 = hj2 > hi2 ? hj2 : hi2;
+    const bool soft = r2 < hh2;
+    if (soft) {
+        dsoft<R>(r2, hj > hi ? hj : hi, F, P, FrR, dFh, dPh);
+        if (self) { F = R(0); P = R(0); FrR = R(0); dFh = R(0); dPh = R(0); }
+    }
+    const R ad = gax * dx + gay * dy + gaz * dz;
+    const R c1 = ad * FrR + gp * F;
+    Sx = mj * (F * gax + c1 * dx);
+    Sy = mj * (F * gay + c1 * dy);
+    Sz = mj * (F * gaz + c1 * dz);
+    Tm = ad * F - gp * P;
+    Th = soft ? mj * (ad * dFh - gp * dPh) : R(0);
+    share_i = hi > hj ? R(1) : (hi == hj ? R(0.5) : R(0));
+}
+
+// Node term, r = x_i - c: g = dL/dr (the centre of mass gets -g), gM = dL/dM,
+// gs = symmetric dL/dQ (xx yy zz xy xz yz; zero for monopoles).
+template <typename R, int ORDER>
+__device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz,
+                                           R qyz, R gax, R gay, R gaz, R gp, R &gx, R &gy,
+                                           R &gz, R &gM, R gs[6]) {
+    const R r2 = rx * rx + ry * ry + rz * rz;
+    const R ri = rsq(r2);
+    const R ri2 = ri * ri;
+    const R ri3 = ri * ri2;
+    const R ri5 = ri3 * ri2;
+    const R ra = rx * gax + ry * gay + rz * gaz;
+    gM = -ra * ri3 - gp * ri;
+    // monopole part: -M ri3 a + 3 M ra ri5 r + gp M ri3 r
+    const R cr = R(3) * M * ra * ri5 + gp * M * ri3;
+    gx = -M * ri3 * gax + cr * rx;
+    gy = -M * ri3 * gay + cr * ry;
+    gz = -M * ri3 * gaz + cr * rz;
+    if (ORDER == 2) {
+        const R qzz = -(qxx + qyy);
+        const R qx = qxx * rx + qxy * ry + qxz * rz;
+        const R qy = qxy * rx + qyy * ry + qyz * rz;
+        const R qz = qxz * rx + qyz * ry + qzz * rz;
+        const R Qax = qxx * gax + qxy * gay + qxz * gaz;
+        const R Qay = qxy * gax + qyy * gay + qyz * gaz;
+        const R Qaz = qxz * gax + qyz * gay + qzz * gaz;
+        const R q = qx * rx + qy * ry + qz * rz;
+        const R aQr = gax * qx + gay * qy + gaz * qz;
+        const R ri7 = ri5 * ri2;
+        const R ri9 = ri7 * ri2;
+        // + ri5 Qa - 5 aQr ri7 r - 5 ra ri7 Qr - 2.5 q ri7 a + 17.5 q ra ri9 r
+        // - gp ri5 Qr + 2.5 gp q ri7 r
+        const R cr2 = R(-5) * aQr * ri7 + R(17.5) * q * ra * ri9 + R(2.5) * gp * q * ri7;
+        const R cq = R(-5) * ra * ri7 - gp * ri5;
+        const R ca = R(-2.5) * q * ri7;
+        gx += ri5 * Qax + cr2 * rx + cq * qx + ca * gax;
+        gy += ri5 * Qay + cr2 * ry + cq * qy + ca * gay;
+        gz += ri5 * Qaz + cr2 * rz + cq * qz + ca * gaz;
+        const R k = R(2.5) * ra * ri7 + R(0.5) * gp * ri5;
+        const R h5 = R(0.5) * ri5;
+        gs[0] = gax * rx * ri5 - k * rx * rx;
+        gs[1] = gay * ry * ri5 - k * ry * ry;
+        gs[2] = gaz * rz * ri5 - k * rz * rz;
+        gs[3] = h5 * (gax * ry + gay * rx) - k * rx * ry;
+        gs[4] = h5 * (gax * rz + gaz * rx) - k * rx * rz;
+        gs[5] = h5 * (gay * rz + gaz * ry) - k * ry * rz;
+    } else {
+        for (int d = 0; d < 6; ++d) gs[d] = R(0);
+    }
+}
+
+template <typename T>
+struct WalkArgsB {
+    WalkNodes nd;
+    const T *xs, *ys, *zs, *ms, *hs;
+    const int32_t *order;
+    int64_t n, n_gas;
+    const int32_t *n_groups_dev, *gfirst, *gcount;
+    const double *gbox, *ghmax, *gcen;
+    const int32_t *sink_pos;
+    int64_t n_sink;
+    const T *g_acc, *g_pot;     // caller order
+    double *tgt;                // 5 per sorted particle: target side (x y z m h)
+    double *scat;               // 5 per sorted particle: source side (atomic)
+    double *nadj;               // 10 per node: M, c(3), dQ(6) (atomic)
+    int32_t *task_ctr, *err;
+};
+
+template <typename R> struct alignas(16) TStage { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx, act; };
+
+__device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+template <typename T, int FORM, int ORDER>
+struct GroupEvalB {
+    using R = typename FormT<FORM>::R;
+    const WalkArgsB<T> *a;
+    PPStage<R> *spp;
+    PCStage<R> *spc;
+    TStage<R> *st;
+    int ntg;                    // targets staged (lanes < ntg)
+    double cen[3];
+    TStage<R> me;
+    Acc<FORM> ox, oy, oz, oh;
+
+    __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        const int lane = threadIdx.x;
+        int node = -1;
+        PCStage<R> sn;
+        if ((uint32_t)lane < nb) {
+            node = L.pc[(head + lane) & 127];
+            const WalkNodes &nd = a->nd;
+            sn.x = dto_frame<FORM>(nd.com[3 * node], cen[0]);
+            sn.y = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
+            sn.z = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            sn.M = (R)nd.M[node];
+            sn.qxx = sn.qyy = sn.qxy = sn.qxz = sn.qyz = R(0);
+            if (ORDER == 2) {
+                sn.qxx = (R)nd.Q[6 * node];
+                sn.qyy = (R)nd.Q[6 * node + 1];
+                sn.qxy = (R)nd.Q[6 * node + 3];
+                sn.qxz = (R)nd.Q[6 * node + 4];
+                sn.qyz = (R)nd.Q[6 * node + 5];
+            }
+            spc[lane] = sn;
+        }
+        __syncthreads();
+        // pass 1: lanes own targets
+        R bx = 0, by = 0, bz = 0;
+        for (uint32_t j = 0; j < nb; ++j) {
+            const PCStage<R> s = spc[j];
+            R gx, gy, gz, gM, gs[6];
+            bmultipole<R, ORDER>(me.x - s.x, me.y - s.y, me.z - s.z, s.M, s.qxx, s.qyy, s.qxy,
+                                 s.qxz, s.qyz, me.gx, me.gy, me.gz, me.gp, gx, gy, gz, gM, gs);
+            bx += gx;
+            by += gy;
+            bz += gz;
+        }
+        ox.fold(bx);
+        oy.fold(by);
+        oz.fold(bz);
+        // pass 2: lanes own nodes, loop over the group's active targets
+        if ((uint32_t)lane < nb) {
+            R cx = 0, cy = 0, cz = 0, mb = 0, g6[6] = {0, 0, 0, 0, 0, 0};
+            for (int t = 0; t < ntg; ++t) {
+                const TStage<R> q = st[t];
+                if (!q.act) continue;
+                R gx, gy, gz, gM, gs[6];
+                bmultipole<R, ORDER>(q.x - sn.x, q.y - sn.y, q.z - sn.z, sn.M, sn.qxx, sn.qyy,
+                                     sn.qxy, sn.qxz, sn.qyz, q.gx, q.gy, q.gz, q.gp, gx, gy, gz,
+                                     gM, gs);
+                cx -= gx;
+                cy -= gy;
+                cz -= gz;
+                mb += gM;
+                for (int d = 0; d < 6; ++d) g6[d] += gs[d];
+            }
+            double *o = a->nadj + 10 * (int64_t)node;
+            atomic_add_f64(o, (double)mb);
+            atomic_add_f64(o + 1, (double)cx);
+            atomic_add_f64(o + 2, (double)cy);
+            atomic_add_f64(o + 3, (double)cz);
+            if (ORDER == 2)
+                for (int d = 0; d < 6; ++d) atomic_add_f64(o + 4 + d, (double)g6[d]);
+        }
+        __syncthreads();
+    }
+
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        const int lane = threadIdx.x;
+        PPStage<R> sj;
+        int p = -1;
+        if ((uint32_t)lane < nb) {
+            p = L.slot[lane];
+            sj.x = to_frame<FORM>(a->xs[p], cen[0]);
+            sj.y = to_frame<FORM>(a->ys[p], cen[1]);
+            sj.z = to_frame<FORM>(a->zs[p], cen[2]);
+            sj.m = (R)a->ms[p];
+            sj.h = (R)a->hs[p];
+            sj.h2 = sj.h * sj.h;
+            sj.idx = p;
+            spp[lane] = sj;
+        }
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bh = 0;
+        for (uint32_t j = 0; j < nb; ++j) {
+            const PPStage<R> s = spp[j];
+            R Sx, Sy, Sz, Tm, Th, sh;
+            bpair<R>(s.x - me.x, s.y - me.y, s.z - me.z, s.m, s.h2, s.h, me.h2, me.h, me.gx, me.gy,
+                     me.gz, me.gp, s.idx == me.idx, Sx, Sy, Sz, Tm, Th, sh);
+            bx -= Sx;
+            by -= Sy;
+            bz -= Sz;
+            bh += sh * Th;
+        }
+        ox.fold(bx);
+        oy.fold(by);
+        oz.fold(bz);
+        oh.fold(bh);
+        if ((uint32_t)lane < nb) {
+            R sx = 0, sy = 0, sz = 0, sm = 0, shh = 0;
+            for (int t = 0; t < ntg; ++t) {
+                const TStage<R> q = st[t];
+                if (!q.act) continue;
+                R Sx, Sy, Sz, Tm, Th, sh;
+                bpair<R>(sj.x - q.x, sj.y - q.y, sj.z - q.z, sj.m, sj.h2, sj.h, q.h2, q.h, q.gx,
+                         q.gy, q.gz, q.gp, p == q.idx, Sx, Sy, Sz, Tm, Th, sh);
+                sx += Sx;
+                sy += Sy;
+                sz += Sz;
+                sm += Tm;
+                shh += (R(1) - sh) * Th;
+            }
+            double *o = a->scat + 5 * (int64_t)p;
+            atomic_add_f64(o, (double)sx);
+            atomic_add_f64(o + 1, (double)sy);
+            atomic_add_f64(o + 2, (double)sz);
+            atomic_add_f64(o + 3, (double)sm);
+            atomic_add_f64(o + 4, (double)shh);
+        }
+        __syncthreads();
+    }
+};
+
+template <typename T, int FORM, int ORDER>
+__global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
+    using R = typename FormT<FORM>::R;
+    __shared__ WalkLds L;
+    __shared__ PPStage<R> spp[64];
+    __shared__ PCStage<R> spc[64];
+    __shared__ TStage<R> st[64];
+    const int lane = threadIdx.x;
+    const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
+    GroupEvalB<T, FORM, ORDER> ev;
+    ev.a = &a;
+    ev.spp = spp;
+    ev.spc = spc;
+    ev.st = st;
+    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+        const int64_t gf = a.gfirst[g], gc = a.gcount[g];
+        double blo[3], bhi[3];
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = a.gbox[6 * g + d];
+            bhi[d] = a.gbox[6 * g + 3 + d];
+            ev.cen[d] = a.gcen[3 * g + d];
+        }
+        const double hg = a.ghmax[g];
+        const bool has = lane < gc;
+        const int64_t i = gf + (has ? lane : 0);
+        const bool active = has && a.order[i] < a.n_gas;
+        if (__ballot(active) == 0ull) continue;
+        const int64_t o = a.order[i];
+        TStage<R> me;
+        me.x = to_frame<FORM>(a.xs[i], ev.cen[0]);
+        me.y = to_frame<FORM>(a.ys[i], ev.cen[1]);
+        me.z = to_frame<FORM>(a.zs[i], ev.cen[2]);
+        me.h = (R)a.hs[i];
+        me.h2 = me.h * me.h;
+        me.gx = (R)a.g_acc[3 * o];
+        me.gy = (R)a.g_acc[3 * o + 1];
+        me.gz = (R)a.g_acc[3 * o + 2];
+        me.gp = a.g_pot ? (R)a.g_pot[o] : R(0);
+        me.idx = has ? (int32_t)i : -1;
+        me.act = active ? 1 : 0;
+        st[lane] = me;
+        ev.me = me;
+        ev.ntg = (int)gc;
+        ev.ox.zero();
+        ev.oy.zero();
+        ev.oz.zero();
+        ev.oh.zero();
+        __syncthreads();
+        uint32_t npc, npp;
+        walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
+        if (active) {
+            a.tgt[5 * i] = ev.ox.value();
+            a.tgt[5 * i + 1] = ev.oy.value();
+            a.tgt[5 * i + 2] = ev.oz.value();
+            a.tgt[5 * i + 3] = 0.0;
+            a.tgt[5 * i + 4] = ev.oh.value();
+        }
+    }
+}
+
+template <typename T, int FORM, int ORDER>
+struct SinkEvalB {
+    using R = typename FormT<FORM>::R;
+    const WalkArgsB<T> *a;
+    double cen[3];
+    R th, th2, gx, gy, gz, gp;
+    int32_t tidx;
+    Acc<FORM> ox, oy, oz, oh;   // per lane partials of the target side
+
+    __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        const int lane = threadIdx.x;
+        R bx = 0, by = 0, bz = 0;
+        if ((uint32_t)lane < nb) {
+            const int node = L.pc[(head + lane) & 127];
+            const WalkNodes &nd = a->nd;
+            const R cx = dto_frame<FORM>(nd.com[3 * node], cen[0]);
+            const R cy = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
+            const R cz = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
+            const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
+            const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
+            R qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
+            if (ORDER == 2) {
+                qxx = (R)nd.Q[6 * node];
+                qyy = (R)nd.Q[6 * node + 1];
+                qxy = (R)nd.Q[6 * node + 3];
+                qxz = (R)nd.Q[6 * node + 4];
+                qyz = (R)nd.Q[6 * node + 5];
+            }
+            R g0, g1, g2, gM, gs[6];
+            bmultipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.M[node], qxx, qyy, qxy, qxz, qyz,
+                                 gx, gy, gz, gp, g0, g1, g2, gM, gs);
+            bx = g0;
+            by = g1;
+            bz = g2;
+            double *o = a->nadj + 10 * (int64_t)node;
+            atomic_add_f64(o, (double)gM);
+            atomic_add_f64(o + 1, -(double)g0);
+            atomic_add_f64(o + 2, -(double)g1);
+            atomic_add_f64(o + 3, -(double)g2);
+            if (ORDER == 2)
+                for (int d = 0; d < 6; ++d) atomic_add_f64(o + 4 + d, (double)gs[d]);
+        }
+        ox.fold(bx);
+        oy.fold(by);
+        oz.fold(bz);
+    }
+
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        const int lane = threadIdx.x;
+        R bx = 0, by = 0, bz = 0, bh = 0;
+        if ((uint32_t)lane < nb) {
+            const int p = L.slot[lane];
+            if (a->order[p] < a->n_gas) {
+                const R sx = to_frame<FORM>(a->xs[p], cen[0]);
+                const R sy = to_frame<FORM>(a->ys[p], cen[1]);
+                const R sz = to_frame<FORM>(a->zs[p], cen[2]);
+                const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
+                const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
+                const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
+                const R h = (R)a->hs[p];
+                R Sx, Sy, Sz, Tm, Th, sh;
+                bpair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, gx, gy, gz, gp,
+                         p == tidx, Sx, Sy, Sz, Tm, Th, sh);
+                bx = -Sx;
+                by = -Sy;
+                bz = -Sz;
+                bh = sh * Th;
+                double *o = a->scat + 5 * (int64_t)p;
+                atomic_add_f64(o, (double)Sx);
+                atomic_add_f64(o + 1, (double)Sy);
+                atomic_add_f64(o + 2, (double)Sz);
+                atomic_add_f64(o + 3, (double)Tm);
+                atomic_add_f64(o + 4, (double)((R(1) - sh) * Th));
+            }
+        }
+        ox.fold(bx);
+        oy.fold(by);
+        oz.fold(bz);
+        oh.fold(bh);
+        __syncthreads();
+    }
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int FORM, int ORDER>
+__global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
+    using R = typename FormT<FORM>::R;
+    __shared__ WalkLds L;
+    const int lane = threadIdx.x;
+    SinkEvalB<T, FORM, ORDER> ev;
+    ev.a = &a;
+    for (int k = next_task(a.task_ctr); k < a.n_sink; k = next_task(a.task_ctr)) {
+        const int64_t p = a.sink_pos[k];
+        const int64_t o = a.order[p];
+        double b[3] = {(double)a.xs[p], (double)a.ys[p], (double)a.zs[p]};
+        for (int d = 0; d < 3; ++d) ev.cen[d] = b[d];
+        ev.th = (R)a.hs[p];
+        ev.th2 = ev.th * ev.th;
+        ev.gx = (R)a.g_acc[3 * o];
+        ev.gy = (R)a.g_acc[3 * o + 1];
+        ev.gz = (R)a.g_acc[3 * o + 2];
+        ev.gp = a.g_pot ? (R)a.g_pot[o] : R(0);
+        ev.tidx = (int32_t)p;
+        ev.ox.zero();
+        ev.oy.zero();
+        ev.oz.zero();
+        ev.oh.zero();
+        uint32_t npc, npp;
+        walk_task(a.nd, L, ev, b, b, (double)a.hs[p], p, p + 1, a.err, npc, npp);
+        const double s0 = wave_sum_d(ev.ox.value()), s1 = wave_sum_d(ev.oy.value());
+        const double s2 = wave_sum_d(ev.oz.value()), s4 = wave_sum_d(ev.oh.value());
+        if (lane == 0) {
+            a.tgt[5 * p] = s0;
+            a.tgt[5 * p + 1] = s1;
+            a.tgt[5 * p + 2] = s2;
+            a.tgt[5 * p + 3] = 0.0;
+            a.tgt[5 * p + 4] = s4;
+        }
+    }
+}
+
+// Push node adjoints down to particles, add every part and write the output.
+// For each sorted particle: walk its leaf's ancestors; set 0 (all particles)
+// always, set 1 (gas only) for gas particles.
+template <typename T>
+__global__ void k_pushdown(int64_t n, int64_t n_gas, const T *__restrict__ xs,
+                           const T *__restrict__ ys, const T *__restrict__ zs,
+                           const T *__restrict__ ms, const int32_t *__restrict__ order,
+                           const int32_t *__restrict__ pleaf, const int32_t *__restrict__ nparent,
+                           const double *__restrict__ M0, const double *__restrict__ com0,
+                           const double *__restrict__ M1, const double *__restrict__ com1,
+                           const double *__restrict__ nadj0, const double *__restrict__ nadj1,
+                           const double *__restrict__ tgt, const double *__restrict__ scat,
+                           const int32_t *__restrict__ sink_pos, int64_t n_sink,
+                           const double *__restrict__ ssb, double G, T *__restrict__ g_pos,
+                           T *__restrict__ g_mass, T *__restrict__ g_soft) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double x[3] = {(double)xs[s], (double)ys[s], (double)zs[s]};
+    const double m = (double)ms[s];
+    const int64_t o = order[s];
+    const bool gas = o < n_gas;
+    double g[5];
+    for (int d = 0; d < 5; ++d) g[d] = tgt[5 * s + d] + scat[5 * s + d];
+    for (int set = 0; set < 2; ++set) {
+        if (set == 1 && !gas) break;
+        const double *Ms = set ? M1 : M0;
+        const double *cs = set ? com1 : com0;
+        const double *ad = set ? nadj1 : nadj0;
+        for (int64_t nd = pleaf[s]; nd >= 0; nd = nparent[nd]) {
+            const double Mn = Ms[nd];
+            if (!(Mn > 0.0)) continue;
+            const double *a10 = ad + 10 * nd;
+            const double y0 = x[0] - cs[3 * nd], y1 = x[1] - cs[3 * nd + 1], y2 = x[2] - cs[3 * nd + 2];
+            const double gxx = a10[4], gyy = a10[5], gzz = a10[6], gxy = a10[7], gxz = a10[8],
+                         gyz = a10[9];
+            const double tr = gxx + gyy + gzz;
+            const double Gy0 = gxx * y0 + gxy * y1 + gxz * y2;
+            const double Gy1 = gxy * y0 + gyy * y1 + gyz * y2;
+            const double Gy2 = gxz * y0 + gyz * y1 + gzz * y2;
+            const double w = m / Mn;
+            g[0] += w * a10[1] + m * (6.0 * Gy0 - 2.0 * tr * y0);
+            g[1] += w * a10[2] + m * (6.0 * Gy1 - 2.0 * tr * y1);
+            g[2] += w * a10[3] + m * (6.0 * Gy2 - 2.0 * tr * y2);
+            g[3] += a10[0] + (a10[1] * y0 + a10[2] * y1 + a10[3] * y2) / Mn +
+                    3.0 * (y0 * Gy0 + y1 * Gy1 + y2 * Gy2) - (y0 * y0 + y1 * y1 + y2 * y2) * tr;
+        }
+    }
+    if (!gas && ssb) {
+        int64_t lo = 0, hi = n_sink;   // rank of s among the sorted sink positions
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sink_pos[mid] < s) lo = mid + 1; else hi = mid;
+        }
+        for (int d = 0; d < 5; ++d) g[d] += ssb[5 * lo + d];
+    }
+    if (g_pos) {
+        g_pos[3 * o] = (T)(G * g[0]);
+        g_pos[3 * o + 1] = (T)(G * g[1]);
+        g_pos[3 * o + 2] = (T)(G * g[2]);
+    }
+    if (g_mass) g_mass[o] = (T)(G * g[3]);
+    if (g_soft) g_soft[o] = (T)(G * g[4]);
+}
+
+template <typename T>
+static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, const void *g_acc,
+                                const void *g_pot, double *tgt, double *scat, double *nadj,
+                                int32_t *ctr) {
+    WalkArgsB<T> a{};
+    a.nd.n_nodes = t->n_nodes;
+    a.nd.nlevel = t->nlevel;
+    a.nd.nfirst = t->nfirst;
+    a.nd.ncount = t->ncount;
+    a.nd.nchild = t->nchild;
+    a.nd.nnchild = t->nnchild;
+    a.nd.clo = t->clo;
+    a.nd.chi = t->chi;
+    a.nd.M = t->M[set];
+    a.nd.com = t->com[set];
+    a.nd.Q = t->Q[set];
+    a.nd.hmax = t->hmax[set];
+    a.nd.side = t->hframe.side;
+    a.nd.th2 = o.theta * o.theta;
+    a.xs = (const T *)t->xs;
+    a.ys = (const T *)t->ys;
+    a.zs = (const T *)t->zs;
+    a.ms = (const T *)t->ms;
+    a.hs = (const T *)t->hs;
+    a.order = t->order;
+    a.n = t->n;
+    a.n_gas = t->n_gas;
+    a.n_groups_dev = t->n_groups_dev;
+    a.gfirst = t->gfirst;
+    a.gcount = t->gcount;
+    a.gbox = t->gbox;
+    a.ghmax = t->ghmax;
+    a.gcen = t->gcen;
+    a.sink_pos = t->sink_pos;
+    a.n_sink = t->n_sink;
+    a.g_acc = (const T *)g_acc;
+    a.g_pot = (const T *)g_pot;
+    a.tgt = tgt;
+    a.scat = scat;
+    a.nadj = nadj;
+    a.task_ctr = ctr;
+    a.err = ctr + 2;
+    return a;
+}
+
+template <typename T, int FORM, int ORDER>
+static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
+                           const void *g_pot, double *tgt, double *scat, double *nadj0,
+                           double *nadj1, int32_t *ctr) {
+    const unsigned grid = (unsigned)(device_cu_count() * 16);
+    WalkArgsB<T> ag = make_args_b<T>(t, o, 0, g_acc, g_pot, tgt, scat, nadj0, ctr);
+    phase_begin(t, 8);
+    hipLaunchKernelGGL((k_walk_groups_b<T, FORM, ORDER>), dim3(grid), dim3(64), 0, t->stream, ag);
+    phase_end(t, 8);
+    if (t->n_sink > 0) {
+        WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + 1);
+        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
+        phase_begin(t, 9);
+        hipLaunchKernelGGL((k_walk_sinks_b<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
+        phase_end(t, 9);
+    }
+}
+
+template <typename T>
+static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
+                                 const void *g_pot, void *g_pos, void *g_mass, void *g_soft,
+                                 DevArena &ar) {
+    hipStream_t s = t->stream;
+    const int64_t n = t->n, nn = t->n_nodes;
+    int32_t *ctr;
+    double *tgt, *scat, *nadj0, *nadj1, *ssb = nullptr;
+    SF_ALLOC_TMP(ar, ctr, 4);
+    SF_ALLOC_TMP(ar, tgt, 5 * n);
+    SF_ALLOC_TMP(ar, scat, 5 * n);
+    SF_ALLOC_TMP(ar, nadj0, 10 * nn);
+    SF_ALLOC_TMP(ar, nadj1, 10 * nn);
+    fill_u32((uint32_t *)ctr, 4, 0u, s);
+    fill_u32((uint32_t *)tgt, 10 * n, 0u, s);
+    fill_u32((uint32_t *)scat, 10 * n, 0u, s);
+    fill_u32((uint32_t *)nadj0, 20 * nn, 0u, s);
+    fill_u32((uint32_t *)nadj1, 20 * nn, 0u, s);
+    if (t->n_sink > 0) {
+        SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
+        phase_begin(t, 7);
+        sink_sink_backward<T>(t, g_acc, g_pot, ssb);
+        phase_end(t, 7);
+    }
+#define SF_WB(F, O) launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr)
+    if (o.order == 0) {
+        if (o.form == SF_FP32C) SF_WB(SF_FP32C, 0);
+        else if (o.form == SF_FP32) SF_WB(SF_FP32, 0);
+        else SF_WB(SF_FP64, 0);
+    } else {
+        if (o.form == SF_FP32C) SF_WB(SF_FP32C, 2);
+        else if (o.form == SF_FP32) SF_WB(SF_FP32, 2);
+        else SF_WB(SF_FP64, 2);
+    }
+#undef SF_WB
+    phase_begin(t, 10);
+    hipLaunchKernelGGL(k_pushdown<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       t->n_gas, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
+                       (const T *)t->ms, t->order, t->pleaf, t->nparent, t->M[0], t->com[0],
+                       t->M[1], t->com[1], nadj0, nadj1, tgt, scat, t->sink_pos, t->n_sink, ssb,
+                       o.G, (T *)g_pos, (T *)g_mass, (T *)g_soft);
+    phase_end(t, 10);
+    SF_HIP(hipGetLastError());
+    int32_t herr = 0;
+    SF_HIP(hipMemcpyAsync(&herr, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipStreamSynchronize(s));
+    if (herr)
+        return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);
+    return SF_OK;
+}
+
 sf_status tree_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
                         const void *g_pot, void *g_pos, void *g_mass, void *g_soft,
                         DevArena &ar) {
-    (void)t; (void)o; (void)g_acc; (void)g_pot; (void)g_pos; (void)g_mass; (void)g_soft; (void)ar;
-    return sf_fail(SF_E_UNSUPPORTED, "tree adjoint not available yet");
+    if (t->dt == SF_F32)
+        return tree_backward_t<float>(t, o, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
+    return tree_backward_t<double>(t, o, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
 }
 
 }  // namespace sf

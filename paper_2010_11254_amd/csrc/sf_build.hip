@@ -462,7 +462,8 @@ __global__ void k_moments(int64_t n_nodes, const int32_t *__restrict__ nfirst,
                           const T *__restrict__ xs, const T *__restrict__ ys,
                           const T *__restrict__ zs, const T *__restrict__ ms,
                           const T *__restrict__ hs, const int32_t *__restrict__ order,
-                          int64_t n_gas, double *raw0, double *raw1, uint32_t *arrive) {
+                          int64_t n_gas, double *raw0, double *raw1, uint32_t *arrive,
+                          int32_t *__restrict__ pleaf) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes || nnchild[k] != 0) return;
     double g[3];
@@ -472,6 +473,7 @@ __global__ void k_moments(int64_t n_nodes, const int32_t *__restrict__ nfirst,
     raw_zero(rg);
     const int64_t f = nfirst[k], c = ncount[k];
     for (int64_t p = f; p < f + c; ++p) {
+        pleaf[p] = (int32_t)k;
         const double m = (double)ms[p], h = (double)hs[p];
         const double y0 = (double)xs[p] - g[0], y1 = (double)ys[p] - g[1], y2 = (double)zs[p] - g[2];
         raw_add_point(ra, m, y0, y1, y2, h);
@@ -551,6 +553,7 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
     SF_ALLOC_TMP(ar, raw0, 11 * nn);
     SF_ALLOC_TMP(ar, raw1, 11 * nn);
     SF_ALLOC_TMP(ar, arrive, nn);
+    SF_ALLOC(ar, t->pleaf, t->n);
     fill_u32(arrive, nn, 0u, s);
     for (int set = 0; set < 2; ++set) {
         SF_ALLOC(ar, t->M[set], nn);
@@ -563,13 +566,13 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
                            t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
                            (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
                            (const float *)t->ms, (const float *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, arrive);
+                           raw1, arrive, t->pleaf);
     else
         hipLaunchKernelGGL(k_moments<double>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, t->nfirst,
                            t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
                            (const double *)t->xs, (const double *)t->ys, (const double *)t->zs,
                            (const double *)t->ms, (const double *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, arrive);
+                           raw1, arrive, t->pleaf);
     double *raws[2] = {raw0, raw1};
     for (int set = 0; set < 2; ++set)
         hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,

@@ -130,6 +130,7 @@ struct sf_grav_tree_s {
     int32_t *nlevel = nullptr, *nfirst = nullptr, *ncount = nullptr, *nparent = nullptr;
     int32_t *nchild = nullptr, *nnchild = nullptr;
     double *clo = nullptr, *chi = nullptr;            // cube corners, 3 per node
+    int32_t *pleaf = nullptr;                         // leaf node of each sorted particle
     // moments, set 0 = all particles, set 1 = gas only
     double *M[2] = {nullptr, nullptr};
     double *com[2] = {nullptr, nullptr};              // 3 per node

@@ -24,80 +24,9 @@
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_walk.h"
 
 namespace sf {
-
-constexpr int kStack = 22 * 64 + 64;
-
-struct WalkNodes {
-    int64_t n_nodes;
-    const int32_t *nlevel, *nfirst, *ncount, *nchild, *nnchild;
-    const double *clo, *chi;
-    const double *M, *com, *Q, *hmax;   // the moment set used by this walk
-    double side;                         // root cube side (cell = side 2^-level)
-    double th2;                          // theta^2
-};
-
-struct WalkLds {
-    uint32_t stack[kStack];
-    int32_t pc[128];
-    int32_t ppf[128];
-    int32_t ppc[128];
-    int32_t slot[64];
-};
-
-template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h; int32_t idx, pad0, pad1, pad2; };
-template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz, pad0, pad1, pad2; };
-
-// Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
-template <typename R>
-__device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R ti2, R ti, bool self,
-                                     R &bx, R &by, R &bz, R &bp) {
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    const R ri = rsq(r2);
-    R P = ri;
-    R F = ri * ri * ri;
-    const R hh2 = hj2 > ti2 ? hj2 : ti2;
-    if (r2 < hh2) {
-        soft_FP<R>(r2, hj > ti ? hj : ti, F, P);
-        if (self) { F = R(0); P = R(0); }
-    }
-    const R mF = m * F;
-    bx += mF * dx;
-    by += mF * dy;
-    bz += mF * dz;
-    bp -= m * P;
-}
-
-// Multipole term: r = target - centre of mass.
-template <typename R, int ORDER>
-__device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz, R qyz,
-                                          R &bx, R &by, R &bz, R &bp) {
-    const R r2 = rx * rx + ry * ry + rz * rz;
-    const R ri = rsq(r2);
-    const R ri2 = ri * ri;
-    const R Mri = M * ri;
-    if (ORDER == 0) {
-        const R c = -Mri * ri2;
-        bx += c * rx;
-        by += c * ry;
-        bz += c * rz;
-        bp -= Mri;
-    } else {
-        const R qzz = -(qxx + qyy);
-        const R qx = qxx * rx + qxy * ry + qxz * rz;
-        const R qy = qxy * rx + qyy * ry + qyz * rz;
-        const R qz = qxz * rx + qyz * ry + qzz * rz;
-        const R rqr = qx * rx + qy * ry + qz * rz;
-        const R ri5 = ri2 * ri2 * ri;
-        const R t = R(0.5) * rqr * ri5;
-        bp -= Mri + t;
-        const R c = -(Mri + R(5) * t) * ri2;
-        bx += c * rx + ri5 * qx;
-        by += c * ry + ri5 * qy;
-        bz += c * rz + ri5 * qz;
-    }
-}
 
 // ---------------------------------------------------------------- common args
 
@@ -120,192 +49,6 @@ struct WalkArgs {
     T *acc, *pot;
     double G;
 };
-
-// ---------------------------------------------------------------- walk core
-
-// Test one node against the task box; returns 0 skip, 1 accept, 2 open leaf,
-// 3 open inner.  All FP64 steps are separately rounded (no contraction).
-__device__ __forceinline__ int classify(const WalkNodes &nd, int node, const double blo[3],
-                                        const double bhi[3], double hg, int64_t gf, int64_t gl) {
-    const double M = nd.M[node];
-    if (!(M > 0.0)) return 0;
-    const int64_t f = nd.nfirst[node], c = nd.ncount[node];
-    bool open = (f < gl) && (gf < f + c);
-    double lo[3], hi[3], cm[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = nd.clo[3 * node + d];
-        hi[d] = nd.chi[3 * node + d];
-        cm[d] = nd.com[3 * node + d];
-    }
-    const bool meets = lo[0] <= bhi[0] && blo[0] <= hi[0] && lo[1] <= bhi[1] && blo[1] <= hi[1] &&
-                       lo[2] <= bhi[2] && blo[2] <= hi[2];
-    double g[3], e[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        g[d] = fmax(fmax(dsub(lo[d], bhi[d]), dsub(blo[d], hi[d])), 0.0);
-        e[d] = fmax(fmax(dsub(blo[d], cm[d]), dsub(cm[d], bhi[d])), 0.0);
-    }
-    const double dbb2 = dadd(dadd(dmul(g[0], g[0]), dmul(g[1], g[1])), dmul(g[2], g[2]));
-    const double hm = fmax(nd.hmax[node], hg);
-    const bool soft = dbb2 < dmul(hm, hm);
-    const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
-    const double L = ldexp(nd.side, -nd.nlevel[node]);
-    const bool angle = dmul(L, L) > dmul(nd.th2, r2);
-    open = open || meets || soft || angle;
-    if (!open) return 1;
-    return nd.nnchild[node] == 0 ? 2 : 3;
-}
-
-// Next task index for the whole wave, as a scalar (SGPR) value: lane 0 takes
-// it from the counter and readfirstlane broadcasts it.  Keeping every loop
-// bound of the walk in scalar registers makes all loop exits scalar
-// branches; a task index broadcast through a vector register let the
-// compiler structure the task loop as a divergent loop.
-__device__ __forceinline__ int next_task(int32_t *ctr) {
-    int g = 0;
-    if ((threadIdx.x & 63) == 0) g = atomicAdd(ctr, 1);
-    return __builtin_amdgcn_readfirstlane(g);
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
-}
-
-// Walk one task.  Ev supplies pc_batch(L, head, nb) and pp_batch(L, nb).
-template <class Ev>
-__device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double blo[3],
-                          const double bhi[3], double hg, int64_t gf, int64_t gl, int32_t *err,
-                          uint32_t &n_pc, uint32_t &n_pp) {
-    const int lane = threadIdx.x;
-    const uint64_t lt = lane_mask_lt();
-    uint32_t sp = 1;
-    if (lane == 0) L.stack[0] = 1u;   // root (node 0), one node
-    uint32_t pc_h = 0, pc_t = 0, pp_h = 0, pp_t = 0, pp_pend = 0;
-    n_pc = 0;
-    n_pp = 0;
-    __syncthreads();
-    // Every node is popped at most once per task, so a task takes at most
-    // n_nodes steps; the bound makes termination unconditional.
-    int64_t steps = 0;
-    while (sp > 0) {
-        if (++steps > nd.n_nodes + 1) {
-            if (lane == 0) atomicOr(err, 2);
-            break;
-        }
-        // pop whole entries from the top, at most 64 nodes
-        const int ei = (int)sp - 1 - lane;
-        const uint32_t ent = ei >= 0 ? L.stack[ei] : 0u;
-        const uint32_t cnt = ent & 15u;
-        const uint32_t incl = wave_scan_incl(cnt);
-        const bool take = ei >= 0 && incl <= 64u;
-        const uint32_t ntake = (uint32_t)popc64(__ballot(take));
-        const uint32_t nnodes = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ntake - 1);
-        if (take)
-            for (uint32_t o = 0; o < cnt; ++o) L.slot[incl - cnt + o] = (int32_t)((ent >> 4) + o);
-        sp -= ntake;
-        __syncthreads();
-        const int node = lane < (int)nnodes ? L.slot[lane] : -1;
-        int cls = 0;
-        if (node >= 0) cls = classify(nd, node, blo, bhi, hg, gf, gl);
-        const uint64_t macc = __ballot(cls == 1), mleaf = __ballot(cls == 2), mint = __ballot(cls == 3);
-        if (cls == 1) L.pc[(pc_t + popc64(macc & lt)) & 127] = node;
-        pc_t += (uint32_t)popc64(macc);
-        uint32_t lc = 0;
-        if (cls == 2) {
-            const uint32_t q = (pp_t + popc64(mleaf & lt)) & 127;
-            lc = (uint32_t)nd.ncount[node];
-            L.ppf[q] = nd.nfirst[node];
-            L.ppc[q] = (int32_t)lc;
-        }
-        pp_t += (uint32_t)popc64(mleaf);
-        pp_pend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lc));
-        const uint32_t npush = (uint32_t)popc64(mint);
-        if (sp + npush > (uint32_t)kStack) {   // cannot happen (see header); stop safely
-            if (lane == 0) atomicOr(err, 1);
-            break;
-        }
-        if (cls == 3) {
-            const uint32_t r = (uint32_t)popc64(mint & lt);
-            L.stack[sp + npush - 1 - r] =
-                ((uint32_t)nd.nchild[node] << 4) | (uint32_t)nd.nnchild[node];
-        }
-        sp += npush;
-        __syncthreads();
-        while (pc_t - pc_h >= 64u) {
-            ev.pc_batch(L, pc_h, 64);
-            pc_h += 64;
-            n_pc += 64;
-        }
-        while (pp_pend >= 64u) {
-            // gather 64 particle indices from the front ranges
-            uint32_t k = 0;
-            int guard = 0;
-            while (k < 64u) {
-                if (++guard > 130 || pp_h == pp_t) {   // ring holds <= 128 ranges
-                    if (lane == 0) atomicOr(err, 4);
-                    break;
-                }
-                const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
-                const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
-                const uint32_t tk = (uint32_t)c < 64u - k ? (uint32_t)c : 64u - k;
-                if ((uint32_t)lane < tk) L.slot[k + lane] = f + lane;
-                k += tk;
-                __syncthreads();
-                if (tk < (uint32_t)c) {
-                    if (lane == 0) {
-                        L.ppf[pp_h & 127] = f + (int32_t)tk;
-                        L.ppc[pp_h & 127] = c - (int32_t)tk;
-                    }
-                } else {
-                    ++pp_h;
-                }
-                __syncthreads();
-            }
-            if (k < 64u) {
-                pp_pend = 0;
-                break;
-            }
-            ev.pp_batch(L, 64);
-            pp_pend -= 64;
-            n_pp += 64;
-        }
-    }
-    if (pc_t > pc_h) {
-        ev.pc_batch(L, pc_h, pc_t - pc_h);
-        n_pc += pc_t - pc_h;
-    }
-    if (pp_pend > 0) {
-        uint32_t k = 0;
-        while (pp_h != pp_t) {
-            const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
-            const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
-            if (c < 1 || k + (uint32_t)c > 64u) {   // fewer than 64 particles remain
-                if (lane == 0) atomicOr(err, 8);
-                break;
-            }
-            if ((int32_t)lane < c) L.slot[k + lane] = f + lane;
-            k += (uint32_t)c;
-            ++pp_h;
-        }
-        __syncthreads();
-        ev.pp_batch(L, k);
-        n_pp += k;
-    }
-    __syncthreads();
-}
 
 // ---------------------------------------------------------------- group mode
 
