@@ -329,7 +329,7 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
 
 // Pair (target i, source j), d = x_j - x_i: S = dT/dx_j (target gets -S),
 // Tm = dT/dm_j, Th = dT/dh_ij, share_i = part of Th owned by the target.
-template <typename R>
+template <typename R, bool SOFT = true>
 __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2, R hi, R gax,
                                       R gay, R gaz, R gp, bool self, R &Sx, R &Sy, R &Sz, R &Tm,
                                       R &Th, R &share_i) {
@@ -338,7 +338,7 @@ __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2
     const R ri2 = ri * ri;
     R F = ri * ri2, P = ri, FrR = R(-3) * F * ri2, dFh = R(0), dPh = R(0);
     const R hh2 = hj2 > hi2 ? hj2 : hi2;
-    const bool soft = r2 < hh2;
+    const bool soft = SOFT && r2 < hh2;
     if (soft) {
         dsoft<R>(r2, hj > hi ? hj : hi, F, P, FrR, dFh, dPh);
         if (self) { F = R(0); P = R(0); FrR = R(0); dFh = R(0); dPh = R(0); }
@@ -500,6 +500,7 @@ struct GroupEvalB {
         __syncthreads();
     }
 
+    template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const int lane = threadIdx.x;
         PPStage<R> sj;
@@ -520,8 +521,8 @@ struct GroupEvalB {
         for (uint32_t j = 0; j < nb; ++j) {
             const PPStage<R> s = spp[j];
             R Sx, Sy, Sz, Tm, Th, sh;
-            bpair<R>(s.x - me.x, s.y - me.y, s.z - me.z, s.m, s.h2, s.h, me.h2, me.h, me.gx, me.gy,
-                     me.gz, me.gp, s.idx == me.idx, Sx, Sy, Sz, Tm, Th, sh);
+            bpair<R, SOFT>(s.x - me.x, s.y - me.y, s.z - me.z, s.m, s.h2, s.h, me.h2, me.h, me.gx,
+                           me.gy, me.gz, me.gp, s.idx == me.idx, Sx, Sy, Sz, Tm, Th, sh);
             bx -= Sx;
             by -= Sy;
             bz -= Sz;
@@ -537,8 +538,8 @@ struct GroupEvalB {
                 const TStage<R> q = st[t];
                 if (!q.act) continue;
                 R Sx, Sy, Sz, Tm, Th, sh;
-                bpair<R>(sj.x - q.x, sj.y - q.y, sj.z - q.z, sj.m, sj.h2, sj.h, q.h2, q.h, q.gx,
-                         q.gy, q.gz, q.gp, p == q.idx, Sx, Sy, Sz, Tm, Th, sh);
+                bpair<R, SOFT>(sj.x - q.x, sj.y - q.y, sj.z - q.z, sj.m, sj.h2, sj.h, q.h2, q.h,
+                               q.gx, q.gy, q.gz, q.gp, p == q.idx, Sx, Sy, Sz, Tm, Th, sh);
                 sx += Sx;
                 sy += Sy;
                 sz += Sz;
@@ -664,6 +665,7 @@ struct SinkEvalB {
         oz.fold(bz);
     }
 
+    template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const int lane = threadIdx.x;
         R bx = 0, by = 0, bz = 0, bh = 0;
@@ -678,8 +680,8 @@ struct SinkEvalB {
                 const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
                 const R h = (R)a->hs[p];
                 R Sx, Sy, Sz, Tm, Th, sh;
-                bpair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, gx, gy, gz, gp,
-                         p == tidx, Sx, Sy, Sz, Tm, Th, sh);
+                bpair<R, SOFT>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, gx, gy,
+                               gz, gp, p == tidx, Sx, Sy, Sz, Tm, Th, sh);
                 bx = -Sx;
                 by = -Sy;
                 bz = -Sz;

@@ -6,7 +6,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
+#include <vector>
 
 #include "sf_build.h"
 #include "sf_prims.h"
@@ -25,35 +29,132 @@ sf_status sf_fail(sf_status st, const char *fmt, ...) {
 
 namespace sf {
 
+// Device memory cache.  Every build and call allocates and frees a few
+// dozen arrays; the runtime's stream-ordered allocator costs tens of
+// microseconds per call, which adds up to milliseconds per force evaluation.
+// Freed blocks are kept here by (size class, device, stream) and handed out
+// again in stream order, so reuse on the same stream needs no
+// synchronisation.  Blocks of another stream are never reused.
+namespace {
+struct BlockKey {
+    size_t bytes;
+    int dev;
+    hipStream_t s;
+    bool operator<(const BlockKey &o) const {
+        if (bytes != o.bytes) return bytes < o.bytes;
+        if (dev != o.dev) return dev < o.dev;
+        return (uintptr_t)s < (uintptr_t)o.s;
+    }
+};
+struct LiveBlock {
+    size_t bytes;
+    int dev;
+};
+std::mutex g_mu;
+std::multimap<BlockKey, void *> g_free;
+std::unordered_map<void *, LiveBlock> g_live;
+size_t g_cached_bytes = 0;
+const size_t kCacheLimit = size_t(64) << 30;   // keep at most 64 GiB cached
+
+size_t size_class(size_t b) {
+    if (b < 256) return 256;
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+}  // namespace
+
+void cache_release(void *p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    const LiveBlock lb = it->second;
+    g_live.erase(it);
+    if (g_cached_bytes + lb.bytes > kCacheLimit) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    g_free.emplace(BlockKey{lb.bytes, lb.dev, s}, p);
+    g_cached_bytes += lb.bytes;
+}
+
 sf_status DevArena::alloc(void **p, size_t bytes, bool temp) {
     *p = nullptr;
-    if (bytes == 0) bytes = 16;
-    hipError_t e = hipMallocAsync(p, bytes, s);
-    if (e != hipSuccess || *p == nullptr) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return sf_fail(SF_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes,
-                       hipGetErrorString(e));
+    const size_t cls = size_class(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_free.find(BlockKey{cls, dev, s});
+        if (it != g_free.end()) {
+            *p = it->second;
+            g_free.erase(it);
+            g_cached_bytes -= cls;
+            g_live[*p] = LiveBlock{cls, dev};
+        }
+    }
+    if (!*p) {
+        hipError_t e = hipMallocAsync(p, cls, s);
+        if (e != hipSuccess || *p == nullptr) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return sf_fail(SF_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes,
+                           hipGetErrorString(e));
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live[*p] = LiveBlock{cls, dev};
     }
     (temp ? tmp : keep).push_back(*p);
     return SF_OK;
 }
 
 void DevArena::free_tmp() {
-    for (void *p : tmp) hipFreeAsync(p, s);
+    for (void *p : tmp) cache_release(p, s);
     tmp.clear();
 }
 
 void DevArena::free_keep() {
-    for (void *p : keep) hipFreeAsync(p, s);
+    for (void *p : keep) cache_release(p, s);
     keep.clear();
+}
+
+// hipEvents for the phase timers, reused across handles.
+static std::mutex g_ev_mu;
+static std::vector<hipEvent_t> g_events;
+
+static hipEvent_t event_get() {
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        if (!g_events.empty()) {
+            hipEvent_t e = g_events.back();
+            g_events.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void event_put(hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    g_events.push_back(e);
 }
 
 void phase_begin(sf_grav_tree_s *t, int ph) {
     if (!t->timing) return;
     if (!t->ev0[ph]) {
-        if (hipEventCreate(&t->ev0[ph]) != hipSuccess || hipEventCreate(&t->ev1[ph]) != hipSuccess) {
-            t->ev0[ph] = nullptr;
+        t->ev0[ph] = event_get();
+        t->ev1[ph] = event_get();
+        if (!t->ev0[ph] || !t->ev1[ph]) {
+            event_put(t->ev0[ph]);
+            event_put(t->ev1[ph]);
+            t->ev0[ph] = t->ev1[ph] = nullptr;
             return;
         }
     }
@@ -112,11 +213,11 @@ static sf_status check_arrays(const void *pos, const void *mass, const void *sof
 static void free_handle_memory(sf_grav_tree_s *t) {
     if (!t) return;
     (void)hipStreamSynchronize(t->stream);
-    for (void *p : t->allocs) (void)hipFree(p);
+    for (void *p : t->allocs) sf::cache_release(p, t->stream);
     t->allocs.clear();
     for (int p = 0; p < sf_grav_tree_s::kPhases; ++p) {
-        if (t->ev0[p]) (void)hipEventDestroy(t->ev0[p]);
-        if (t->ev1[p]) (void)hipEventDestroy(t->ev1[p]);
+        sf::event_put(t->ev0[p]);
+        sf::event_put(t->ev1[p]);
         t->ev0[p] = t->ev1[p] = nullptr;
     }
 }
@@ -206,10 +307,13 @@ sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft
         DevArena ar(t->stream);
         st = build_all(t, pos, mass, soft, o, ar);
         if (st != SF_OK) {
-            hipStreamSynchronize(t->stream);
+            (void)hipStreamSynchronize(t->stream);
             ar.free_keep();
             ar.free_tmp();
-            hipStreamSynchronize(t->stream);
+            for (int p = 0; p < sf_grav_tree_s::kPhases; ++p) {
+                sf::event_put(t->ev0[p]);
+                sf::event_put(t->ev1[p]);
+            }
             delete t;
             return st;
         }

@@ -18,10 +18,13 @@ struct DevArena {
     std::vector<void *> keep, tmp;
     explicit DevArena(hipStream_t st) : s(st) {}
     ~DevArena() { free_tmp(); }
-    sf_status alloc(void **p, size_t bytes, bool temp);
+    sf_status alloc(void **p, size_t bytes, bool temp);   // cached, stream ordered
     void free_tmp();
     void free_keep();
 };
+
+// Return a block from DevArena::alloc to the library's cache (stream ordered).
+void cache_release(void *p, hipStream_t s);
 
 }  // namespace sf
 

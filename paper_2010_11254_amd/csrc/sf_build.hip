@@ -69,20 +69,32 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const T *__restrict__ pos,
 
 // Root cube: lo = per-axis minimum; side = largest extent (1 if zero);
 // scale = 2^21 / side (correctly rounded FP64 division).
-__global__ void k_bbox_final(const double *__restrict__ part, int nblocks, Frame *frame) {
-    if (threadIdx.x != 0) return;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nblocks; ++b)
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nblocks,
+                                                    Frame *frame) {
+    __shared__ double sh[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
         for (int d = 0; d < 3; ++d) {
-            lo[d] = fmin(lo[d], part[b * 6 + d]);
-            hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+            v[d] = fmin(v[d], part[b * 6 + d]);
+            v[3 + d] = fmax(v[3 + d], part[b * 6 + 3 + d]);
         }
+    for (int d = 0; d < 6; ++d) sh[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + w]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     double side = 0.0;
     for (int d = 0; d < 3; ++d) {
-        double e = dsub(hi[d], lo[d]);
+        const double e = dsub(sh[3 + d][0], sh[d][0]);
         side = e > side ? e : side;
-        frame->lo[d] = lo[d];
-        frame->hi[d] = hi[d];
+        frame->lo[d] = sh[d][0];
+        frame->hi[d] = sh[3 + d][0];
     }
     if (side == 0.0) side = 1.0;
     frame->side = side;
@@ -157,7 +169,7 @@ static sf_status sort_stage(const void *pos, const void *mass, const void *soft,
     int bb = (int)std::min<int64_t>(kBoxBlocks, (n + 255) / 256);
     hipLaunchKernelGGL(k_bbox_partial<T>, dim3(bb), dim3(256), 0, s, (const T *)pos,
                        (const T *)mass, (const T *)soft, n, validate ? 1 : 0, part, t->frame);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, bb, t->frame);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, bb, t->frame);
 
     uint64_t *ktmp = nullptr;
     uint32_t *vtmp = nullptr, *scr = nullptr;
@@ -357,10 +369,11 @@ sf_status build_topology(sf_grav_tree_s *t, DevArena &ar) {
                        levhist);
     scan_u32(nn, dfs, n, scr, misc + 304, s);
     hipLaunchKernelGGL(k_topo_levoff, dim3(1), dim3(64), 0, s, levhist, misc + 24, misc + 48);
-    uint32_t total = 0;
-    SF_HIP(hipMemcpyAsync(&total, misc + 304, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    uint32_t hmisc[24 + 23];
+    SF_HIP(hipMemcpyAsync(hmisc, misc + 24, 23 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SF_HIP(hipStreamSynchronize(s));
-    const int64_t nn_total = total;
+    const int64_t nn_total = hmisc[kLevels + 1];
+    for (int l = 0; l <= kLevels + 1; ++l) t->level_off[l] = hmisc[l];
     t->n_nodes = nn_total;
     uint64_t *pdfs, *pbfs;
     SF_ALLOC_TMP(ar, pdfs, nn_total);
@@ -454,16 +467,18 @@ __device__ __forceinline__ void centre(const double *clo, const double *chi, int
     for (int d = 0; d < 3; ++d) g[d] = 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
 }
 
+// Leaves: sums over their particles about the cube centre (and each
+// particle's leaf index, used by the adjoint).
 template <typename T>
-__global__ void k_moments(int64_t n_nodes, const int32_t *__restrict__ nfirst,
-                          const int32_t *__restrict__ ncount, const int32_t *__restrict__ nparent,
-                          const int32_t *__restrict__ nchild, const int32_t *__restrict__ nnchild,
-                          const double *__restrict__ clo, const double *__restrict__ chi,
-                          const T *__restrict__ xs, const T *__restrict__ ys,
-                          const T *__restrict__ zs, const T *__restrict__ ms,
-                          const T *__restrict__ hs, const int32_t *__restrict__ order,
-                          int64_t n_gas, double *raw0, double *raw1, uint32_t *arrive,
-                          int32_t *__restrict__ pleaf) {
+__global__ void k_moments_leaf(int64_t n_nodes, const int32_t *__restrict__ nfirst,
+                               const int32_t *__restrict__ ncount,
+                               const int32_t *__restrict__ nnchild, const double *__restrict__ clo,
+                               const double *__restrict__ chi, const T *__restrict__ xs,
+                               const T *__restrict__ ys, const T *__restrict__ zs,
+                               const T *__restrict__ ms, const T *__restrict__ hs,
+                               const int32_t *__restrict__ order, int64_t n_gas,
+                               double *__restrict__ raw0, double *__restrict__ raw1,
+                               int32_t *__restrict__ pleaf) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes || nnchild[k] != 0) return;
     double g[3];
@@ -481,34 +496,41 @@ __global__ void k_moments(int64_t n_nodes, const int32_t *__restrict__ nfirst,
     }
     raw_store(raw0, k, ra);
     raw_store(raw1, k, rg);
-    // climb: the last child to arrive combines its parent from all children
-    int64_t cur = k;
-    while (true) {
-        const int64_t par = nparent[cur];
-        if (par < 0) break;
-        __threadfence();
-        const uint32_t old = atomicAdd(&arrive[par], 1u);
-        if ((int)old != nnchild[par] - 1) break;
-        __threadfence();
-        double gp[3];
-        centre(clo, chi, par, gp);
-        raw_zero(ra);
-        raw_zero(rg);
-        const int64_t c0 = nchild[par], c1 = c0 + nnchild[par];
-        for (int64_t ch = c0; ch < c1; ++ch) {
-            double gc[3], dl[3];
-            centre(clo, chi, ch, gc);
-            for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
-            RawMom cm;
-            raw_load_dev(raw0, ch, cm);
-            raw_add_child(ra, cm, dl);
-            raw_load_dev(raw1, ch, cm);
-            raw_add_child(rg, cm, dl);
-        }
-        raw_store(raw0, par, ra);
-        raw_store(raw1, par, rg);
-        cur = par;
+}
+
+__device__ __forceinline__ void raw_load(const double *raw, int64_t k, RawMom &r) {
+    const double *p = raw + 11 * k;
+    r.M = p[0];
+    for (int d = 0; d < 3; ++d) r.D[d] = p[1 + d];
+    for (int d = 0; d < 6; ++d) r.S[d] = p[4 + d];
+    r.h = p[10];
+}
+
+// Inner nodes of one level, from their children (one level down, final).
+__global__ void k_moments_level(int64_t k0, int64_t k1, const int32_t *__restrict__ nchild,
+                                const int32_t *__restrict__ nnchild,
+                                const double *__restrict__ clo, const double *__restrict__ chi,
+                                double *__restrict__ raw0, double *__restrict__ raw1) {
+    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k1 || nnchild[k] == 0) return;
+    double gp[3];
+    centre(clo, chi, k, gp);
+    RawMom ra, rg;
+    raw_zero(ra);
+    raw_zero(rg);
+    const int64_t c0 = nchild[k], c1 = c0 + nnchild[k];
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        double gc[3], dl[3];
+        centre(clo, chi, ch, gc);
+        for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
+        RawMom cm;
+        raw_load(raw0, ch, cm);
+        raw_add_child(ra, cm, dl);
+        raw_load(raw1, ch, cm);
+        raw_add_child(rg, cm, dl);
     }
+    raw_store(raw0, k, ra);
+    raw_store(raw1, k, rg);
 }
 
 // Final per-node moments: com = g + D/M, S_com = S - D D^T / M,
@@ -549,12 +571,9 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
     hipStream_t s = t->stream;
     const int64_t nn = t->n_nodes;
     double *raw0, *raw1;
-    uint32_t *arrive;
     SF_ALLOC_TMP(ar, raw0, 11 * nn);
     SF_ALLOC_TMP(ar, raw1, 11 * nn);
-    SF_ALLOC_TMP(ar, arrive, nn);
     SF_ALLOC(ar, t->pleaf, t->n);
-    fill_u32(arrive, nn, 0u, s);
     for (int set = 0; set < 2; ++set) {
         SF_ALLOC(ar, t->M[set], nn);
         SF_ALLOC(ar, t->com[set], 3 * nn);
@@ -562,17 +581,22 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
         SF_ALLOC(ar, t->hmax[set], nn);
     }
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_moments<float>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, t->nfirst,
-                           t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
-                           (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
-                           (const float *)t->ms, (const float *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, arrive, t->pleaf);
+        hipLaunchKernelGGL(k_moments_leaf<float>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
+                           t->ncount, t->nnchild, t->clo, t->chi, (const float *)t->xs,
+                           (const float *)t->ys, (const float *)t->zs, (const float *)t->ms,
+                           (const float *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
     else
-        hipLaunchKernelGGL(k_moments<double>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, t->nfirst,
-                           t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi,
-                           (const double *)t->xs, (const double *)t->ys, (const double *)t->zs,
-                           (const double *)t->ms, (const double *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, arrive, t->pleaf);
+        hipLaunchKernelGGL(k_moments_leaf<double>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
+                           t->ncount, t->nnchild, t->clo, t->chi, (const double *)t->xs,
+                           (const double *)t->ys, (const double *)t->zs, (const double *)t->ms,
+                           (const double *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
+    // inner nodes, deepest level first (level offsets are known on the host)
+    for (int l = kLevels - 1; l >= 0; --l) {
+        const int64_t k0 = t->level_off[l], k1 = t->level_off[l + 1];
+        if (k1 <= k0 || t->level_off[l + 2] == t->level_off[l + 1]) continue;   // no children below
+        hipLaunchKernelGGL(k_moments_level, dim3(nblk(k1 - k0)), dim3(256), 0, s, k0, k1, t->nchild,
+                           t->nnchild, t->clo, t->chi, raw0, raw1);
+    }
     double *raws[2] = {raw0, raw1};
     for (int set = 0; set < 2; ++set)
         hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,

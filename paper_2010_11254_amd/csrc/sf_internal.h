@@ -127,6 +127,7 @@ struct sf_grav_tree_s {
     // nodes (breadth-first)
     int64_t n_nodes = 0, n_leaves = 0;
     int max_level = 0;
+    int64_t level_off[24] = {};                       // first node of each level
     int32_t *nlevel = nullptr, *nfirst = nullptr, *ncount = nullptr, *nparent = nullptr;
     int32_t *nchild = nullptr, *nnchild = nullptr;
     double *clo = nullptr, *chi = nullptr;            // cube corners, 3 per node

@@ -16,11 +16,17 @@ struct WalkNodes {
     double th2;                          // theta^2
 };
 
+// Ring of opened-leaf particle ranges (first, count).
+struct PPRing {
+    int32_t f[128];
+    int32_t c[128];
+};
+
 struct WalkLds {
     uint32_t stack[kStack];
     int32_t pc[128];
-    int32_t ppf[128];
-    int32_t ppc[128];
+    PPRing near;   // leaves that may hold softened pairs (incl. the task's own)
+    PPRing far;    // leaves whose every pair with the task is Newtonian
     int32_t slot[64];
 };
 
@@ -45,6 +51,19 @@ __device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R ti2, 
     by += mF * dy;
     bz += mF * dz;
     bp -= m * P;
+}
+
+// Newtonian particle pair (no softening possible, not a self pair).
+template <typename R>
+__device__ __forceinline__ void pair_newton(R dx, R dy, R dz, R m, R &bx, R &by, R &bz, R &bp) {
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R ri = rsq(r2);
+    const R mri = m * ri;
+    const R mri3 = mri * ri * ri;
+    bp -= mri;
+    bx += mri3 * dx;
+    by += mri3 * dy;
+    bz += mri3 * dz;
 }
 
 // Multipole term: r = target - centre of mass.
@@ -79,8 +98,10 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
 
 // ---------------------------------------------------------------- walk core
 
-// Test one node against the task box; returns 0 skip, 1 accept, 2 open leaf,
-// 3 open inner.  All FP64 steps are separately rounded (no contraction).
+// Test one node against the task box; returns 0 skip, 1 accept, 2 open leaf
+// that may hold softened pairs, 3 open inner, 4 open leaf with only Newtonian
+// pairs (gap to the box at least the larger max softening).  All FP64 steps
+// are separately rounded (no contraction).
 __device__ __forceinline__ int classify(const WalkNodes &nd, int node, const double blo[3],
                                         const double bhi[3], double hg, int64_t gf, int64_t gl) {
     const double M = nd.M[node];
@@ -108,9 +129,10 @@ __device__ __forceinline__ int classify(const WalkNodes &nd, int node, const dou
     const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
     const double L = ldexp(nd.side, -nd.nlevel[node]);
     const bool angle = dmul(L, L) > dmul(nd.th2, r2);
-    open = open || meets || soft || angle;
-    if (!open) return 1;
-    return nd.nnchild[node] == 0 ? 2 : 3;
+    const bool opened = open || meets || soft || angle;
+    if (!opened) return 1;
+    if (nd.nnchild[node] != 0) return 3;
+    return (open || meets || soft) ? 2 : 4;
 }
 
 // Next task index for the whole wave, as a scalar (SGPR) value: lane 0 takes
@@ -140,7 +162,41 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
     return v;
 }
 
-// Walk one task.  Ev supplies pc_batch(L, head, nb) and pp_batch(L, nb).
+// Gather `want` particle indices from the front of a range ring into slot[].
+// Returns false (and flags err) if the ring runs dry, which the pending
+// counts rule out.
+__device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, int32_t *slot,
+                                            uint32_t want, int32_t *err) {
+    const int lane = threadIdx.x;
+    uint32_t k = 0;
+    int guard = 0;
+    while (k < want) {
+        if (++guard > 130 || h == t) {
+            if (lane == 0) atomicOr(err, 4);
+            return false;
+        }
+        const int32_t f = __builtin_amdgcn_readfirstlane(R.f[h & 127]);
+        const int32_t c = __builtin_amdgcn_readfirstlane(R.c[h & 127]);
+        const uint32_t tk = (uint32_t)c < want - k ? (uint32_t)c : want - k;
+        if ((uint32_t)lane < tk) slot[k + lane] = f + lane;
+        k += tk;
+        __syncthreads();
+        if (tk < (uint32_t)c) {
+            if (lane == 0) {
+                R.f[h & 127] = f + (int32_t)tk;
+                R.c[h & 127] = c - (int32_t)tk;
+            }
+        } else {
+            ++h;
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// Walk one task.  Ev supplies pc_batch(L, head, nb) and
+// pp_batch<SOFT>(L, nb) (SOFT = false: every pair is Newtonian and none is a
+// self pair).
 template <class Ev>
 __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double blo[3],
                           const double bhi[3], double hg, int64_t gf, int64_t gl, int32_t *err,
@@ -149,7 +205,9 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
     const uint64_t lt = lane_mask_lt();
     uint32_t sp = 1;
     if (lane == 0) L.stack[0] = 1u;   // root (node 0), one node
-    uint32_t pc_h = 0, pc_t = 0, pp_h = 0, pp_t = 0, pp_pend = 0;
+    uint32_t pc_h = 0, pc_t = 0;
+    uint32_t nh = 0, nt = 0, npend = 0;   // near ring
+    uint32_t fh = 0, ft = 0, fpend = 0;   // far ring
     n_pc = 0;
     n_pp = 0;
     __syncthreads();
@@ -176,18 +234,27 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
         const int node = lane < (int)nnodes ? L.slot[lane] : -1;
         int cls = 0;
         if (node >= 0) cls = classify(nd, node, blo, bhi, hg, gf, gl);
-        const uint64_t macc = __ballot(cls == 1), mleaf = __ballot(cls == 2), mint = __ballot(cls == 3);
+        const uint64_t macc = __ballot(cls == 1), mnear = __ballot(cls == 2),
+                       mint = __ballot(cls == 3), mfar = __ballot(cls == 4);
         if (cls == 1) L.pc[(pc_t + popc64(macc & lt)) & 127] = node;
         pc_t += (uint32_t)popc64(macc);
-        uint32_t lc = 0;
+        uint32_t lcn = 0, lcf = 0;
         if (cls == 2) {
-            const uint32_t q = (pp_t + popc64(mleaf & lt)) & 127;
-            lc = (uint32_t)nd.ncount[node];
-            L.ppf[q] = nd.nfirst[node];
-            L.ppc[q] = (int32_t)lc;
+            const uint32_t q = (nt + popc64(mnear & lt)) & 127;
+            lcn = (uint32_t)nd.ncount[node];
+            L.near.f[q] = nd.nfirst[node];
+            L.near.c[q] = (int32_t)lcn;
         }
-        pp_t += (uint32_t)popc64(mleaf);
-        pp_pend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lc));
+        if (cls == 4) {
+            const uint32_t q = (ft + popc64(mfar & lt)) & 127;
+            lcf = (uint32_t)nd.ncount[node];
+            L.far.f[q] = nd.nfirst[node];
+            L.far.c[q] = (int32_t)lcf;
+        }
+        nt += (uint32_t)popc64(mnear);
+        ft += (uint32_t)popc64(mfar);
+        npend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lcn));
+        fpend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lcf));
         const uint32_t npush = (uint32_t)popc64(mint);
         if (sp + npush > (uint32_t)kStack) {   // cannot happen (see header); stop safely
             if (lane == 0) atomicOr(err, 1);
@@ -205,37 +272,16 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
             pc_h += 64;
             n_pc += 64;
         }
-        while (pp_pend >= 64u) {
-            // gather 64 particle indices from the front ranges
-            uint32_t k = 0;
-            int guard = 0;
-            while (k < 64u) {
-                if (++guard > 130 || pp_h == pp_t) {   // ring holds <= 128 ranges
-                    if (lane == 0) atomicOr(err, 4);
-                    break;
-                }
-                const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
-                const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
-                const uint32_t tk = (uint32_t)c < 64u - k ? (uint32_t)c : 64u - k;
-                if ((uint32_t)lane < tk) L.slot[k + lane] = f + lane;
-                k += tk;
-                __syncthreads();
-                if (tk < (uint32_t)c) {
-                    if (lane == 0) {
-                        L.ppf[pp_h & 127] = f + (int32_t)tk;
-                        L.ppc[pp_h & 127] = c - (int32_t)tk;
-                    }
-                } else {
-                    ++pp_h;
-                }
-                __syncthreads();
-            }
-            if (k < 64u) {
-                pp_pend = 0;
-                break;
-            }
-            ev.pp_batch(L, 64);
-            pp_pend -= 64;
+        while (fpend >= 64u) {
+            if (!ring_gather(L.far, fh, ft, L.slot, 64, err)) { fpend = 0; break; }
+            ev.template pp_batch<false>(L, 64);
+            fpend -= 64;
+            n_pp += 64;
+        }
+        while (npend >= 64u) {
+            if (!ring_gather(L.near, nh, nt, L.slot, 64, err)) { npend = 0; break; }
+            ev.template pp_batch<true>(L, 64);
+            npend -= 64;
             n_pp += 64;
         }
     }
@@ -243,22 +289,17 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
         ev.pc_batch(L, pc_h, pc_t - pc_h);
         n_pc += pc_t - pc_h;
     }
-    if (pp_pend > 0) {
-        uint32_t k = 0;
-        while (pp_h != pp_t) {
-            const int32_t f = __builtin_amdgcn_readfirstlane(L.ppf[pp_h & 127]);
-            const int32_t c = __builtin_amdgcn_readfirstlane(L.ppc[pp_h & 127]);
-            if (c < 1 || k + (uint32_t)c > 64u) {   // fewer than 64 particles remain
-                if (lane == 0) atomicOr(err, 8);
-                break;
-            }
-            if ((int32_t)lane < c) L.slot[k + lane] = f + lane;
-            k += (uint32_t)c;
-            ++pp_h;
+    if (fpend > 0) {
+        if (ring_gather(L.far, fh, ft, L.slot, fpend, err)) {
+            ev.template pp_batch<false>(L, fpend);
+            n_pp += fpend;
         }
-        __syncthreads();
-        ev.pp_batch(L, k);
-        n_pp += k;
+    }
+    if (npend > 0) {
+        if (ring_gather(L.near, nh, nt, L.slot, npend, err)) {
+            ev.template pp_batch<true>(L, npend);
+            n_pp += npend;
+        }
     }
     __syncthreads();
 }

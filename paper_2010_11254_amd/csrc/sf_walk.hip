@@ -96,6 +96,7 @@ struct GroupEval {
         __syncthreads();
     }
 
+    template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const int lane = threadIdx.x;
         if ((uint32_t)lane < nb) {
@@ -114,8 +115,11 @@ struct GroupEval {
         R bx = 0, by = 0, bz = 0, bp = 0;
         for (uint32_t j = 0; j < nb; ++j) {
             const PPStage<R> s = spp[j];
-            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx, by,
-                    bz, bp);
+            if (SOFT)
+                pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx,
+                        by, bz, bp);
+            else
+                pair_newton<R>(s.x - tx, s.y - ty, s.z - tz, s.m, bx, by, bz, bp);
         }
         ax.fold(bx);
         ay.fold(by);
@@ -219,6 +223,7 @@ struct SinkEval {
         ap.fold(bp);
     }
 
+    template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const int lane = threadIdx.x;
         R bx = 0, by = 0, bz = 0, bp = 0;
@@ -232,8 +237,11 @@ struct SinkEval {
                 const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
                 const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
                 const R h = (R)a->hs[p];
-                pair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, p == tidx, bx,
-                        by, bz, bp);
+                if (SOFT)
+                    pair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, p == tidx,
+                            bx, by, bz, bp);
+                else
+                    pair_newton<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], bx, by, bz, bp);
             }
         }
         ax.fold(bx);
