@@ -49,6 +49,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--leaf-cap", type=int, default=16)
+    ap.add_argument("--group-cap", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -72,12 +76,19 @@ def main():
         f"generated in {time.time() - t0:.1f}s")
     dev = torch.device("cuda", 0)
     x, m, h = (torch.as_tensor(v).to(dev) for v in (ps.x, ps.m, ps.h))
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
     pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
 
     def opts(form, timing=False, stats=False):
-        return L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=16, group_cap=64,
-                           n_gas=ps.n_gas, timing=timing, collect_stats=stats)
+        return L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=args.leaf_cap,
+                           group_cap=args.group_cap, n_gas=ps.n_gas, timing=timing,
+                           collect_stats=stats)
 
     def step(o):
         t = L.sf_grav_build_tree(x, m, h, o)
@@ -178,7 +189,8 @@ def main():
         "config": {"workload": "precision4m: 4,194,304 clustered gas + 2048 sink binaries",
                    "n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "inputs": "fp32",
                    "path": "tree", "theta": args.theta, "order": "quadrupole",
-                   "form": "fp32c", "leaf_cap": 16, "group_cap": 64, "seed": 2},
+                   "form": "fp32c", "leaf_cap": args.leaf_cap, "group_cap": args.group_cap,
+                   "seed": 2},
         "roofline": {"bound": "alu", "kernel": "k_walk_groups", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,

@@ -444,17 +444,17 @@ struct GroupEvalB {
         if ((uint32_t)lane < nb) {
             node = L.pc[(head + lane) & 127];
             const WalkNodes &nd = a->nd;
-            sn.x = dto_frame<FORM>(nd.com[3 * node], cen[0]);
-            sn.y = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
-            sn.z = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
-            sn.M = (R)nd.M[node];
+            sn.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            sn.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            sn.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            sn.M = (R)nd.w[node].M;
             sn.qxx = sn.qyy = sn.qxy = sn.qxz = sn.qyz = R(0);
             if (ORDER == 2) {
-                sn.qxx = (R)nd.Q[6 * node];
-                sn.qyy = (R)nd.Q[6 * node + 1];
-                sn.qxy = (R)nd.Q[6 * node + 3];
-                sn.qxz = (R)nd.Q[6 * node + 4];
-                sn.qyz = (R)nd.Q[6 * node + 5];
+                sn.qxx = (R)nd.q[node].q[0];
+                sn.qyy = (R)nd.q[node].q[1];
+                sn.qxy = (R)nd.q[node].q[2];
+                sn.qxz = (R)nd.q[node].q[3];
+                sn.qyz = (R)nd.q[node].q[4];
             }
             spc[lane] = sn;
         }
@@ -632,22 +632,22 @@ struct SinkEvalB {
         if ((uint32_t)lane < nb) {
             const int node = L.pc[(head + lane) & 127];
             const WalkNodes &nd = a->nd;
-            const R cx = dto_frame<FORM>(nd.com[3 * node], cen[0]);
-            const R cy = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
-            const R cz = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            const R cx = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            const R cy = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            const R cz = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
             const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
             const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
             const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
             R qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
             if (ORDER == 2) {
-                qxx = (R)nd.Q[6 * node];
-                qyy = (R)nd.Q[6 * node + 1];
-                qxy = (R)nd.Q[6 * node + 3];
-                qxz = (R)nd.Q[6 * node + 4];
-                qyz = (R)nd.Q[6 * node + 5];
+                qxx = (R)nd.q[node].q[0];
+                qyy = (R)nd.q[node].q[1];
+                qxy = (R)nd.q[node].q[2];
+                qxz = (R)nd.q[node].q[3];
+                qyz = (R)nd.q[node].q[4];
             }
             R g0, g1, g2, gM, gs[6];
-            bmultipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.M[node], qxx, qyy, qxy, qxz, qyz,
+            bmultipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.w[node].M, qxx, qyy, qxy, qxz, qyz,
                                  gx, gy, gz, gp, g0, g1, g2, gM, gs);
             bx = g0;
             by = g1;
@@ -815,17 +815,8 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
                                 int32_t *ctr) {
     WalkArgsB<T> a{};
     a.nd.n_nodes = t->n_nodes;
-    a.nd.nlevel = t->nlevel;
-    a.nd.nfirst = t->nfirst;
-    a.nd.ncount = t->ncount;
-    a.nd.nchild = t->nchild;
-    a.nd.nnchild = t->nnchild;
-    a.nd.clo = t->clo;
-    a.nd.chi = t->chi;
-    a.nd.M = t->M[set];
-    a.nd.com = t->com[set];
-    a.nd.Q = t->Q[set];
-    a.nd.hmax = t->hmax[set];
+    a.nd.w = t->nw[set];
+    a.nd.q = t->nq[set];
     a.nd.side = t->hframe.side;
     a.nd.th2 = o.theta * o.theta;
     a.xs = (const T *)t->xs;

@@ -538,9 +538,34 @@ __global__ void k_moments_level(int64_t k0, int64_t k1, const int32_t *__restric
 __global__ void k_moments_final(int64_t n_nodes, const double *__restrict__ clo,
                                 const double *__restrict__ chi, const double *__restrict__ raw,
                                 double *__restrict__ M, double *__restrict__ com,
-                                double *__restrict__ Q, double *__restrict__ hmax) {
+                                double *__restrict__ Q, double *__restrict__ hmax,
+                                const int32_t *__restrict__ nfirst,
+                                const int32_t *__restrict__ ncount,
+                                const int32_t *__restrict__ nchild,
+                                const int32_t *__restrict__ nnchild,
+                                const int32_t *__restrict__ nlevel, NodeW *__restrict__ nw,
+                                NodeQ *__restrict__ nq) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_nodes) return;
+    {
+        NodeW w;
+        const double *pr = raw + 11 * k;
+        const double m = pr[0];
+        for (int d = 0; d < 3; ++d) {
+            w.clo[d] = clo[3 * k + d];
+            w.chi[d] = chi[3 * k + d];
+            w.com[d] = m > 0.0 ? 0.5 * (clo[3 * k + d] + chi[3 * k + d]) + pr[1 + d] / m
+                               : 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
+        }
+        w.hmax = pr[10];
+        w.M = m;
+        w.first = nfirst[k];
+        w.count = ncount[k];
+        w.child = nchild[k];
+        w.lvl_nch = (nlevel[k] << 8) | nnchild[k];
+        w.pad[0] = w.pad[1] = 0.0;
+        nw[k] = w;
+    }
     double g[3];
     centre(clo, chi, k, g);
     const double *p = raw + 11 * k;
@@ -565,6 +590,14 @@ __global__ void k_moments_final(int64_t n_nodes, const double *__restrict__ clo,
         for (int d = 0; d < 3; ++d) com[3 * k + d] = g[d];
         for (int d = 0; d < 6; ++d) Q[6 * k + d] = 0.0;
     }
+    NodeQ q;
+    q.q[0] = Q[6 * k];
+    q.q[1] = Q[6 * k + 1];
+    q.q[2] = Q[6 * k + 3];
+    q.q[3] = Q[6 * k + 4];
+    q.q[4] = Q[6 * k + 5];
+    q.pad = 0.0;
+    nq[k] = q;
 }
 
 sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
@@ -579,6 +612,8 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
         SF_ALLOC(ar, t->com[set], 3 * nn);
         SF_ALLOC(ar, t->Q[set], 6 * nn);
         SF_ALLOC(ar, t->hmax[set], nn);
+        SF_ALLOC(ar, t->nw[set], nn);
+        SF_ALLOC(ar, t->nq[set], nn);
     }
     if (t->dt == SF_F32)
         hipLaunchKernelGGL(k_moments_leaf<float>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
@@ -600,7 +635,8 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
     double *raws[2] = {raw0, raw1};
     for (int set = 0; set < 2; ++set)
         hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,
-                           raws[set], t->M[set], t->com[set], t->Q[set], t->hmax[set]);
+                           raws[set], t->M[set], t->com[set], t->Q[set], t->hmax[set], t->nfirst,
+                           t->ncount, t->nchild, t->nnchild, t->nlevel, t->nw[set], t->nq[set]);
     SF_HIP(hipGetLastError());
     return SF_OK;
 }

@@ -106,6 +106,24 @@ struct Comp {
     __device__ __forceinline__ double value() const { return (double)hi + (double)lo; }
 };
 
+// Node record read by the walk: one 128-byte line per node and moment set.
+struct alignas(128) NodeW {
+    double clo[3], chi[3];     // cube corners
+    double com[3];             // centre of mass of the set
+    double hmax;               // largest softening radius in the set
+    double M;                  // mass of the set
+    int32_t first, count;      // particle range (sorted order)
+    int32_t child;             // first child (-1 for leaves)
+    int32_t lvl_nch;           // level << 8 | number of children
+    double pad[2];
+};
+
+// Traceless quadrupole of a node (xx yy xy xz yz; zz = -xx - yy).
+struct alignas(16) NodeQ {
+    double q[5];
+    double pad;
+};
+
 }  // namespace sf
 
 // Opaque handle (C linkage name from the public header).
@@ -137,6 +155,8 @@ struct sf_grav_tree_s {
     double *com[2] = {nullptr, nullptr};              // 3 per node
     double *Q[2] = {nullptr, nullptr};                // 6 per node: xx yy zz xy xz yz
     double *hmax[2] = {nullptr, nullptr};
+    sf::NodeW *nw[2] = {nullptr, nullptr};
+    sf::NodeQ *nq[2] = {nullptr, nullptr};
 
     // groups
     int64_t n_groups = 0;

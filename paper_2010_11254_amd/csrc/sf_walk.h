@@ -9,9 +9,8 @@ constexpr int kStack = 22 * 64 + 64;
 
 struct WalkNodes {
     int64_t n_nodes;
-    const int32_t *nlevel, *nfirst, *ncount, *nchild, *nnchild;
-    const double *clo, *chi;
-    const double *M, *com, *Q, *hmax;   // the moment set used by this walk
+    const NodeW *w;                      // node records of the moment set used
+    const NodeQ *q;                      // quadrupoles of that set
     double side;                         // root cube side (cell = side 2^-level)
     double th2;                          // theta^2
 };
@@ -104,16 +103,17 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
 // are separately rounded (no contraction).
 __device__ __forceinline__ int classify(const WalkNodes &nd, int node, const double blo[3],
                                         const double bhi[3], double hg, int64_t gf, int64_t gl) {
-    const double M = nd.M[node];
+    const NodeW &w = nd.w[node];
+    const double M = w.M;
     if (!(M > 0.0)) return 0;
-    const int64_t f = nd.nfirst[node], c = nd.ncount[node];
+    const int64_t f = w.first, c = w.count;
     bool open = (f < gl) && (gf < f + c);
     double lo[3], hi[3], cm[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        lo[d] = nd.clo[3 * node + d];
-        hi[d] = nd.chi[3 * node + d];
-        cm[d] = nd.com[3 * node + d];
+        lo[d] = w.clo[d];
+        hi[d] = w.chi[d];
+        cm[d] = w.com[d];
     }
     const bool meets = lo[0] <= bhi[0] && blo[0] <= hi[0] && lo[1] <= bhi[1] && blo[1] <= hi[1] &&
                        lo[2] <= bhi[2] && blo[2] <= hi[2];
@@ -124,14 +124,14 @@ __device__ __forceinline__ int classify(const WalkNodes &nd, int node, const dou
         e[d] = fmax(fmax(dsub(blo[d], cm[d]), dsub(cm[d], bhi[d])), 0.0);
     }
     const double dbb2 = dadd(dadd(dmul(g[0], g[0]), dmul(g[1], g[1])), dmul(g[2], g[2]));
-    const double hm = fmax(nd.hmax[node], hg);
+    const double hm = fmax(w.hmax, hg);
     const bool soft = dbb2 < dmul(hm, hm);
     const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
-    const double L = ldexp(nd.side, -nd.nlevel[node]);
+    const double L = ldexp(nd.side, -(w.lvl_nch >> 8));
     const bool angle = dmul(L, L) > dmul(nd.th2, r2);
     const bool opened = open || meets || soft || angle;
     if (!opened) return 1;
-    if (nd.nnchild[node] != 0) return 3;
+    if ((w.lvl_nch & 255) != 0) return 3;
     return (open || meets || soft) ? 2 : 4;
 }
 
@@ -241,14 +241,14 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
         uint32_t lcn = 0, lcf = 0;
         if (cls == 2) {
             const uint32_t q = (nt + popc64(mnear & lt)) & 127;
-            lcn = (uint32_t)nd.ncount[node];
-            L.near.f[q] = nd.nfirst[node];
+            lcn = (uint32_t)nd.w[node].count;
+            L.near.f[q] = nd.w[node].first;
             L.near.c[q] = (int32_t)lcn;
         }
         if (cls == 4) {
             const uint32_t q = (ft + popc64(mfar & lt)) & 127;
-            lcf = (uint32_t)nd.ncount[node];
-            L.far.f[q] = nd.nfirst[node];
+            lcf = (uint32_t)nd.w[node].count;
+            L.far.f[q] = nd.w[node].first;
             L.far.c[q] = (int32_t)lcf;
         }
         nt += (uint32_t)popc64(mnear);
@@ -263,7 +263,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
         if (cls == 3) {
             const uint32_t r = (uint32_t)popc64(mint & lt);
             L.stack[sp + npush - 1 - r] =
-                ((uint32_t)nd.nchild[node] << 4) | (uint32_t)nd.nnchild[node];
+                ((uint32_t)nd.w[node].child << 4) | (uint32_t)(nd.w[node].lvl_nch & 255);
         }
         sp += npush;
         __syncthreads();

@@ -61,6 +61,7 @@ struct GroupEval {
     double cen[3];
     R tx, ty, tz, th, th2;
     int32_t tidx;
+    uint32_t sub, k;            // lane splitting: lane handles sources sub, sub+k, ...
     Acc<FORM> ax, ay, az, ap;
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
@@ -69,22 +70,22 @@ struct GroupEval {
             const int node = L.pc[(head + lane) & 127];
             const WalkNodes &nd = a->nd;
             PCStage<R> s;
-            s.x = dto_frame<FORM>(nd.com[3 * node], cen[0]);
-            s.y = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
-            s.z = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
-            s.M = (R)nd.M[node];
+            s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            s.M = (R)nd.w[node].M;
             if (ORDER == 2) {
-                s.qxx = (R)nd.Q[6 * node];
-                s.qyy = (R)nd.Q[6 * node + 1];
-                s.qxy = (R)nd.Q[6 * node + 3];
-                s.qxz = (R)nd.Q[6 * node + 4];
-                s.qyz = (R)nd.Q[6 * node + 5];
+                s.qxx = (R)nd.q[node].q[0];
+                s.qyy = (R)nd.q[node].q[1];
+                s.qxy = (R)nd.q[node].q[2];
+                s.qxz = (R)nd.q[node].q[3];
+                s.qyz = (R)nd.q[node].q[4];
             }
             spc[lane] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        for (uint32_t j = 0; j < nb; ++j) {
+        for (uint32_t j = sub; j < nb; j += k) {
             const PCStage<R> s = spc[j];
             multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
                                 s.qyz, bx, by, bz, bp);
@@ -113,7 +114,7 @@ struct GroupEval {
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        for (uint32_t j = 0; j < nb; ++j) {
+        for (uint32_t j = sub; j < nb; j += k) {
             const PPStage<R> s = spp[j];
             if (SOFT)
                 pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx,
@@ -151,8 +152,16 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.cen[d] = a.gcen[3 * g + d];
         }
         const double hg = a.ghmax[g];
-        const bool has = lane < gc;
-        const int64_t i = gf + (has ? lane : 0);
+        // Lane splitting: W = smallest power of two >= group size; each target
+        // gets k = 64/W lanes that share every batch's sources.
+        uint32_t W = 1;
+        while (W < (uint32_t)gc) W <<= 1;
+        const uint32_t k = 64u / W;
+        const uint32_t tl = (uint32_t)lane & (W - 1);
+        ev.sub = (uint32_t)lane / W;
+        ev.k = k;
+        const bool has = tl < (uint32_t)gc;
+        const int64_t i = gf + (has ? tl : 0);
         const bool active = has && a.order[i] < a.n_gas;
         uint32_t npc = 0, npp = 0;
         if (__ballot(active) != 0ull) {   // groups of sinks only are left to the sink walk
@@ -167,12 +176,15 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.az.zero();
             ev.ap.zero();
             walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
-            if (active) {
+            double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
+            for (uint32_t off = W; off < 64u; off <<= 1)
+                for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
+            if (active && ev.sub == 0) {
                 const int64_t o = a.order[i];
-                a.acc[3 * o] = (T)(a.G * ev.ax.value());
-                a.acc[3 * o + 1] = (T)(a.G * ev.ay.value());
-                a.acc[3 * o + 2] = (T)(a.G * ev.az.value());
-                if (a.pot) a.pot[o] = (T)(a.G * ev.ap.value());
+                a.acc[3 * o] = (T)(a.G * v[0]);
+                a.acc[3 * o + 1] = (T)(a.G * v[1]);
+                a.acc[3 * o + 2] = (T)(a.G * v[2]);
+                if (a.pot) a.pot[o] = (T)(a.G * v[3]);
             }
         }
         if (STATS && lane == 0) {
@@ -200,21 +212,21 @@ struct SinkEval {
             const int node = L.pc[(head + lane) & 127];
             const WalkNodes &nd = a->nd;
             // target at the frame origin (FP32C) or at its own coordinates
-            const R cx = dto_frame<FORM>(nd.com[3 * node], cen[0]);
-            const R cy = dto_frame<FORM>(nd.com[3 * node + 1], cen[1]);
-            const R cz = dto_frame<FORM>(nd.com[3 * node + 2], cen[2]);
+            const R cx = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            const R cy = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            const R cz = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
             const R tx = FormT<FORM>::rel ? R(0) : (R)cen[0];
             const R ty = FormT<FORM>::rel ? R(0) : (R)cen[1];
             const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
             R qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
             if (ORDER == 2) {
-                qxx = (R)nd.Q[6 * node];
-                qyy = (R)nd.Q[6 * node + 1];
-                qxy = (R)nd.Q[6 * node + 3];
-                qxz = (R)nd.Q[6 * node + 4];
-                qyz = (R)nd.Q[6 * node + 5];
+                qxx = (R)nd.q[node].q[0];
+                qyy = (R)nd.q[node].q[1];
+                qxy = (R)nd.q[node].q[2];
+                qxz = (R)nd.q[node].q[3];
+                qyz = (R)nd.q[node].q[4];
             }
-            multipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.M[node], qxx, qyy, qxy, qxz, qyz,
+            multipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.w[node].M, qxx, qyy, qxy, qxz, qyz,
                                 bx, by, bz, bp);
         }
         ax.fold(bx);
@@ -361,17 +373,8 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
                              int32_t *ctr, double *ss) {
     WalkArgs<T> a{};
     a.nd.n_nodes = t->n_nodes;
-    a.nd.nlevel = t->nlevel;
-    a.nd.nfirst = t->nfirst;
-    a.nd.ncount = t->ncount;
-    a.nd.nchild = t->nchild;
-    a.nd.nnchild = t->nnchild;
-    a.nd.clo = t->clo;
-    a.nd.chi = t->chi;
-    a.nd.M = t->M[set];
-    a.nd.com = t->com[set];
-    a.nd.Q = t->Q[set];
-    a.nd.hmax = t->hmax[set];
+    a.nd.w = t->nw[set];
+    a.nd.q = t->nq[set];
     a.nd.side = t->hframe.side;
     a.nd.th2 = o.theta * o.theta;
     a.xs = (const T *)t->xs;
