@@ -10,15 +10,22 @@ tree build (box, keys, radix sort, gather, topology, moments, groups), group
 walk with quadrupole nodes at theta = 0.5, FP64 sink-sink sum, sink walk and
 output scatter.  value = particles / step time (accelerations per second).
 
-Reported beside it: the same step in the FP64 form, the median and p99
-relative force error of both forms against the FP64 CPU oracle (direct sum) on
-a random target subsample, the walk kernel's roofline (algorithmic FLOP per
-launch / launch time from HIP events on the library's stream), and the oracle
-itself timed on the host cores over that subsample.
+Reported beside it, on the same inputs:
+  * the tree step in the plain FP32 and the FP64 forms;
+  * the adjoint (accel_backward) against the force evaluation on one handle;
+  * the direct (all-pairs) path in FP32C and FP64, one evaluation each;
+  * the median and p99 relative force error of every form and path against
+    the FP64 CPU oracle (direct sum) on a random target subsample;
+  * the walk kernel's roofline (algorithmic FLOP per launch / launch time from
+    HIP events on the library's stream), the direct kernel's likewise, the
+    build's algorithmic HBM bytes per phase time, and the oracle itself timed
+    on the host cores over the subsample.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,10 +39,45 @@ FLOP_PP = 20
 FLOP_PC = {0: 20, 2: 54}
 PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (published, packed)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+# Algorithmic HBM bytes per particle of the sort phase with FP32 inputs:
+# box (read x 12) + keys (read x 12, write key 8 + index 4) + digit
+# histograms (read keys 8) + 8 scatter passes (read and write key + index,
+# 8 x 24) + gather (read index 4 and x, m, h 20, write 20) + sink positions
+# (flags 8, scan 8, compaction 8).
+SORT_BYTES_PER_PARTICLE = 12 + 24 + 8 + 8 * 24 + 44 + 24
+# Files whose change invalidates the stored walk-kernel byte counters.
+WALK_SOURCES = ("sf_internal.h", "sf_math.h", "sf_walk.h", "sf_walk.hip")
+WALK_PMC_FILE = os.path.join(ROOT, "profiles", "walk_precision4m_pmc.md")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def walk_source_hash():
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_11254_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_walk_traffic():
+    """HBM bytes per walk launch from the committed counter summary, if it was
+    taken on the current walk sources (else None)."""
+    try:
+        with open(WALK_PMC_FILE) as fh:
+            m = re.search(r"<!-- bench: (\{.*?\}) -->", fh.read())
+    except OSError:
+        return None
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("src_sha") != walk_source_hash():
+        return None
+    return rec
 
 
 def main():
@@ -47,10 +89,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form comparison")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 and plain-FP32 forms")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-path evaluations")
+    ap.add_argument("--no-backward", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="run one 256 MiB device copy first (calibrates HBM byte counters)")
+                    help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
     ap.add_argument("--leaf-cap", type=int, default=16)
     ap.add_argument("--group-cap", type=int, default=64)
     args = ap.parse_args()
@@ -63,7 +107,7 @@ def main():
     import torch
 
     from paper_2010_11254_amd import _lib as L
-    from synth import precision_cloud, subsample
+    from synth import cotangents, precision_cloud, subsample
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -79,11 +123,28 @@ def main():
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)   # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
     acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
     pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
+
+    # oracle target sample: size it to the requested CPU time first
+    sample = None
+    xd = md = hd = None
+    if not args.no_cpu:
+        from oracle import direct as odirect
+        xd, md, hd = (np.asarray(v, dtype=np.float64) for v in (ps.x, ps.m, ps.h))
+        probe = subsample(ps.n, 256, seed=2)
+        t0 = time.perf_counter()
+        odirect.direct(xd, md, hd, targets=probe)
+        rate = probe.size / (time.perf_counter() - t0)
+        sample = subsample(ps.n, int(min(65536, max(512, rate * args.cpu_seconds))), seed=2)
+    outs = {}
+
+    def keep(name):
+        if sample is not None:
+            outs[name] = acc[torch.as_tensor(sample, device=dev)].double().cpu().numpy()
 
     def opts(form, timing=False, stats=False):
         return L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=args.leaf_cap,
@@ -114,6 +175,20 @@ def main():
         wall = (time.perf_counter() - t_start) / steps
         return wall, float(np.mean(walk_ms)), {k: float(np.mean(v)) for k, v in phase.items()}
 
+    def event_ms(fn, reps):
+        """Mean time of fn() over reps calls, HIP events on the current stream
+        (the one the library enqueues on)."""
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
     # interaction counts of one evaluation (untimed), for the FLOP count
     t = step(opts("fp32c", stats=True))
     torch.cuda.synchronize()
@@ -133,46 +208,92 @@ def main():
     log(f"tree: {info['n_nodes']} nodes, {info['n_groups']} groups, max level {info['max_level']}; "
         f"interactions/target: {n_pc / ps.n_gas:.0f} node + {n_pp / ps.n_gas:.0f} particle")
 
+    # headline: FP32C tree steps
     wall32, walk32, ph32 = timed("fp32c", args.steps, args.warmup)
-    out32 = acc.double().cpu().numpy()
+    keep("tree_fp32c")
     log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
         + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
     res = {}
     if not args.no_fp64:
         k64 = max(2, args.steps // 3)
-        wall64, walk64, ph64 = timed("fp64", k64, 1)
-        out64 = acc.double().cpu().numpy()
-        res["fp64"] = {"ms_per_step": wall64 * 1e3, "value": ps.n / wall64,
-                       "walk_ms": walk64, "phases_ms": ph64}
-        log(f"fp64: {wall64 * 1e3:.2f} ms/step, walk kernel {walk64:.2f} ms")
+        for form in ("fp64", "fp32"):
+            wall, walk, ph = timed(form, k64, 1)
+            keep("tree_" + form)
+            res[form] = {"ms_per_step": wall * 1e3, "value": ps.n / wall, "walk_ms": walk,
+                         "phases_ms": ph}
+            log(f"{form}: {wall * 1e3:.2f} ms/step, walk kernel {walk:.2f} ms")
+
+    # adjoint against the force evaluation on one handle (build excluded)
+    adj = {}
+    if not args.no_backward:
+        ga, gp = cotangents(ps.n, seed=2, dtype=np.float32)
+        ga, gp = torch.as_tensor(ga).to(dev), torch.as_tensor(gp).to(dev)
+        for form in ("fp32c",) + (() if args.no_fp64 else ("fp64",)):
+            o = opts(form)
+            t = L.sf_grav_build_tree(x, m, h, o)
+            fwd = event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot), 3)
+            bwd = event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga, gp), 2)
+            L.sf_grav_tree_free(t)
+            build = res.get(form, {}).get("phases_ms") if form != "fp32c" else ph32
+            b_ms = sum(build[k] for k in ("sort", "topology", "moments", "groups")) if build else None
+            adj[form] = {"accel_ms": fwd, "backward_ms": bwd, "backward_over_accel": bwd / fwd}
+            if b_ms is not None:
+                adj[form]["with_build"] = (bwd + b_ms) / (fwd + b_ms)
+            log(f"adjoint {form}: accel {fwd:.2f} ms, backward {bwd:.2f} ms, ratio {bwd / fwd:.2f}")
+        del ga, gp
+
+    # direct path: one evaluation per form over all pairs
+    direct = {}
+    if not args.no_direct:
+        pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
+        for form in ("fp32c", "fp64"):
+            o = opts(form)
+            k = min(ps.n, 65536)
+            wx, wm, wh = x[:k].contiguous(), m[:k].contiguous(), h[:k].contiguous()
+            L.sf_grav_accel(None, wx, wm, wh, L.make_opts(form=form, n_gas=min(k, ps.n_gas)),
+                            acc=acc[:k], pot=pot[:k])   # loads the kernels
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            L.sf_grav_accel(None, x, m, h, o, acc=acc, pot=pot)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            keep("direct_" + form)
+            tf = FLOP_PP * pairs / (ms * 1e-3) / 1e12
+            peak = PEAK_FP32_TFLOPS if form == "fp32c" else PEAK_FP64_TFLOPS
+            direct[form] = {"ms": ms, "value": ps.n / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
+                            "achieved_tflops": tf, "peak": peak, "frac": tf / peak}
+            if form == "fp32c":
+                direct[form]["frac_nonpacked"] = tf / PEAK_FP32_NONPACKED_TFLOPS
+            log(f"direct {form}: {ms:.1f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, {tf:.1f} TFLOP/s")
 
     cpu = None
-    if not args.no_cpu:
+    errs = {}
+    if sample is not None:
         from oracle import direct as odirect
-        xd, md, hd = (np.asarray(v, dtype=np.float64) for v in (ps.x, ps.m, ps.h))
-        probe = subsample(ps.n, 256, seed=2)
         t0 = time.perf_counter()
-        odirect.direct(xd, md, hd, targets=probe)
-        rate = probe.size / (time.perf_counter() - t0)
-        k = int(min(65536, max(512, rate * args.cpu_seconds)))
-        sample = subsample(ps.n, k, seed=2)
-        t0 = time.perf_counter()
-        ar, pr = odirect.direct(xd, md, hd, targets=sample)
+        ar, _ = odirect.direct(xd, md, hd, targets=sample)
         tcpu = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = {"value": sample.size / tcpu, "unit": "accels/s", "cores": cores, "kind": "oracle",
                "sample": f"{sample.size} random targets x all {ps.n} sources, FP64 direct sum, "
                          f"{tcpu:.1f}s"}
         log(f"oracle: {sample.size} targets in {tcpu:.1f}s on {cores} threads")
-
-        def errs(out):
-            e = np.linalg.norm(out[sample] - ar, axis=1) / np.linalg.norm(ar, axis=1)
-            return float(np.median(e)), float(np.quantile(e, 0.99))
-        res["err_fp32c"] = errs(out32)
-        if "fp64" in res:
-            res["err_fp64"] = errs(out64)
+        nref = np.linalg.norm(ar, axis=1)
+        ok = nref > 0
+        for name, out in outs.items():
+            e = np.linalg.norm(out - ar, axis=1)[ok] / nref[ok]
+            errs[name] = {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99))}
+            log(f"error {name}: median {errs[name]['median']:.3e}, p99 {errs[name]['p99']:.3e}")
 
     achieved = walk_flop / (walk32 * 1e-3) / 1e12
+    traffic = None
+    pmc = stored_walk_traffic()
+    if pmc is not None:
+        traffic = pmc["bytes_per_launch"]
+    sort_ms = ph32.get("sort")
     line = {
         "metric": "softened-gravity accels/sec at 4M particles (FP32c vs FP64); p99 force err",
         "value": ps.n / wall32,
@@ -195,20 +316,32 @@ def main():
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                     "traffic": None,
+                     "traffic": traffic,
                      "walk_ms": walk32, "flop_per_launch": walk_flop,
                      "interactions_per_s": (n_pc + n_pp) / (walk32 * 1e-3),
                      "n_pc": n_pc, "n_pp": n_pp},
         "cpu_baseline": cpu,
         "phases_ms": ph32,
     }
+    if sort_ms:
+        gbs = SORT_BYTES_PER_PARTICLE * ps.n / (sort_ms * 1e-3) / 1e9
+        line["build_sort_hbm"] = {"bytes_per_particle": SORT_BYTES_PER_PARTICLE,
+                                  "achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
+    for form in ("fp64", "fp32"):
+        if form in res:
+            line[form] = res[form]
     if "fp64" in res:
-        line["fp64"] = res["fp64"]
         line["fp32c_over_fp64"] = res["fp64"]["ms_per_step"] / (wall32 * 1e3)
-    if "err_fp32c" in res:
-        line["rel_err_fp32c"] = {"median": res["err_fp32c"][0], "p99": res["err_fp32c"][1]}
-        if "err_fp64" in res:
-            line["rel_err_fp64"] = {"median": res["err_fp64"][0], "p99": res["err_fp64"][1]}
+    if adj:
+        line["adjoint"] = adj
+    if direct:
+        line["direct"] = direct
+        if "fp64" in direct:
+            line["direct"]["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+    if errs:
+        line["rel_err"] = errs
+        if "tree_fp32c" in errs:
+            line["rel_err_fp32c"] = errs["tree_fp32c"]
     print(json.dumps(line), flush=True)
 
 
