@@ -39,7 +39,9 @@
  *     SF_E_DEVICE, allocation failures to SF_E_NOMEM (no partial handle is
  *     leaked).  sf_grav_last_error() gives a message for the calling thread.
  *   - The library allocates its device scratch with stream-ordered
- *     allocation on `stream`.
+ *     allocation on `stream` and keeps freed blocks in a per-stream cache
+ *     (at most 64 GiB) for later calls on the same stream; the cache is
+ *     returned to HIP only when the process ends.
  */
 #ifndef SF_GRAV_H
 #define SF_GRAV_H

@@ -170,12 +170,7 @@ def build_tree(x, leaf_cap=16):
 
 # --------------------------------------------------------------- moments
 
-def node_moments(tree, x, m, h, sel=None):
-    """M, centre of mass, traceless quadrupole Q = 3S - tr(S) I and max h.
-
-    S = sum m (x - com)(x - com)^T over the node's particles; `sel` (bool per
-    input particle) restricts the sums (e.g. gas only).  Sums are plain FP64.
-    """
+def _sorted_fields(tree, x, m, h, sel):
     xs = np.asarray(x, dtype=np.float64)[tree.order]
     ms = np.asarray(m, dtype=np.float64)[tree.order]
     hs = np.asarray(h, dtype=np.float64)[tree.order]
@@ -183,25 +178,72 @@ def node_moments(tree, x, m, h, sel=None):
         w = np.asarray(sel, dtype=bool)[tree.order]
         ms = np.where(w, ms, 0.0)
         hs = np.where(w, hs, 0.0)
+    return xs, ms, hs
+
+
+def _one_node(xs, ms, hs, f, c):
+    """M, centre of mass, traceless Q and max h of the particles [f, f + c)."""
+    mk = ms[f:f + c]
+    xk = xs[f:f + c]
+    Mk = mk.sum()
+    ck = np.zeros(3)
+    Qk = np.zeros((3, 3))
+    if Mk > 0:
+        ck = (mk[:, None] * xk).sum(axis=0) / Mk
+        y = xk - ck
+        S = (mk[:, None, None] * y[:, :, None] * y[:, None, :]).sum(axis=0)
+        Qk = 3.0 * S - np.trace(S) * np.eye(3)
+    return Mk, ck, Qk, hs[f:f + c].max()
+
+
+def node_moments(tree, x, m, h, sel=None):
+    """M, centre of mass, traceless quadrupole Q = 3S - tr(S) I and max h.
+
+    S = sum m (x - com)(x - com)^T over the node's particles; `sel` (bool per
+    input particle) restricts the sums (e.g. gas only).  Sums are plain FP64.
+    """
+    xs, ms, hs = _sorted_fields(tree, x, m, h, sel)
     nn = tree.n_nodes
     M = np.zeros(nn)
     com = np.zeros((nn, 3))
     Q = np.zeros((nn, 3, 3))
     hmax = np.zeros(nn)
     for k in range(nn):
-        f, c = tree.first[k], tree.count[k]
-        mk = ms[f:f + c]
-        xk = xs[f:f + c]
-        Mk = mk.sum()
-        M[k] = Mk
-        hmax[k] = hs[f:f + c].max()
-        if Mk > 0:
-            ck = (mk[:, None] * xk).sum(axis=0) / Mk
-            y = xk - ck
-            S = (mk[:, None, None] * y[:, :, None] * y[:, None, :]).sum(axis=0)
-            com[k] = ck
-            Q[k] = 3.0 * S - np.trace(S) * np.eye(3)
+        M[k], com[k], Q[k], hmax[k] = _one_node(xs, ms, hs, tree.first[k], tree.count[k])
     return {"M": M, "com": com, "Q": Q, "hmax": hmax}
+
+
+class LazyMoments:
+    """The same per-node sums as node_moments, computed the first time a node
+    is indexed -- for walking a few groups of a tree with millions of nodes.
+    `mom["M"][idx]`, `mom["com"][idx]`, ... behave like the arrays."""
+
+    class _Field:
+        def __init__(self, owner, name):
+            self.owner, self.name = owner, name
+
+        def __getitem__(self, idx):
+            self.owner._ensure(idx)
+            return self.owner.arr[self.name][idx]
+
+    def __init__(self, tree, x, m, h, sel=None):
+        self.tree = tree
+        self.xs, self.ms, self.hs = _sorted_fields(tree, x, m, h, sel)
+        nn = tree.n_nodes
+        self.done = np.zeros(nn, dtype=bool)
+        self.arr = {"M": np.zeros(nn), "com": np.zeros((nn, 3)), "Q": np.zeros((nn, 3, 3)),
+                    "hmax": np.zeros(nn)}
+
+    def _ensure(self, idx):
+        ks = np.unique(np.atleast_1d(np.arange(self.tree.n_nodes)[idx]))
+        for k in ks[~self.done[ks]]:
+            out = _one_node(self.xs, self.ms, self.hs, self.tree.first[k], self.tree.count[k])
+            for name, v in zip(("M", "com", "Q", "hmax"), out):
+                self.arr[name][k] = v
+            self.done[k] = True
+
+    def __getitem__(self, name):
+        return LazyMoments._Field(self, name)
 
 
 # --------------------------------------------------------------- groups
@@ -339,14 +381,17 @@ class TreeLists:
     n_pp: int = 0
 
 
-def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=None):
-    """Build the tree and every interaction list (optionally for some groups)."""
+def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=None,
+               lazy=False):
+    """Build the tree and every interaction list (optionally for some groups;
+    `lazy` computes node moments only where the walks look)."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     tree = build_tree(x, leaf_cap)
     is_sink = np.arange(n) >= n_gas
-    tree.mom["all"] = node_moments(tree, x, m, h)
-    tree.mom["gas"] = node_moments(tree, x, m, h, sel=~is_sink)
+    moments = LazyMoments if lazy else node_moments
+    tree.mom["all"] = moments(tree, x, m, h)
+    tree.mom["gas"] = moments(tree, x, m, h, sel=~is_sink)
     clo, chi, cell = tree.cube()
     groups = make_groups(tree, group_cap)
     xs = x[tree.order]

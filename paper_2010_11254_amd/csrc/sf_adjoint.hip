@@ -316,13 +316,13 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
 // The tree result is a sum over the frozen interaction lists of pair terms
 // (target i, particle j) and node terms (target i, node n with mass M, centre
 // of mass c, traceless quadrupole Q).  Its gradient has three parts:
-//   * target side: d/dx_i, d/dh_i of the target's own terms (gathered by the
-//     lane that owns the target, as in the forward walk);
-//   * source side: d/dx_j, d/dm_j, d/dh_j of pair terms (pass 2 of each batch:
-//     lanes own the sources and loop over the group's targets, then one FP64
-//     atomic add per source and value);
-//   * node side: d/dM, d/dc, d/dQ of node terms (pass 2 for nodes), later
-//     pushed down to every particle of the node through M = sum m,
+//   * target side: d/dx_i, d/dh_i of the target's own terms (gathered in the
+//     registers of the lanes that own the target, as in the forward walk);
+//   * source side: d/dx_j, d/dm_j, d/dh_j of pair terms (each term is
+//     evaluated once, by the target's lane, and added to the source's LDS
+//     accumulator; one FP64 atomic add per source and value and batch);
+//   * node side: d/dM, d/dc, d/dQ of node terms (accumulated the same way),
+//     later pushed down to every particle of the node through M = sum m,
 //     c = sum m x / M, Q = sum m (3 y y^T - |y|^2 I), y = x - c.
 // Opening decisions are held fixed, so this is the exact derivative of the
 // tree approximation as evaluated.
@@ -416,86 +416,107 @@ struct WalkArgsB {
     int64_t n_sink;
     const T *g_acc, *g_pot;     // caller order
     double *tgt;                // 5 per sorted particle: target side (x y z m h)
-    double *scat;               // 5 per sorted particle: source side (atomic)
-    double *nadj;               // 10 per node: M, c(3), dQ(6) (atomic)
+    // Atomic arrays, component-major (value c of particle p at c n + p, of
+    // node k at c n_nodes + k) so that a batch's 64 adds to one component
+    // fall into a few cache lines; kXcd copies each.
+    double *scat;               // 5 per sorted particle: source side (x y z m h)
+    double *nadj;               // 10 per node: M, c(3), dQ(6)
+    int64_t scat_stride, nadj_stride;   // elements between copies
     int32_t *task_ctr, *err;
 };
 
-template <typename R> struct alignas(16) TStage { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx, act; };
+// Per-lane target of the group adjoint.
+template <typename R> struct TgtB { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx; bool act; };
+
+// LDS accumulation of one batch's source-side terms: the lanes of a step hold
+// distinct batch entries wherever the group is large enough, so these adds
+// rarely collide; they are LDS atomics, so collisions only cost time.  The
+// accumulators are FP64 in every form: FP64 LDS adds measured several times
+// faster than FP32 ones on gfx950 (and keep the batch sums exact enough).
+__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Group tasks, one pass per batch: each (target, entry) term is evaluated
+// once and split into its target side (kept in the lane's registers) and its
+// entry side (added to the entry's LDS accumulator, flushed to the global
+// FP64 adjoint arrays once per batch).  Lane splitting as in the forward
+// walk: a group of gc targets uses W = next power of two >= gc lanes per
+// copy and k = 64 / W copies; copy `sub` takes the entries sub, sub + k, ...
+// of a batch, visited from a per-target rotation so that the lanes of a
+// copy sit on different entries in every step.
 template <typename T, int FORM, int ORDER>
 struct GroupEvalB {
     using R = typename FormT<FORM>::R;
     const WalkArgsB<T> *a;
-    PPStage<R> *spp;
-    PCStage<R> *spc;
-    TStage<R> *st;
-    int ntg;                    // targets staged (lanes < ntg)
+    // Batch entries staged structure-of-arrays: the lanes of a step read
+    // different entries, and one component of consecutive entries sits in
+    // consecutive LDS words, so those reads are free of bank conflicts.
+    R (*stg)[64];               // [9][64]: x y z m|M, then h2 h (pairs) or Q (nodes)
+    int32_t *sidx;              // [64] particle index of a pair entry
+    double (*bacc)[64];         // [10][64] entry-side accumulators
+    double *scat, *nadj;        // this XCD's copies of the atomic arrays
     double cen[3];
-    TStage<R> me;
+    TgtB<R> me;
+    uint32_t tl, sub, k;
     Acc<FORM> ox, oy, oz, oh;
+
+    // Steps of a batch of nb entries for this lane's copy: m = ceil((nb - sub) / k)
+    // slots, slot q holds entry sub + k q; the lane starts at slot tl mod m.
+    __device__ __forceinline__ uint32_t slots(uint32_t nb) const {
+        return (nb + k - 1) / k;   // uniform: the largest copy's count
+    }
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
         const int lane = threadIdx.x;
         int node = -1;
-        PCStage<R> sn;
         if ((uint32_t)lane < nb) {
             node = L.pc[(head + lane) & 127];
             const WalkNodes &nd = a->nd;
-            sn.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
-            sn.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
-            sn.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
-            sn.M = (R)nd.w[node].M;
-            sn.qxx = sn.qyy = sn.qxy = sn.qxz = sn.qyz = R(0);
-            if (ORDER == 2) {
-                sn.qxx = (R)nd.q[node].q[0];
-                sn.qyy = (R)nd.q[node].q[1];
-                sn.qxy = (R)nd.q[node].q[2];
-                sn.qxz = (R)nd.q[node].q[3];
-                sn.qyz = (R)nd.q[node].q[4];
-            }
-            spc[lane] = sn;
+            stg[0][lane] = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            stg[1][lane] = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            stg[2][lane] = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            stg[3][lane] = (R)nd.w[node].M;
+            if (ORDER == 2)
+                for (int d = 0; d < 5; ++d) stg[4 + d][lane] = (R)nd.q[node].q[d];
         }
         __syncthreads();
-        // pass 1: lanes own targets
+        const uint32_t m = slots(nb);
+        uint32_t q = tl % m;
         R bx = 0, by = 0, bz = 0;
-        for (uint32_t j = 0; j < nb; ++j) {
-            const PCStage<R> s = spc[j];
-            R gx, gy, gz, gM, gs[6];
-            bmultipole<R, ORDER>(me.x - s.x, me.y - s.y, me.z - s.z, s.M, s.qxx, s.qyy, s.qxy,
-                                 s.qxz, s.qyz, me.gx, me.gy, me.gz, me.gp, gx, gy, gz, gM, gs);
-            bx += gx;
-            by += gy;
-            bz += gz;
+        for (uint32_t s = 0; s < m; ++s) {
+            const uint32_t j = sub + k * q;
+            if (me.act && j < nb) {
+                R q5[5] = {R(0), R(0), R(0), R(0), R(0)};
+                if (ORDER == 2)
+                    for (int d = 0; d < 5; ++d) q5[d] = stg[4 + d][j];
+                R gx, gy, gz, gM, gs[6];
+                bmultipole<R, ORDER>(me.x - stg[0][j], me.y - stg[1][j], me.z - stg[2][j],
+                                     stg[3][j], q5[0], q5[1], q5[2], q5[3], q5[4], me.gx, me.gy,
+                                     me.gz, me.gp, gx, gy, gz, gM, gs);
+                bx += gx;
+                by += gy;
+                bz += gz;
+                lds_add(&bacc[0][j], (double)(gM));
+                lds_add(&bacc[1][j], (double)(-gx));
+                lds_add(&bacc[2][j], (double)(-gy));
+                lds_add(&bacc[3][j], (double)(-gz));
+                if (ORDER == 2)
+                    for (int d = 0; d < 6; ++d) lds_add(&bacc[4 + d][j], (double)(gs[d]));
+            }
+            q = q + 1 == m ? 0 : q + 1;
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
-        // pass 2: lanes own nodes, loop over the group's active targets
+        __syncthreads();
         if ((uint32_t)lane < nb) {
-            R cx = 0, cy = 0, cz = 0, mb = 0, g6[6] = {0, 0, 0, 0, 0, 0};
-            for (int t = 0; t < ntg; ++t) {
-                const TStage<R> q = st[t];
-                if (!q.act) continue;
-                R gx, gy, gz, gM, gs[6];
-                bmultipole<R, ORDER>(q.x - sn.x, q.y - sn.y, q.z - sn.z, sn.M, sn.qxx, sn.qyy,
-                                     sn.qxy, sn.qxz, sn.qyz, q.gx, q.gy, q.gz, q.gp, gx, gy, gz,
-                                     gM, gs);
-                cx -= gx;
-                cy -= gy;
-                cz -= gz;
-                mb += gM;
-                for (int d = 0; d < 6; ++d) g6[d] += gs[d];
+            const int64_t nn = a->nd.n_nodes;
+            const int nv = ORDER == 2 ? 10 : 4;
+            for (int d = 0; d < nv; ++d) {
+                atomic_add_f64(nadj + d * nn + node, bacc[d][lane]);
+                bacc[d][lane] = 0.0;
             }
-            double *o = a->nadj + 10 * (int64_t)node;
-            atomic_add_f64(o, (double)mb);
-            atomic_add_f64(o + 1, (double)cx);
-            atomic_add_f64(o + 2, (double)cy);
-            atomic_add_f64(o + 3, (double)cz);
-            if (ORDER == 2)
-                for (int d = 0; d < 6; ++d) atomic_add_f64(o + 4 + d, (double)g6[d]);
         }
         __syncthreads();
     }
@@ -503,55 +524,57 @@ struct GroupEvalB {
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const int lane = threadIdx.x;
-        PPStage<R> sj;
         int p = -1;
         if ((uint32_t)lane < nb) {
             p = L.slot[lane];
-            sj.x = to_frame<FORM>(a->xs[p], cen[0]);
-            sj.y = to_frame<FORM>(a->ys[p], cen[1]);
-            sj.z = to_frame<FORM>(a->zs[p], cen[2]);
-            sj.m = (R)a->ms[p];
-            sj.h = (R)a->hs[p];
-            sj.h2 = sj.h * sj.h;
-            sj.idx = p;
-            spp[lane] = sj;
+            stg[0][lane] = to_frame<FORM>(a->xs[p], cen[0]);
+            stg[1][lane] = to_frame<FORM>(a->ys[p], cen[1]);
+            stg[2][lane] = to_frame<FORM>(a->zs[p], cen[2]);
+            stg[3][lane] = (R)a->ms[p];
+            const R h = (R)a->hs[p];
+            stg[4][lane] = h * h;
+            stg[5][lane] = h;
+            sidx[lane] = p;
         }
         __syncthreads();
+        const uint32_t m = slots(nb);
+        uint32_t q = tl % m;
         R bx = 0, by = 0, bz = 0, bh = 0;
-        for (uint32_t j = 0; j < nb; ++j) {
-            const PPStage<R> s = spp[j];
-            R Sx, Sy, Sz, Tm, Th, sh;
-            bpair<R, SOFT>(s.x - me.x, s.y - me.y, s.z - me.z, s.m, s.h2, s.h, me.h2, me.h, me.gx,
-                           me.gy, me.gz, me.gp, s.idx == me.idx, Sx, Sy, Sz, Tm, Th, sh);
-            bx -= Sx;
-            by -= Sy;
-            bz -= Sz;
-            bh += sh * Th;
+        for (uint32_t s = 0; s < m; ++s) {
+            const uint32_t j = sub + k * q;
+            if (me.act && j < nb) {
+                R Sx, Sy, Sz, Tm, Th, sh;
+                const R hj2 = SOFT ? stg[4][j] : R(0), hj = SOFT ? stg[5][j] : R(0);
+                const bool self = SOFT && sidx[j] == me.idx;
+                bpair<R, SOFT>(stg[0][j] - me.x, stg[1][j] - me.y, stg[2][j] - me.z, stg[3][j],
+                               hj2, hj, me.h2, me.h, me.gx, me.gy, me.gz, me.gp, self, Sx, Sy, Sz,
+                               Tm, Th, sh);
+                bx -= Sx;
+                by -= Sy;
+                bz -= Sz;
+                lds_add(&bacc[0][j], (double)(Sx));
+                lds_add(&bacc[1][j], (double)(Sy));
+                lds_add(&bacc[2][j], (double)(Sz));
+                lds_add(&bacc[3][j], (double)(Tm));
+                if (SOFT) {
+                    bh += sh * Th;
+                    lds_add(&bacc[4][j], (double)((R(1) - sh) * Th));
+                }
+            }
+            q = q + 1 == m ? 0 : q + 1;
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
-        oh.fold(bh);
+        if (SOFT) oh.fold(bh);
+        __syncthreads();
         if ((uint32_t)lane < nb) {
-            R sx = 0, sy = 0, sz = 0, sm = 0, shh = 0;
-            for (int t = 0; t < ntg; ++t) {
-                const TStage<R> q = st[t];
-                if (!q.act) continue;
-                R Sx, Sy, Sz, Tm, Th, sh;
-                bpair<R, SOFT>(sj.x - q.x, sj.y - q.y, sj.z - q.z, sj.m, sj.h2, sj.h, q.h2, q.h,
-                               q.gx, q.gy, q.gz, q.gp, p == q.idx, Sx, Sy, Sz, Tm, Th, sh);
-                sx += Sx;
-                sy += Sy;
-                sz += Sz;
-                sm += Tm;
-                shh += (R(1) - sh) * Th;
+            const int64_t n = a->n;
+            const int nv = SOFT ? 5 : 4;
+            for (int d = 0; d < nv; ++d) {
+                atomic_add_f64(scat + d * n + p, bacc[d][lane]);
+                bacc[d][lane] = 0.0;
             }
-            double *o = a->scat + 5 * (int64_t)p;
-            atomic_add_f64(o, (double)sx);
-            atomic_add_f64(o + 1, (double)sy);
-            atomic_add_f64(o + 2, (double)sz);
-            atomic_add_f64(o + 3, (double)sm);
-            atomic_add_f64(o + 4, (double)shh);
         }
         __syncthreads();
     }
@@ -561,16 +584,20 @@ template <typename T, int FORM, int ORDER>
 __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
     using R = typename FormT<FORM>::R;
     __shared__ WalkLds L;
-    __shared__ PPStage<R> spp[64];
-    __shared__ PCStage<R> spc[64];
-    __shared__ TStage<R> st[64];
+    __shared__ R stg[9][64];
+    __shared__ int32_t sidx[64];
+    __shared__ double bacc[10][64];
     const int lane = threadIdx.x;
+    for (int d = 0; d < 10; ++d) bacc[d][lane] = 0.0;
     const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
     GroupEvalB<T, FORM, ORDER> ev;
     ev.a = &a;
-    ev.spp = spp;
-    ev.spc = spc;
-    ev.st = st;
+    ev.stg = stg;
+    ev.sidx = sidx;
+    ev.bacc = bacc;
+    const int xcd = xcd_id();
+    ev.scat = a.scat + xcd * a.scat_stride;
+    ev.nadj = a.nadj + xcd * a.nadj_stride;
     for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
         const int64_t gf = a.gfirst[g], gc = a.gcount[g];
         double blo[3], bhi[3];
@@ -580,12 +607,17 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
             ev.cen[d] = a.gcen[3 * g + d];
         }
         const double hg = a.ghmax[g];
-        const bool has = lane < gc;
-        const int64_t i = gf + (has ? lane : 0);
+        uint32_t W = 1;
+        while (W < (uint32_t)gc) W <<= 1;
+        ev.k = 64u / W;
+        ev.tl = (uint32_t)lane & (W - 1);
+        ev.sub = (uint32_t)lane / W;
+        const bool has = ev.tl < (uint32_t)gc;
+        const int64_t i = gf + (has ? ev.tl : 0);
         const bool active = has && a.order[i] < a.n_gas;
         if (__ballot(active) == 0ull) continue;
         const int64_t o = a.order[i];
-        TStage<R> me;
+        TgtB<R> &me = ev.me;
         me.x = to_frame<FORM>(a.xs[i], ev.cen[0]);
         me.y = to_frame<FORM>(a.ys[i], ev.cen[1]);
         me.z = to_frame<FORM>(a.zs[i], ev.cen[2]);
@@ -596,23 +628,22 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
         me.gz = (R)a.g_acc[3 * o + 2];
         me.gp = a.g_pot ? (R)a.g_pot[o] : R(0);
         me.idx = has ? (int32_t)i : -1;
-        me.act = active ? 1 : 0;
-        st[lane] = me;
-        ev.me = me;
-        ev.ntg = (int)gc;
+        me.act = active;
         ev.ox.zero();
         ev.oy.zero();
         ev.oz.zero();
         ev.oh.zero();
-        __syncthreads();
         uint32_t npc, npp;
         walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
-        if (active) {
-            a.tgt[5 * i] = ev.ox.value();
-            a.tgt[5 * i + 1] = ev.oy.value();
-            a.tgt[5 * i + 2] = ev.oz.value();
+        double v[4] = {ev.ox.value(), ev.oy.value(), ev.oz.value(), ev.oh.value()};
+        for (uint32_t off = W; off < 64u; off <<= 1)
+            for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
+        if (active && ev.sub == 0) {
+            a.tgt[5 * i] = v[0];
+            a.tgt[5 * i + 1] = v[1];
+            a.tgt[5 * i + 2] = v[2];
             a.tgt[5 * i + 3] = 0.0;
-            a.tgt[5 * i + 4] = ev.oh.value();
+            a.tgt[5 * i + 4] = v[3];
         }
     }
 }
@@ -621,6 +652,7 @@ template <typename T, int FORM, int ORDER>
 struct SinkEvalB {
     using R = typename FormT<FORM>::R;
     const WalkArgsB<T> *a;
+    double *scat, *nadj;        // this XCD's copies of the atomic arrays
     double cen[3];
     R th, th2, gx, gy, gz, gp;
     int32_t tidx;
@@ -652,13 +684,13 @@ struct SinkEvalB {
             bx = g0;
             by = g1;
             bz = g2;
-            double *o = a->nadj + 10 * (int64_t)node;
-            atomic_add_f64(o, (double)gM);
-            atomic_add_f64(o + 1, -(double)g0);
-            atomic_add_f64(o + 2, -(double)g1);
-            atomic_add_f64(o + 3, -(double)g2);
+            const int64_t nn = a->nd.n_nodes;
+            atomic_add_f64(nadj + node, (double)gM);
+            atomic_add_f64(nadj + nn + node, -(double)g0);
+            atomic_add_f64(nadj + 2 * nn + node, -(double)g1);
+            atomic_add_f64(nadj + 3 * nn + node, -(double)g2);
             if (ORDER == 2)
-                for (int d = 0; d < 6; ++d) atomic_add_f64(o + 4 + d, (double)gs[d]);
+                for (int d = 0; d < 6; ++d) atomic_add_f64(nadj + (4 + d) * nn + node, (double)gs[d]);
         }
         ox.fold(bx);
         oy.fold(by);
@@ -686,12 +718,12 @@ struct SinkEvalB {
                 by = -Sy;
                 bz = -Sz;
                 bh = sh * Th;
-                double *o = a->scat + 5 * (int64_t)p;
-                atomic_add_f64(o, (double)Sx);
-                atomic_add_f64(o + 1, (double)Sy);
-                atomic_add_f64(o + 2, (double)Sz);
-                atomic_add_f64(o + 3, (double)Tm);
-                atomic_add_f64(o + 4, (double)((R(1) - sh) * Th));
+                const int64_t n = a->n;
+                atomic_add_f64(scat + p, (double)Sx);
+                atomic_add_f64(scat + n + p, (double)Sy);
+                atomic_add_f64(scat + 2 * n + p, (double)Sz);
+                atomic_add_f64(scat + 3 * n + p, (double)Tm);
+                atomic_add_f64(scat + 4 * n + p, (double)((R(1) - sh) * Th));
             }
         }
         ox.fold(bx);
@@ -715,6 +747,9 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
     const int lane = threadIdx.x;
     SinkEvalB<T, FORM, ORDER> ev;
     ev.a = &a;
+    const int xcd = xcd_id();
+    ev.scat = a.scat + xcd * a.scat_stride;
+    ev.nadj = a.nadj + xcd * a.nadj_stride;
     for (int k = next_task(a.task_ctr); k < a.n_sink; k = next_task(a.task_ctr)) {
         const int64_t p = a.sink_pos[k];
         const int64_t o = a.order[p];
@@ -745,11 +780,22 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
     }
 }
 
+// Fold the kXcd per-XCD copies of an atomic array into copy 0.
+__global__ void k_sum_copies(double *__restrict__ base, int64_t len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = base[i];
+#pragma unroll
+        for (int x = 1; x < kXcd; ++x) v += base[x * len + i];
+        base[i] = v;
+    }
+}
+
 // Push node adjoints down to particles, add every part and write the output.
 // For each sorted particle: walk its leaf's ancestors; set 0 (all particles)
 // always, set 1 (gas only) for gas particles.
 template <typename T>
-__global__ void k_pushdown(int64_t n, int64_t n_gas, const T *__restrict__ xs,
+__global__ void k_pushdown(int64_t n, int64_t n_gas, int64_t nn, const T *__restrict__ xs,
                            const T *__restrict__ ys, const T *__restrict__ zs,
                            const T *__restrict__ ms, const int32_t *__restrict__ order,
                            const int32_t *__restrict__ pleaf, const int32_t *__restrict__ nparent,
@@ -767,7 +813,7 @@ __global__ void k_pushdown(int64_t n, int64_t n_gas, const T *__restrict__ xs,
     const int64_t o = order[s];
     const bool gas = o < n_gas;
     double g[5];
-    for (int d = 0; d < 5; ++d) g[d] = tgt[5 * s + d] + scat[5 * s + d];
+    for (int d = 0; d < 5; ++d) g[d] = tgt[5 * s + d] + scat[d * n + s];
     for (int set = 0; set < 2; ++set) {
         if (set == 1 && !gas) break;
         const double *Ms = set ? M1 : M0;
@@ -776,7 +822,8 @@ __global__ void k_pushdown(int64_t n, int64_t n_gas, const T *__restrict__ xs,
         for (int64_t nd = pleaf[s]; nd >= 0; nd = nparent[nd]) {
             const double Mn = Ms[nd];
             if (!(Mn > 0.0)) continue;
-            const double *a10 = ad + 10 * nd;
+            double a10[10];
+            for (int c = 0; c < 10; ++c) a10[c] = ad[c * nn + nd];
             const double y0 = x[0] - cs[3 * nd], y1 = x[1] - cs[3 * nd + 1], y2 = x[2] - cs[3 * nd + 2];
             const double gxx = a10[4], gyy = a10[5], gzz = a10[6], gxy = a10[7], gxz = a10[8],
                          gyz = a10[9];
@@ -840,8 +887,10 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
     a.tgt = tgt;
     a.scat = scat;
     a.nadj = nadj;
+    a.scat_stride = 5 * t->n;
+    a.nadj_stride = 10 * t->n_nodes;
     a.task_ctr = ctr;
-    a.err = ctr + 2;
+    a.err = ctr + kCtrErr;
     return a;
 }
 
@@ -855,7 +904,8 @@ static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_a
     hipLaunchKernelGGL((k_walk_groups_b<T, FORM, ORDER>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 8);
     if (t->n_sink > 0) {
-        WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + 1);
+        WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + kCtrSinks);
+        as.err = ctr + kCtrErr;
         const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
         phase_begin(t, 9);
         hipLaunchKernelGGL((k_walk_sinks_b<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
@@ -871,16 +921,16 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     const int64_t n = t->n, nn = t->n_nodes;
     int32_t *ctr;
     double *tgt, *scat, *nadj0, *nadj1, *ssb = nullptr;
-    SF_ALLOC_TMP(ar, ctr, 4);
+    SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, tgt, 5 * n);
-    SF_ALLOC_TMP(ar, scat, 5 * n);
-    SF_ALLOC_TMP(ar, nadj0, 10 * nn);
-    SF_ALLOC_TMP(ar, nadj1, 10 * nn);
-    fill_u32((uint32_t *)ctr, 4, 0u, s);
+    SF_ALLOC_TMP(ar, scat, kXcd * 5 * n);
+    SF_ALLOC_TMP(ar, nadj0, kXcd * 10 * nn);
+    SF_ALLOC_TMP(ar, nadj1, kXcd * 10 * nn);
+    fill_u32((uint32_t *)ctr, kCtrWords, 0u, s);
     fill_u32((uint32_t *)tgt, 10 * n, 0u, s);
-    fill_u32((uint32_t *)scat, 10 * n, 0u, s);
-    fill_u32((uint32_t *)nadj0, 20 * nn, 0u, s);
-    fill_u32((uint32_t *)nadj1, 20 * nn, 0u, s);
+    fill_u32((uint32_t *)scat, kXcd * 10 * n, 0u, s);
+    fill_u32((uint32_t *)nadj0, kXcd * 20 * nn, 0u, s);
+    fill_u32((uint32_t *)nadj1, kXcd * 20 * nn, 0u, s);
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
         phase_begin(t, 7);
@@ -899,15 +949,20 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     }
 #undef SF_WB
     phase_begin(t, 10);
+    const unsigned rb = (unsigned)std::min<int64_t>(8192, (10 * nn + 255) / 256);
+    hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, scat, (int64_t)5 * n);
+    hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj0, (int64_t)10 * nn);
+    if (t->n_sink > 0)
+        hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj1, (int64_t)10 * nn);
     hipLaunchKernelGGL(k_pushdown<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       t->n_gas, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
+                       t->n_gas, nn, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
                        (const T *)t->ms, t->order, t->pleaf, t->nparent, t->M[0], t->com[0],
                        t->M[1], t->com[1], nadj0, nadj1, tgt, scat, t->sink_pos, t->n_sink, ssb,
                        o.G, (T *)g_pos, (T *)g_mass, (T *)g_soft);
     phase_end(t, 10);
     SF_HIP(hipGetLastError());
     int32_t herr = 0;
-    SF_HIP(hipMemcpyAsync(&herr, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     SF_HIP(hipStreamSynchronize(s));
     if (herr)
         return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);

@@ -89,9 +89,12 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
         const R t = R(0.5) * rqr * ri5;
         bp -= Mri + t;
         const R c = -(Mri + R(5) * t) * ri2;
-        bx += c * rx + ri5 * qx;
-        by += c * ry + ri5 * qy;
-        bz += c * rz + ri5 * qz;
+        bx = fma(c, rx, bx);
+        by = fma(c, ry, by);
+        bz = fma(c, rz, bz);
+        bx = fma(ri5, qx, bx);
+        by = fma(ri5, qy, by);
+        bz = fma(ri5, qz, bz);
     }
 }
 
@@ -145,6 +148,21 @@ __device__ __forceinline__ int next_task(int32_t *ctr) {
     if ((threadIdx.x & 63) == 0) g = atomicAdd(ctr, 1);
     return __builtin_amdgcn_readfirstlane(g);
 }
+
+// XCD (the L2 domain, one of 8 on MI355X) of the executing wave, read from
+// the hardware register XCC_ID.  Used only to place work and scratch copies
+// near an L2; no result depends on its value.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcd - 1);   // hwreg(XCC_ID, 0, 4)
+}
+
+// Task counters: the group-task counter, the sink-task counter and the error
+// word, 64 bytes apart.
+constexpr int kCtrStride = 16;
+constexpr int kCtrSinks = kCtrStride;
+constexpr int kCtrErr = kCtrSinks + kCtrStride;
+constexpr int kCtrWords = kCtrErr + kCtrStride;
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll

@@ -52,6 +52,13 @@ struct WalkArgs {
 
 // ---------------------------------------------------------------- group mode
 
+// Batch staging for lane splitting: entry e of a batch (e < nb <= 64) goes to
+// LDS slot (e mod k) m + e / k with m = ceil(nb / k), so copy `sub` finds its
+// entries sub, sub + k, ... in the consecutive slots [sub m, sub m + m) and
+// every lane runs the same m steps.  Slots of entries e in [nb, k m) hold
+// zero-mass dummies far away, whose terms are exactly zero.
+constexpr float kFar = 1e30f;
+
 template <typename T, int FORM, int ORDER>
 struct GroupEval {
     using R = typename FormT<FORM>::R;
@@ -61,32 +68,40 @@ struct GroupEval {
     double cen[3];
     R tx, ty, tz, th, th2;
     int32_t tidx;
-    uint32_t sub, k;            // lane splitting: lane handles sources sub, sub+k, ...
+    uint32_t sub, k;            // lane splitting: lane handles entries sub, sub+k, ...
     Acc<FORM> ax, ay, az, ap;
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
-        const int lane = threadIdx.x;
-        if ((uint32_t)lane < nb) {
-            const int node = L.pc[(head + lane) & 127];
-            const WalkNodes &nd = a->nd;
+        const uint32_t e = threadIdx.x;
+        const uint32_t m = (nb + k - 1) / k;
+        if (e < k * m) {
             PCStage<R> s;
-            s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
-            s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
-            s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
-            s.M = (R)nd.w[node].M;
-            if (ORDER == 2) {
-                s.qxx = (R)nd.q[node].q[0];
-                s.qyy = (R)nd.q[node].q[1];
-                s.qxy = (R)nd.q[node].q[2];
-                s.qxz = (R)nd.q[node].q[3];
-                s.qyz = (R)nd.q[node].q[4];
+            if (e < nb) {
+                const int node = L.pc[(head + e) & 127];
+                const WalkNodes &nd = a->nd;
+                s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+                s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+                s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+                s.M = (R)nd.w[node].M;
+                s.qxx = s.qyy = s.qxy = s.qxz = s.qyz = R(0);
+                if (ORDER == 2) {
+                    s.qxx = (R)nd.q[node].q[0];
+                    s.qyy = (R)nd.q[node].q[1];
+                    s.qxy = (R)nd.q[node].q[2];
+                    s.qxz = (R)nd.q[node].q[3];
+                    s.qyz = (R)nd.q[node].q[4];
+                }
+            } else {
+                s.x = s.y = s.z = R(kFar);
+                s.M = s.qxx = s.qyy = s.qxy = s.qxz = s.qyz = R(0);
             }
-            spc[lane] = s;
+            spc[(e % k) * m + e / k] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        for (uint32_t j = sub; j < nb; j += k) {
-            const PCStage<R> s = spc[j];
+        const PCStage<R> *src = spc + sub * m;
+        for (uint32_t j = 0; j < m; ++j) {
+            const PCStage<R> s = src[j];
             multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
                                 s.qyz, bx, by, bz, bp);
         }
@@ -99,23 +114,31 @@ struct GroupEval {
 
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
-        const int lane = threadIdx.x;
-        if ((uint32_t)lane < nb) {
-            const int p = L.slot[lane];
+        const uint32_t e = threadIdx.x;
+        const uint32_t m = (nb + k - 1) / k;
+        if (e < k * m) {
             PPStage<R> s;
-            s.x = to_frame<FORM>(a->xs[p], cen[0]);
-            s.y = to_frame<FORM>(a->ys[p], cen[1]);
-            s.z = to_frame<FORM>(a->zs[p], cen[2]);
-            s.m = (R)a->ms[p];
-            s.h = (R)a->hs[p];
-            s.h2 = s.h * s.h;
-            s.idx = p;
-            spp[lane] = s;
+            if (e < nb) {
+                const int p = L.slot[e];
+                s.x = to_frame<FORM>(a->xs[p], cen[0]);
+                s.y = to_frame<FORM>(a->ys[p], cen[1]);
+                s.z = to_frame<FORM>(a->zs[p], cen[2]);
+                s.m = (R)a->ms[p];
+                s.h = (R)a->hs[p];
+                s.h2 = s.h * s.h;
+                s.idx = p;
+            } else {
+                s.x = s.y = s.z = R(kFar);
+                s.m = s.h = s.h2 = R(0);
+                s.idx = -1;
+            }
+            spp[(e % k) * m + e / k] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        for (uint32_t j = sub; j < nb; j += k) {
-            const PPStage<R> s = spp[j];
+        const PPStage<R> *src = spp + sub * m;
+        for (uint32_t j = 0; j < m; ++j) {
+            const PPStage<R> s = src[j];
             if (SOFT)
                 pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx,
                         by, bz, bp);
@@ -395,7 +418,7 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     a.n_sink = t->n_sink;
     a.ss = ss;
     a.task_ctr = ctr;
-    a.err = ctr + 2;
+    a.err = ctr + kCtrErr;
     a.gnpc = t->gnpc;
     a.gnpp = t->gnpp;
     a.acc = (T *)acc;
@@ -416,7 +439,8 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, false>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 5);
     if (t->n_sink > 0) {
-        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + 1, ss);
+        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss);
+        as.err = ctr + kCtrErr;
         const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
         phase_begin(t, 6);
         hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
@@ -443,8 +467,8 @@ static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
     int32_t *ctr = nullptr;
     double *ss = nullptr;
-    SF_ALLOC_TMP(ar, ctr, 4);
-    fill_u32((uint32_t *)ctr, 4, 0u, t->stream);
+    SF_ALLOC_TMP(ar, ctr, kCtrWords);
+    fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
         phase_begin(t, 4);
@@ -467,7 +491,7 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     else dispatch_walks<double>(t, o, acc, pot, ctr, ss);
     SF_HIP(hipGetLastError());
     int32_t herr = 0;
-    SF_HIP(hipMemcpyAsync(&herr, ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));
     SF_HIP(hipStreamSynchronize(t->stream));
     if (herr)
         return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);

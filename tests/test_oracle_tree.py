@@ -248,3 +248,22 @@ def test_tree_adjoint_matches_frozen_list_differences():
             lm = _tree_loss(ps, lists, ga, gp, 2, torch.tensor(ps.x), torch.tensor(mm), torch.tensor(ps.h))
         fd = float(lp - lm) / (2 * eps)
         assert fd == pytest.approx(float(mt.grad[k]), rel=1e-5, abs=1e-7 * float(mt.grad.abs().max()))
+
+
+def test_lazy_moments_equal_eager_and_lists_agree():
+    # the lazily computed moments are the same sums; walks over a few groups
+    # give the same lists either way
+    ps = clustered_cloud(6000, 20, seed=21, dtype=np.float64)
+    tree = T.build_tree(ps.x, 16)
+    eager = T.node_moments(tree, ps.x, ps.m, ps.h)
+    lazy = T.LazyMoments(tree, ps.x, ps.m, ps.h)
+    idx = np.array([0, 5, 17, tree.n_nodes - 1, 5])
+    for name in ("M", "com", "Q", "hmax"):
+        assert np.array_equal(lazy[name][idx], eager[name][idx])
+    sel = [0, 3, 11]
+    a = T.tree_lists(ps.x, ps.m, ps.h, ps.n_gas, groups_sel=sel)
+    b = T.tree_lists(ps.x, ps.m, ps.h, ps.n_gas, groups_sel=sel, lazy=True)
+    assert a.gas_lists.keys() == b.gas_lists.keys()
+    for g in a.gas_lists:
+        for u, v in zip(a.gas_lists[g], b.gas_lists[g]):
+            assert np.array_equal(u, v)
