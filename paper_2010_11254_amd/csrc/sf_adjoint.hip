@@ -329,6 +329,8 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
 
 // Pair (target i, source j), d = x_j - x_i: S = dT/dx_j (target gets -S),
 // Tm = dT/dm_j, Th = dT/dh_ij, share_i = part of Th owned by the target.
+// With F(r) the force factor, S = m_j (F a + (a.d F'/r + phi F) d) for
+// cotangents a (acceleration) and phi (potential).
 template <typename R, bool SOFT = true>
 __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2, R hi, R gax,
                                       R gay, R gaz, R gp, bool self, R &Sx, R &Sy, R &Sz, R &Tm,
@@ -336,41 +338,56 @@ __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2
     const R r2 = dx * dx + dy * dy + dz * dz;
     const R ri = rsq(r2);
     const R ri2 = ri * ri;
-    R F = ri * ri2, P = ri, FrR = R(-3) * F * ri2, dFh = R(0), dPh = R(0);
-    const R hh2 = hj2 > hi2 ? hj2 : hi2;
-    const bool soft = SOFT && r2 < hh2;
-    if (soft) {
-        dsoft<R>(r2, hj > hi ? hj : hi, F, P, FrR, dFh, dPh);
-        if (self) { F = R(0); P = R(0); FrR = R(0); dFh = R(0); dPh = R(0); }
-    }
     const R ad = gax * dx + gay * dy + gaz * dz;
-    const R c1 = ad * FrR + gp * F;
-    Sx = mj * (F * gax + c1 * dx);
-    Sy = mj * (F * gay + c1 * dy);
-    Sz = mj * (F * gaz + c1 * dz);
-    Tm = ad * F - gp * P;
-    Th = soft ? mj * (ad * dFh - gp * dPh) : R(0);
+    R F = ri * ri2, P = ri, mc1;
+    Th = R(0);
+    if (!SOFT) {
+        // Newtonian: F'/r = -3 F / r^2
+        const R mF = mj * F;
+        mc1 = mF * fma(ad * ri2, R(-3), gp);
+        Sx = fma(mc1, dx, mF * gax);
+        Sy = fma(mc1, dy, mF * gay);
+        Sz = fma(mc1, dz, mF * gaz);
+    } else {
+        R FrR = R(-3) * F * ri2, dFh = R(0), dPh = R(0);
+        const R hh2 = hj2 > hi2 ? hj2 : hi2;
+        const bool soft = r2 < hh2;
+        if (soft) {
+            dsoft<R>(r2, hj > hi ? hj : hi, F, P, FrR, dFh, dPh);
+            if (self) { F = R(0); P = R(0); FrR = R(0); dFh = R(0); dPh = R(0); }
+            Th = mj * (ad * dFh - gp * dPh);
+        }
+        const R mF = mj * F;
+        mc1 = mj * fma(ad, FrR, gp * F);
+        Sx = fma(mc1, dx, mF * gax);
+        Sy = fma(mc1, dy, mF * gay);
+        Sz = fma(mc1, dz, mF * gaz);
+    }
+    Tm = fma(ad, F, -gp * P);
     share_i = hi > hj ? R(1) : (hi == hj ? R(0.5) : R(0));
 }
 
 // Node term, r = x_i - c: g = dL/dr (the centre of mass gets -g), gM = dL/dM,
-// gs = symmetric dL/dQ (xx yy zz xy xz yz; zero for monopoles).
+// gq = dL/dQ as 5 numbers (xx - zz, yy - zz, xy, xz, yz; zero for monopoles).
+// Q is traceless, so dL/dQ matters only up to a multiple of the identity;
+// the zz component is removed by subtracting gzz I.
 template <typename R, int ORDER>
 __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz,
                                            R qyz, R gax, R gay, R gaz, R gp, R &gx, R &gy,
-                                           R &gz, R &gM, R gs[6]) {
+                                           R &gz, R &gM, R gq[5]) {
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R ri = rsq(r2);
     const R ri2 = ri * ri;
     const R ri3 = ri * ri2;
     const R ri5 = ri3 * ri2;
     const R ra = rx * gax + ry * gay + rz * gaz;
-    gM = -ra * ri3 - gp * ri;
-    // monopole part: -M ri3 a + 3 M ra ri5 r + gp M ri3 r
-    const R cr = R(3) * M * ra * ri5 + gp * M * ri3;
-    gx = -M * ri3 * gax + cr * rx;
-    gy = -M * ri3 * gay + cr * ry;
-    gz = -M * ri3 * gaz + cr * rz;
+    gM = -fma(ra, ri3, gp * ri);
+    // monopole part: -M ri3 a + (3 M ra ri5 + gp M ri3) r
+    const R Mri3 = M * ri3;
+    const R cr = M * fma(R(3) * ra, ri5, gp * ri3);
+    gx = fma(cr, rx, -Mri3 * gax);
+    gy = fma(cr, ry, -Mri3 * gay);
+    gz = fma(cr, rz, -Mri3 * gaz);
     if (ORDER == 2) {
         const R qzz = -(qxx + qyy);
         const R qx = qxx * rx + qxy * ry + qxz * rz;
@@ -382,25 +399,25 @@ __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, 
         const R q = qx * rx + qy * ry + qz * rz;
         const R aQr = gax * qx + gay * qy + gaz * qz;
         const R ri7 = ri5 * ri2;
-        const R ri9 = ri7 * ri2;
         // + ri5 Qa - 5 aQr ri7 r - 5 ra ri7 Qr - 2.5 q ri7 a + 17.5 q ra ri9 r
         // - gp ri5 Qr + 2.5 gp q ri7 r
-        const R cr2 = R(-5) * aQr * ri7 + R(17.5) * q * ra * ri9 + R(2.5) * gp * q * ri7;
-        const R cq = R(-5) * ra * ri7 - gp * ri5;
+        const R cr2 = ri7 * fma(R(17.5) * q * ra, ri2, fma(R(2.5) * gp, q, R(-5) * aQr));
+        const R cq = fma(R(-5) * ra, ri7, -gp * ri5);
         const R ca = R(-2.5) * q * ri7;
-        gx += ri5 * Qax + cr2 * rx + cq * qx + ca * gax;
-        gy += ri5 * Qay + cr2 * ry + cq * qy + ca * gay;
-        gz += ri5 * Qaz + cr2 * rz + cq * qz + ca * gaz;
-        const R k = R(2.5) * ra * ri7 + R(0.5) * gp * ri5;
+        gx = fma(ri5, Qax, fma(cr2, rx, fma(cq, qx, fma(ca, gax, gx))));
+        gy = fma(ri5, Qay, fma(cr2, ry, fma(cq, qy, fma(ca, gay, gy))));
+        gz = fma(ri5, Qaz, fma(cr2, rz, fma(cq, qz, fma(ca, gaz, gz))));
+        // dL/dQ = h5 (a r^T + r a^T) - k r r^T (diagonal: ri5 a_d r_d - k r_d^2)
+        const R k = fma(R(2.5) * ra, ri7, R(0.5) * gp * ri5);
         const R h5 = R(0.5) * ri5;
-        gs[0] = gax * rx * ri5 - k * rx * rx;
-        gs[1] = gay * ry * ri5 - k * ry * ry;
-        gs[2] = gaz * rz * ri5 - k * rz * rz;
-        gs[3] = h5 * (gax * ry + gay * rx) - k * rx * ry;
-        gs[4] = h5 * (gax * rz + gaz * rx) - k * rx * rz;
-        gs[5] = h5 * (gay * rz + gaz * ry) - k * ry * rz;
+        const R gzz = fma(gaz * rz, ri5, -k * rz * rz);
+        gq[0] = fma(gax * rx, ri5, -k * rx * rx) - gzz;
+        gq[1] = fma(gay * ry, ri5, -k * ry * ry) - gzz;
+        gq[2] = fma(h5, fma(gax, ry, gay * rx), -k * rx * ry);
+        gq[3] = fma(h5, fma(gax, rz, gaz * rx), -k * rx * rz);
+        gq[4] = fma(h5, fma(gay, rz, gaz * ry), -k * ry * rz);
     } else {
-        for (int d = 0; d < 6; ++d) gs[d] = R(0);
+        for (int d = 0; d < 5; ++d) gq[d] = R(0);
     }
 }
 
@@ -420,162 +437,182 @@ struct WalkArgsB {
     // node k at c n_nodes + k) so that a batch's 64 adds to one component
     // fall into a few cache lines; kXcd copies each.
     double *scat;               // 5 per sorted particle: source side (x y z m h)
-    double *nadj;               // 10 per node: M, c(3), dQ(6)
+    double *nadj;               // 9 per node: M, c(3), dQ(5)
     int64_t scat_stride, nadj_stride;   // elements between copies
     int32_t *task_ctr, *err;
 };
 
 // Per-lane target of the group adjoint.
-template <typename R> struct TgtB { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx; bool act; };
+template <typename R> struct TgtB { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx; };
 
-// LDS accumulation of one batch's source-side terms: the lanes of a step hold
-// distinct batch entries wherever the group is large enough, so these adds
-// rarely collide; they are LDS atomics, so collisions only cost time.  The
-// accumulators are FP64 in every form: FP64 LDS adds measured several times
-// faster than FP32 ones on gfx950 (and keep the batch sums exact enough).
+// LDS accumulation of one batch's entry-side terms.  The accumulators are
+// FP64 in every form: FP64 LDS adds measured several times faster than FP32
+// ones on gfx950 (and keep the batch sums exact enough).
 __device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Positions of staged dummy entries and of lanes that take no part (no
+// target, or a sink target): far enough that every term with them vanishes
+// or underflows, near enough that no square or quadrupole product overflows
+// FP32.
+constexpr float kFarB = 1e15f;
+constexpr float kFarT = -1e15f;
+
 // Group tasks, one pass per batch: each (target, entry) term is evaluated
 // once and split into its target side (kept in the lane's registers) and its
 // entry side (added to the entry's LDS accumulator, flushed to the global
-// FP64 adjoint arrays once per batch).  Lane splitting as in the forward
-// walk: a group of gc targets uses W = next power of two >= gc lanes per
-// copy and k = 64 / W copies; copy `sub` takes the entries sub, sub + k, ...
-// of a batch, visited from a per-target rotation so that the lanes of a
-// copy sit on different entries in every step.
+// FP64 adjoint arrays once per batch).
+//
+// Lane splitting as in the forward walk: a group of gc targets uses W = next
+// power of two >= gc lanes per copy and k = 64 / W copies.  A batch of nb
+// entries is padded to k m entries, m = next power of two >= ceil(nb / k),
+// and entry e is staged in slot (e mod k) m + e / k, so copy `sub` owns the
+// slots [sub m, sub m + m).  In step s its lane for target t takes slot
+// sub m + ((t mod m) xor s): over the m steps every lane meets every slot of
+// its copy once, and within a step lanes of different t mod m sit on
+// different slots, so the LDS adds of a step rarely collide (and stay exact
+// when they do).  Padding entries are zero-mass dummies far away; lanes
+// without a target (or with a sink target) sit far away on the other side
+// with zero cotangents, so both contribute exact zeros to every real sum,
+// and no step needs a predicate.
 template <typename T, int FORM, int ORDER>
 struct GroupEvalB {
     using R = typename FormT<FORM>::R;
     const WalkArgsB<T> *a;
     // Batch entries staged structure-of-arrays: the lanes of a step read
-    // different entries, and one component of consecutive entries sits in
+    // different slots, and one component of consecutive slots sits in
     // consecutive LDS words, so those reads are free of bank conflicts.
     R (*stg)[64];               // [9][64]: x y z m|M, then h2 h (pairs) or Q (nodes)
     int32_t *sidx;              // [64] particle index of a pair entry
-    double (*bacc)[64];         // [10][64] entry-side accumulators
+    double (*bacc)[64];         // [9][64] entry-side accumulators, by slot
     double *scat, *nadj;        // this XCD's copies of the atomic arrays
     double cen[3];
     TgtB<R> me;
     uint32_t tl, sub, k;
     Acc<FORM> ox, oy, oz, oh;
 
-    // Steps of a batch of nb entries for this lane's copy: m = ceil((nb - sub) / k)
-    // slots, slot q holds entry sub + k q; the lane starts at slot tl mod m.
-    __device__ __forceinline__ uint32_t slots(uint32_t nb) const {
-        return (nb + k - 1) / k;   // uniform: the largest copy's count
+    __device__ __forceinline__ uint32_t pad_steps(uint32_t nb) const {
+        const uint32_t c = (nb + k - 1) / k;
+        uint32_t m = 1;
+        while (m < c) m <<= 1;
+        return m;   // k m <= 64: k divides 64 and k ceil(nb/k) <= 64
     }
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
-        const int lane = threadIdx.x;
+        const uint32_t e = threadIdx.x;
+        const uint32_t m = pad_steps(nb);
+        const uint32_t slot = (e % k) * m + e / k;
         int node = -1;
-        if ((uint32_t)lane < nb) {
-            node = L.pc[(head + lane) & 127];
-            const WalkNodes &nd = a->nd;
-            stg[0][lane] = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
-            stg[1][lane] = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
-            stg[2][lane] = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
-            stg[3][lane] = (R)nd.w[node].M;
-            if (ORDER == 2)
-                for (int d = 0; d < 5; ++d) stg[4 + d][lane] = (R)nd.q[node].q[d];
+        if (e < k * m) {
+            if (e < nb) {
+                node = L.pc[(head + e) & 127];
+                const WalkNodes &nd = a->nd;
+                stg[0][slot] = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+                stg[1][slot] = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+                stg[2][slot] = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+                stg[3][slot] = (R)nd.w[node].M;
+                if (ORDER == 2)
+                    for (int d = 0; d < 5; ++d) stg[4 + d][slot] = (R)nd.q[node].q[d];
+            } else {
+                stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
+                for (int d = 3; d < 9; ++d) stg[d][slot] = R(0);
+            }
         }
         __syncthreads();
-        const uint32_t m = slots(nb);
-        uint32_t q = tl % m;
+        const uint32_t base = sub * m, t0 = tl & (m - 1);
         R bx = 0, by = 0, bz = 0;
         for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = sub + k * q;
-            if (me.act && j < nb) {
-                R q5[5] = {R(0), R(0), R(0), R(0), R(0)};
-                if (ORDER == 2)
-                    for (int d = 0; d < 5; ++d) q5[d] = stg[4 + d][j];
-                R gx, gy, gz, gM, gs[6];
-                bmultipole<R, ORDER>(me.x - stg[0][j], me.y - stg[1][j], me.z - stg[2][j],
-                                     stg[3][j], q5[0], q5[1], q5[2], q5[3], q5[4], me.gx, me.gy,
-                                     me.gz, me.gp, gx, gy, gz, gM, gs);
-                bx += gx;
-                by += gy;
-                bz += gz;
-                lds_add(&bacc[0][j], (double)(gM));
-                lds_add(&bacc[1][j], (double)(-gx));
-                lds_add(&bacc[2][j], (double)(-gy));
-                lds_add(&bacc[3][j], (double)(-gz));
-                if (ORDER == 2)
-                    for (int d = 0; d < 6; ++d) lds_add(&bacc[4 + d][j], (double)(gs[d]));
-            }
-            q = q + 1 == m ? 0 : q + 1;
+            const uint32_t j = base + (t0 ^ s);
+            R q5[5] = {R(0), R(0), R(0), R(0), R(0)};
+            if (ORDER == 2)
+                for (int d = 0; d < 5; ++d) q5[d] = stg[4 + d][j];
+            R gx, gy, gz, gM, gq[5];
+            bmultipole<R, ORDER>(me.x - stg[0][j], me.y - stg[1][j], me.z - stg[2][j], stg[3][j],
+                                 q5[0], q5[1], q5[2], q5[3], q5[4], me.gx, me.gy, me.gz, me.gp,
+                                 gx, gy, gz, gM, gq);
+            bx += gx;
+            by += gy;
+            bz += gz;
+            lds_add(&bacc[0][j], (double)gM);
+            lds_add(&bacc[1][j], (double)-gx);
+            lds_add(&bacc[2][j], (double)-gy);
+            lds_add(&bacc[3][j], (double)-gz);
+            if (ORDER == 2)
+                for (int d = 0; d < 5; ++d) lds_add(&bacc[4 + d][j], (double)gq[d]);
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
         __syncthreads();
-        if ((uint32_t)lane < nb) {
+        const int nv = ORDER == 2 ? 9 : 4;
+        if (e < nb) {
             const int64_t nn = a->nd.n_nodes;
-            const int nv = ORDER == 2 ? 10 : 4;
-            for (int d = 0; d < nv; ++d) {
-                atomic_add_f64(nadj + d * nn + node, bacc[d][lane]);
-                bacc[d][lane] = 0.0;
-            }
+            for (int d = 0; d < nv; ++d) atomic_add_f64(nadj + d * nn + node, bacc[d][slot]);
         }
+        __syncthreads();
+        for (int d = 0; d < nv; ++d) bacc[d][e] = 0.0;
         __syncthreads();
     }
 
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
-        const int lane = threadIdx.x;
+        const uint32_t e = threadIdx.x;
+        const uint32_t m = pad_steps(nb);
+        const uint32_t slot = (e % k) * m + e / k;
         int p = -1;
-        if ((uint32_t)lane < nb) {
-            p = L.slot[lane];
-            stg[0][lane] = to_frame<FORM>(a->xs[p], cen[0]);
-            stg[1][lane] = to_frame<FORM>(a->ys[p], cen[1]);
-            stg[2][lane] = to_frame<FORM>(a->zs[p], cen[2]);
-            stg[3][lane] = (R)a->ms[p];
-            const R h = (R)a->hs[p];
-            stg[4][lane] = h * h;
-            stg[5][lane] = h;
-            sidx[lane] = p;
+        if (e < k * m) {
+            if (e < nb) {
+                p = L.slot[e];
+                stg[0][slot] = to_frame<FORM>(a->xs[p], cen[0]);
+                stg[1][slot] = to_frame<FORM>(a->ys[p], cen[1]);
+                stg[2][slot] = to_frame<FORM>(a->zs[p], cen[2]);
+                stg[3][slot] = (R)a->ms[p];
+                const R h = (R)a->hs[p];
+                stg[4][slot] = h * h;
+                stg[5][slot] = h;
+                sidx[slot] = p;
+            } else {
+                stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
+                stg[3][slot] = stg[4][slot] = stg[5][slot] = R(0);
+                sidx[slot] = -1;
+            }
         }
         __syncthreads();
-        const uint32_t m = slots(nb);
-        uint32_t q = tl % m;
+        const uint32_t base = sub * m, t0 = tl & (m - 1);
         R bx = 0, by = 0, bz = 0, bh = 0;
         for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = sub + k * q;
-            if (me.act && j < nb) {
-                R Sx, Sy, Sz, Tm, Th, sh;
-                const R hj2 = SOFT ? stg[4][j] : R(0), hj = SOFT ? stg[5][j] : R(0);
-                const bool self = SOFT && sidx[j] == me.idx;
-                bpair<R, SOFT>(stg[0][j] - me.x, stg[1][j] - me.y, stg[2][j] - me.z, stg[3][j],
-                               hj2, hj, me.h2, me.h, me.gx, me.gy, me.gz, me.gp, self, Sx, Sy, Sz,
-                               Tm, Th, sh);
-                bx -= Sx;
-                by -= Sy;
-                bz -= Sz;
-                lds_add(&bacc[0][j], (double)(Sx));
-                lds_add(&bacc[1][j], (double)(Sy));
-                lds_add(&bacc[2][j], (double)(Sz));
-                lds_add(&bacc[3][j], (double)(Tm));
-                if (SOFT) {
-                    bh += sh * Th;
-                    lds_add(&bacc[4][j], (double)((R(1) - sh) * Th));
-                }
+            const uint32_t j = base + (t0 ^ s);
+            R Sx, Sy, Sz, Tm, Th, sh;
+            const R hj2 = SOFT ? stg[4][j] : R(0), hj = SOFT ? stg[5][j] : R(0);
+            const bool self = SOFT && sidx[j] == me.idx;
+            bpair<R, SOFT>(stg[0][j] - me.x, stg[1][j] - me.y, stg[2][j] - me.z, stg[3][j], hj2,
+                           hj, me.h2, me.h, me.gx, me.gy, me.gz, me.gp, self, Sx, Sy, Sz, Tm, Th,
+                           sh);
+            bx -= Sx;
+            by -= Sy;
+            bz -= Sz;
+            lds_add(&bacc[0][j], (double)Sx);
+            lds_add(&bacc[1][j], (double)Sy);
+            lds_add(&bacc[2][j], (double)Sz);
+            lds_add(&bacc[3][j], (double)Tm);
+            if (SOFT) {
+                bh += sh * Th;
+                lds_add(&bacc[4][j], (double)((R(1) - sh) * Th));
             }
-            q = q + 1 == m ? 0 : q + 1;
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
         if (SOFT) oh.fold(bh);
         __syncthreads();
-        if ((uint32_t)lane < nb) {
+        const int nv = SOFT ? 5 : 4;
+        if (e < nb) {
             const int64_t n = a->n;
-            const int nv = SOFT ? 5 : 4;
-            for (int d = 0; d < nv; ++d) {
-                atomic_add_f64(scat + d * n + p, bacc[d][lane]);
-                bacc[d][lane] = 0.0;
-            }
+            for (int d = 0; d < nv; ++d) atomic_add_f64(scat + d * n + p, bacc[d][slot]);
         }
+        __syncthreads();
+        for (int d = 0; d < nv; ++d) bacc[d][e] = 0.0;
         __syncthreads();
     }
 };
@@ -586,9 +623,9 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
     __shared__ WalkLds L;
     __shared__ R stg[9][64];
     __shared__ int32_t sidx[64];
-    __shared__ double bacc[10][64];
+    __shared__ double bacc[9][64];
     const int lane = threadIdx.x;
-    for (int d = 0; d < 10; ++d) bacc[d][lane] = 0.0;
+    for (int d = 0; d < 9; ++d) bacc[d][lane] = 0.0;
     const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
     GroupEvalB<T, FORM, ORDER> ev;
     ev.a = &a;
@@ -618,17 +655,22 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
         if (__ballot(active) == 0ull) continue;
         const int64_t o = a.order[i];
         TgtB<R> &me = ev.me;
-        me.x = to_frame<FORM>(a.xs[i], ev.cen[0]);
-        me.y = to_frame<FORM>(a.ys[i], ev.cen[1]);
-        me.z = to_frame<FORM>(a.zs[i], ev.cen[2]);
-        me.h = (R)a.hs[i];
+        if (active) {
+            me.x = to_frame<FORM>(a.xs[i], ev.cen[0]);
+            me.y = to_frame<FORM>(a.ys[i], ev.cen[1]);
+            me.z = to_frame<FORM>(a.zs[i], ev.cen[2]);
+            me.h = (R)a.hs[i];
+            me.gx = (R)a.g_acc[3 * o];
+            me.gy = (R)a.g_acc[3 * o + 1];
+            me.gz = (R)a.g_acc[3 * o + 2];
+            me.gp = a.g_pot ? (R)a.g_pot[o] : R(0);
+            me.idx = (int32_t)i;
+        } else {
+            me.x = me.y = me.z = R(kFarT);
+            me.h = me.gx = me.gy = me.gz = me.gp = R(0);
+            me.idx = -1;
+        }
         me.h2 = me.h * me.h;
-        me.gx = (R)a.g_acc[3 * o];
-        me.gy = (R)a.g_acc[3 * o + 1];
-        me.gz = (R)a.g_acc[3 * o + 2];
-        me.gp = a.g_pot ? (R)a.g_pot[o] : R(0);
-        me.idx = has ? (int32_t)i : -1;
-        me.act = active;
         ev.ox.zero();
         ev.oy.zero();
         ev.oz.zero();
@@ -678,9 +720,9 @@ struct SinkEvalB {
                 qxz = (R)nd.q[node].q[3];
                 qyz = (R)nd.q[node].q[4];
             }
-            R g0, g1, g2, gM, gs[6];
+            R g0, g1, g2, gM, gq[5];
             bmultipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.w[node].M, qxx, qyy, qxy, qxz, qyz,
-                                 gx, gy, gz, gp, g0, g1, g2, gM, gs);
+                                 gx, gy, gz, gp, g0, g1, g2, gM, gq);
             bx = g0;
             by = g1;
             bz = g2;
@@ -690,7 +732,7 @@ struct SinkEvalB {
             atomic_add_f64(nadj + 2 * nn + node, -(double)g1);
             atomic_add_f64(nadj + 3 * nn + node, -(double)g2);
             if (ORDER == 2)
-                for (int d = 0; d < 6; ++d) atomic_add_f64(nadj + (4 + d) * nn + node, (double)gs[d]);
+                for (int d = 0; d < 5; ++d) atomic_add_f64(nadj + (4 + d) * nn + node, (double)gq[d]);
         }
         ox.fold(bx);
         oy.fold(by);
@@ -822,20 +864,21 @@ __global__ void k_pushdown(int64_t n, int64_t n_gas, int64_t nn, const T *__rest
         for (int64_t nd = pleaf[s]; nd >= 0; nd = nparent[nd]) {
             const double Mn = Ms[nd];
             if (!(Mn > 0.0)) continue;
-            double a10[10];
-            for (int c = 0; c < 10; ++c) a10[c] = ad[c * nn + nd];
+            double a9[9];
+            for (int c = 0; c < 9; ++c) a9[c] = ad[c * nn + nd];
             const double y0 = x[0] - cs[3 * nd], y1 = x[1] - cs[3 * nd + 1], y2 = x[2] - cs[3 * nd + 2];
-            const double gxx = a10[4], gyy = a10[5], gzz = a10[6], gxy = a10[7], gxz = a10[8],
-                         gyz = a10[9];
+            // dL/dQ up to a multiple of the identity (zz component 0)
+            const double gxx = a9[4], gyy = a9[5], gzz = 0.0, gxy = a9[6], gxz = a9[7],
+                         gyz = a9[8];
             const double tr = gxx + gyy + gzz;
             const double Gy0 = gxx * y0 + gxy * y1 + gxz * y2;
             const double Gy1 = gxy * y0 + gyy * y1 + gyz * y2;
             const double Gy2 = gxz * y0 + gyz * y1 + gzz * y2;
             const double w = m / Mn;
-            g[0] += w * a10[1] + m * (6.0 * Gy0 - 2.0 * tr * y0);
-            g[1] += w * a10[2] + m * (6.0 * Gy1 - 2.0 * tr * y1);
-            g[2] += w * a10[3] + m * (6.0 * Gy2 - 2.0 * tr * y2);
-            g[3] += a10[0] + (a10[1] * y0 + a10[2] * y1 + a10[3] * y2) / Mn +
+            g[0] += w * a9[1] + m * (6.0 * Gy0 - 2.0 * tr * y0);
+            g[1] += w * a9[2] + m * (6.0 * Gy1 - 2.0 * tr * y1);
+            g[2] += w * a9[3] + m * (6.0 * Gy2 - 2.0 * tr * y2);
+            g[3] += a9[0] + (a9[1] * y0 + a9[2] * y1 + a9[3] * y2) / Mn +
                     3.0 * (y0 * Gy0 + y1 * Gy1 + y2 * Gy2) - (y0 * y0 + y1 * y1 + y2 * y2) * tr;
         }
     }
@@ -888,7 +931,7 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
     a.scat = scat;
     a.nadj = nadj;
     a.scat_stride = 5 * t->n;
-    a.nadj_stride = 10 * t->n_nodes;
+    a.nadj_stride = 9 * t->n_nodes;
     a.task_ctr = ctr;
     a.err = ctr + kCtrErr;
     return a;
@@ -924,13 +967,13 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, tgt, 5 * n);
     SF_ALLOC_TMP(ar, scat, kXcd * 5 * n);
-    SF_ALLOC_TMP(ar, nadj0, kXcd * 10 * nn);
-    SF_ALLOC_TMP(ar, nadj1, kXcd * 10 * nn);
+    SF_ALLOC_TMP(ar, nadj0, kXcd * 9 * nn);
+    SF_ALLOC_TMP(ar, nadj1, kXcd * 9 * nn);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, s);
     fill_u32((uint32_t *)tgt, 10 * n, 0u, s);
     fill_u32((uint32_t *)scat, kXcd * 10 * n, 0u, s);
-    fill_u32((uint32_t *)nadj0, kXcd * 20 * nn, 0u, s);
-    fill_u32((uint32_t *)nadj1, kXcd * 20 * nn, 0u, s);
+    fill_u32((uint32_t *)nadj0, kXcd * 18 * nn, 0u, s);
+    fill_u32((uint32_t *)nadj1, kXcd * 18 * nn, 0u, s);
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
         phase_begin(t, 7);
@@ -951,9 +994,9 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     phase_begin(t, 10);
     const unsigned rb = (unsigned)std::min<int64_t>(8192, (10 * nn + 255) / 256);
     hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, scat, (int64_t)5 * n);
-    hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj0, (int64_t)10 * nn);
+    hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj0, (int64_t)9 * nn);
     if (t->n_sink > 0)
-        hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj1, (int64_t)10 * nn);
+        hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj1, (int64_t)9 * nn);
     hipLaunchKernelGGL(k_pushdown<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        t->n_gas, nn, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
                        (const T *)t->ms, t->order, t->pleaf, t->nparent, t->M[0], t->com[0],

@@ -57,7 +57,7 @@ struct WalkArgs {
 // entries sub, sub + k, ... in the consecutive slots [sub m, sub m + m) and
 // every lane runs the same m steps.  Slots of entries e in [nb, k m) hold
 // zero-mass dummies far away, whose terms are exactly zero.
-constexpr float kFar = 1e30f;
+constexpr float kFar = 1e15f;
 
 template <typename T, int FORM, int ORDER>
 struct GroupEval {
