@@ -95,8 +95,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
-    ap.add_argument("--leaf-cap", type=int, default=16)
-    ap.add_argument("--group-cap", type=int, default=64)
+    ap.add_argument("--leaf-cap", type=int, default=32)
+    ap.add_argument("--group-cap", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "

@@ -83,8 +83,8 @@ typedef struct {
     double G;             /* gravitational constant, default 1              */
     double theta;         /* opening angle theta = L/r, >= 0, default 0.5   */
     int32_t order;        /* node expansion: 0 monopole, 2 quadrupole; def 2 */
-    int32_t leaf_cap;     /* a cell holding more is split, 1..64, default 16 */
-    int32_t group_cap;    /* max targets per walk group, 1..64, default 64  */
+    int32_t leaf_cap;     /* a cell holding more is split, 1..64, default 32 */
+    int32_t group_cap;    /* max targets per walk group, 1..64, default 32  */
     int32_t validate;     /* 1: check finite inputs, h > 0, m >= 0 (one pass) */
     int64_t n_gas;        /* particles [0,n_gas) are gas; default -1 = all   */
     int32_t collect_stats;/* 1: record per-group interaction counts          */

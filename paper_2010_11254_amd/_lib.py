@@ -112,7 +112,7 @@ def _check(status, where):
         raise SfGravError(status, where, msg)
 
 
-def make_opts(form="fp32c", G=1.0, theta=0.5, order=2, leaf_cap=16, group_cap=64,
+def make_opts(form="fp32c", G=1.0, theta=0.5, order=2, leaf_cap=32, group_cap=32,
               validate=False, n_gas=-1, collect_stats=False, timing=False):
     o = sf_grav_opts()
     lib().sf_grav_opts_default(ctypes.byref(o))

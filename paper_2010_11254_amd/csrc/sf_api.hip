@@ -232,8 +232,8 @@ void sf_grav_opts_default(sf_grav_opts *o) {
     o->G = 1.0;
     o->theta = 0.5;
     o->order = 2;
-    o->leaf_cap = 16;
-    o->group_cap = 64;
+    o->leaf_cap = 32;
+    o->group_cap = 32;
     o->validate = 0;
     o->n_gas = -1;
     o->collect_stats = 0;

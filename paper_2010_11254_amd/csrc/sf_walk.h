@@ -29,8 +29,13 @@ struct WalkLds {
     int32_t slot[64];
 };
 
-template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h; int32_t idx, pad0, pad1, pad2; };
-template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz, pad0, pad1, pad2; };
+template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h; int32_t idx; };
+template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz; };
+// One batch is staged at a time, so the particle and node stages share LDS.
+template <typename R> union StageBuf {
+    PPStage<R> pp[64];
+    PCStage<R> pc[64];
+};
 
 // Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
 template <typename R>

@@ -157,14 +157,13 @@ template <typename T, int FORM, int ORDER, bool STATS>
 __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
     using R = typename FormT<FORM>::R;
     __shared__ WalkLds L;
-    __shared__ PPStage<R> spp[64];
-    __shared__ PCStage<R> spc[64];
+    __shared__ StageBuf<R> stage;
     const int lane = threadIdx.x;
     const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
     GroupEval<T, FORM, ORDER> ev;
     ev.a = &a;
-    ev.spp = spp;
-    ev.spc = spc;
+    ev.spp = stage.pp;
+    ev.spc = stage.pc;
     for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
         const int64_t gf = a.gfirst[g], gc = a.gcount[g];
         double blo[3], bhi[3];

@@ -34,7 +34,7 @@ def test_opts_layout_and_defaults():
     from paper_2010_11254_amd import _lib
     o = _lib.make_opts()
     assert o.struct_size == ctypes.sizeof(_lib.sf_grav_opts) == 56
-    assert (o.theta, o.order, o.leaf_cap, o.group_cap, o.form) == (0.5, 2, 16, 64, 0)
+    assert (o.theta, o.order, o.leaf_cap, o.group_cap, o.form) == (0.5, 2, 32, 32, 0)
 
 
 def test_strerror_and_invalid_arguments_without_device():

@@ -142,7 +142,7 @@ def test_autograd_function_tree_backward():
     ps = clustered_cloud(3000, 8, seed=17, dtype=np.float64)
     ga, gp = cotangents(ps.n, seed=17)
     x, m, h = (torch.tensor(v, device="cuda", requires_grad=True) for v in (ps.x, ps.m, ps.h))
-    a, p = gravity(x, m, h, path="tree", form="fp64", n_gas=ps.n_gas)
+    a, p = gravity(x, m, h, path="tree", form="fp64", n_gas=ps.n_gas, leaf_cap=16, group_cap=64)
     ((a * torch.tensor(ga, device="cuda")).sum() + (p * torch.tensor(gp, device="cuda")).sum()).backward()
     ref = oracle_tree_vjp(ps, ga, gp)
     for g, r, name in zip((x.grad, m.grad, h.grad), ref, ("x", "m", "h")):

@@ -1,5 +1,5 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark times (leaf 16, group 64, theta 0.5, quadrupole), on outputs the
+benchmark times (leaf 32, group 32, theta 0.5, quadrupole), on outputs the
 oracle computes one by one (sampled groups and targets), plus properties that
 hold at any size: determinism of the forward pass and translation invariance.
 
@@ -15,6 +15,8 @@ from oracle import tree as otree
 from synth import clustered_cloud, precision_cloud, subsample
 
 pytestmark = pytest.mark.gpu
+
+LEAF, GROUP = 32, 32   # the benchmark's capacities
 
 
 def _lib():
@@ -61,11 +63,11 @@ def _tree_sampled(ps, k_rand, k_sink, seed):
     L = _lib()
     x64, m64, h64 = (v.astype(np.float64) for v in (ps.x, ps.m, ps.h))
     _say("oracle tree lists", ps.n)
-    tree = otree.build_tree(x64, 16)
-    groups = otree.make_groups(tree, 64)
+    tree = otree.build_tree(x64, LEAF)
+    groups = otree.make_groups(tree, GROUP)
     sink_sorted = (tree.order >= ps.n_gas)
     sel = _pick_groups(groups, sink_sorted, k_rand, k_sink, seed)
-    lists = otree.tree_lists(x64, m64, h64, ps.n_gas, 0.5, 16, 64, groups_sel=sel, lazy=True)
+    lists = otree.tree_lists(x64, m64, h64, ps.n_gas, 0.5, LEAF, GROUP, groups_sel=sel, lazy=True)
     tgt = np.concatenate([tree.order[groups[g, 0]:groups[g, 0] + groups[g, 1]] for g in sel])
     t64 = lambda v: torch.as_tensor(v)
     with torch.no_grad():
@@ -75,7 +77,8 @@ def _tree_sampled(ps, k_rand, k_sink, seed):
     for form, arrs in (("fp64", (x64, m64, h64)), ("fp32c", (ps.x, ps.m, ps.h))):
         _say("gpu tree", form, ps.n)
         x, m, h = _dev(*arrs)
-        o = L.make_opts(form=form, n_gas=ps.n_gas, collect_stats=True)
+        o = L.make_opts(form=form, n_gas=ps.n_gas, collect_stats=True, leaf_cap=LEAF,
+                        group_cap=GROUP)
         t = L.sf_grav_build_tree(x, m, h, o)
         a, p = L.sf_grav_accel(t, None, None, None, o)
         torch.cuda.synchronize()
@@ -114,15 +117,15 @@ def test_precision4m_build_bit_exact(c2):
     _say("precision4m build bit-exact")
     L = _lib()
     x, m, h = _dev(c2.x, c2.m, c2.h)
-    t = L.sf_grav_build_tree(x, m, h, L.make_opts(n_gas=c2.n_gas))
-    ref = otree.build_tree(c2.x.astype(np.float64), 16)
+    t = L.sf_grav_build_tree(x, m, h, L.make_opts(n_gas=c2.n_gas, leaf_cap=LEAF, group_cap=GROUP))
+    ref = otree.build_tree(c2.x.astype(np.float64), LEAF)
     assert np.array_equal(L.sf_grav_tree_export(t, "keys").numpy().view(np.uint64), ref.keys)
     assert np.array_equal(L.sf_grav_tree_export(t, "order").numpy(), ref.order)
     for name, arr in [("node_level", ref.level), ("node_first", ref.first),
                       ("node_count", ref.count), ("node_parent", ref.parent),
                       ("node_child", ref.child_first), ("node_nchild", ref.n_child)]:
         assert np.array_equal(L.sf_grav_tree_export(t, name).numpy(), arr), name
-    g = otree.make_groups(ref, 64)
+    g = otree.make_groups(ref, GROUP)
     assert np.array_equal(L.sf_grav_tree_export(t, "group_first").numpy(), g[:, 0])
     assert np.array_equal(L.sf_grav_tree_export(t, "group_count").numpy(), g[:, 1])
     # moments of sampled nodes (every level) against the oracle's sums
