@@ -445,11 +445,6 @@ struct WalkArgsB {
 // Per-lane target of the group adjoint.
 template <typename R> struct TgtB { R x, y, z, h, h2, gx, gy, gz, gp; int32_t idx; };
 
-// LDS accumulation of one batch's entry-side terms.  The accumulators are
-// FP64 in every form: FP64 LDS adds measured several times faster than FP32
-// ones on gfx950 (and keep the batch sums exact enough).
-__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
-
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // Positions of staged dummy entries and of lanes that take no part (no
@@ -459,23 +454,56 @@ __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtom
 constexpr float kFarB = 1e15f;
 constexpr float kFarT = -1e15f;
 
+// Gray code: consecutive values differ in exactly one bit.
+__device__ __forceinline__ uint32_t gray(uint32_t s) { return s ^ (s >> 1); }
+
+// FP64 LDS atomic add (ds_add_f64).
+__device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// LDS for the FP64 form's entry-side sums (none for the FP32 forms).
+template <typename R> struct BAccMem {
+    __device__ double (*ptr())[64] { return nullptr; }
+};
+template <> struct BAccMem<double> {
+    double v[9][64];
+    __device__ double (*ptr())[64] { return v; }
+};
+
+// Value of v in the lane whose byte address (4 x lane) is src.
+__device__ __forceinline__ float lane_take(int src, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_take(int src, double v) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Group tasks, one pass per batch: each (target, entry) term is evaluated
-// once and split into its target side (kept in the lane's registers) and its
-// entry side (added to the entry's LDS accumulator, flushed to the global
-// FP64 adjoint arrays once per batch).
+// once and split into its target side (kept in the registers of the lanes
+// that own the target) and its entry side.
 //
 // Lane splitting as in the forward walk: a group of gc targets uses W = next
 // power of two >= gc lanes per copy and k = 64 / W copies.  A batch of nb
-// entries is padded to k m entries, m = next power of two >= ceil(nb / k),
-// and entry e is staged in slot (e mod k) m + e / k, so copy `sub` owns the
-// slots [sub m, sub m + m).  In step s its lane for target t takes slot
-// sub m + ((t mod m) xor s): over the m steps every lane meets every slot of
-// its copy once, and within a step lanes of different t mod m sit on
-// different slots, so the LDS adds of a step rarely collide (and stay exact
-// when they do).  Padding entries are zero-mass dummies far away; lanes
-// without a target (or with a sink target) sit far away on the other side
-// with zero cotangents, so both contribute exact zeros to every real sum,
-// and no step needs a predicate.
+// entries is padded to 64 = k W entries and entry e is staged in slot
+// (e mod k) W + e / k, so copy `sub` owns the slots [sub W, sub W + W).  In
+// step s (of W) the lane of target t takes slot sub W + (t xor gray(s)): the
+// 64 lanes of a step sit on 64 different slots, and every lane meets every
+// slot of its copy once.  The entry-side sums live in registers and travel
+// with their slot: after step s the lane holding slot j hands it to the lane
+// that takes j in step s + 1, at lane distance gray(s) xor gray(s + 1) (one
+// bit, so it stays within the copy), by one lane shuffle per value.  After
+// the last step the sums are written to LDS by slot and flushed with one
+// FP64 global atomic add per entry and value.  (LDS atomic adds measured
+// slower on gfx950, FP32 ones by an order of magnitude; a read-add-write of
+// LDS records exposes the LDS latency in every step.)  The FP64 form keeps
+// FP64 LDS atomic adds instead: its hand-off needs two shuffles per value,
+// which measured slower than the adds.
+//
+// Padding entries are zero-mass dummies far away; lanes without a target (or
+// with a sink target) sit far away on the other side with zero cotangents,
+// so both contribute exact zeros to every real sum, and no step needs a
+// predicate.
 template <typename T, int FORM, int ORDER>
 struct GroupEvalB {
     using R = typename FormT<FORM>::R;
@@ -483,47 +511,51 @@ struct GroupEvalB {
     // Batch entries staged structure-of-arrays: the lanes of a step read
     // different slots, and one component of consecutive slots sits in
     // consecutive LDS words, so those reads are free of bank conflicts.
+    // After a batch's steps the same rows hold its entry-side sums by slot.
     R (*stg)[64];               // [9][64]: x y z m|M, then h2 h (pairs) or Q (nodes)
     int32_t *sidx;              // [64] particle index of a pair entry
-    double (*bacc)[64];         // [9][64] entry-side accumulators, by slot
+    double (*bacc)[64];         // [9][64] FP64 form: entry-side sums by slot
     double *scat, *nadj;        // this XCD's copies of the atomic arrays
     double cen[3];
     TgtB<R> me;
+    static constexpr bool kShuffle = sizeof(R) == 4;
     uint32_t tl, sub, k;
     Acc<FORM> ox, oy, oz, oh;
 
-    __device__ __forceinline__ uint32_t pad_steps(uint32_t nb) const {
-        const uint32_t c = (nb + k - 1) / k;
-        uint32_t m = 1;
-        while (m < c) m <<= 1;
-        return m;   // k m <= 64: k divides 64 and k ceil(nb/k) <= 64
+    template <int NV>
+    __device__ __forceinline__ void pass_on(R (&acc)[NV], uint32_t s) const {
+        // byte address of lane (this lane xor d) for ds_bpermute
+        const int src = (int)((threadIdx.x ^ (gray(s) ^ gray(s + 1))) << 2);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = lane_take(src, acc[v]);
     }
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        constexpr int NV = ORDER == 2 ? 9 : 4;
         const uint32_t e = threadIdx.x;
-        const uint32_t m = pad_steps(nb);
+        const uint32_t m = 64u / k;
         const uint32_t slot = (e % k) * m + e / k;
         int node = -1;
-        if (e < k * m) {
-            if (e < nb) {
-                node = L.pc[(head + e) & 127];
-                const WalkNodes &nd = a->nd;
-                stg[0][slot] = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
-                stg[1][slot] = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
-                stg[2][slot] = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
-                stg[3][slot] = (R)nd.w[node].M;
-                if (ORDER == 2)
-                    for (int d = 0; d < 5; ++d) stg[4 + d][slot] = (R)nd.q[node].q[d];
-            } else {
-                stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
-                for (int d = 3; d < 9; ++d) stg[d][slot] = R(0);
-            }
+        if (e < nb) {
+            node = L.pc[(head + e) & 127];
+            const WalkNodes &nd = a->nd;
+            stg[0][slot] = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            stg[1][slot] = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            stg[2][slot] = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            stg[3][slot] = (R)nd.w[node].M;
+            for (int d = 0; d < 5; ++d) stg[4 + d][slot] = ORDER == 2 ? (R)nd.q[node].q[d] : R(0);
+        } else {
+            stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
+            for (int d = 3; d < 9; ++d) stg[d][slot] = R(0);
         }
         __syncthreads();
-        const uint32_t base = sub * m, t0 = tl & (m - 1);
+        const uint32_t base = sub * m;
+        R acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = R(0);
         R bx = 0, by = 0, bz = 0;
         for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = base + (t0 ^ s);
+            const uint32_t j = base + (tl ^ gray(s));
             R q5[5] = {R(0), R(0), R(0), R(0), R(0)};
             if (ORDER == 2)
                 for (int d = 0; d < 5; ++d) q5[d] = stg[4 + d][j];
@@ -534,55 +566,82 @@ struct GroupEvalB {
             bx += gx;
             by += gy;
             bz += gz;
-            lds_add(&bacc[0][j], (double)gM);
-            lds_add(&bacc[1][j], (double)-gx);
-            lds_add(&bacc[2][j], (double)-gy);
-            lds_add(&bacc[3][j], (double)-gz);
-            if (ORDER == 2)
-                for (int d = 0; d < 5; ++d) lds_add(&bacc[4 + d][j], (double)gq[d]);
+            if constexpr (kShuffle) {
+                acc[0] += gM;
+                acc[1] -= gx;
+                acc[2] -= gy;
+                acc[3] -= gz;
+                if (ORDER == 2)
+                    for (int d = 0; d < 5; ++d) acc[4 + d] += gq[d];
+                if (s + 1 < m) pass_on<NV>(acc, s);
+            } else {
+                lds_add(&bacc[0][j], (double)gM);
+                lds_add(&bacc[1][j], (double)-gx);
+                lds_add(&bacc[2][j], (double)-gy);
+                lds_add(&bacc[3][j], (double)-gz);
+                if (ORDER == 2)
+                    for (int d = 0; d < 5; ++d) lds_add(&bacc[4 + d][j], (double)gq[d]);
+            }
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
-        __syncthreads();
-        const int nv = ORDER == 2 ? 9 : 4;
-        if (e < nb) {
-            const int64_t nn = a->nd.n_nodes;
-            for (int d = 0; d < nv; ++d) atomic_add_f64(nadj + d * nn + node, bacc[d][slot]);
+        flush<NV>(acc, base, nb, slot, nadj + node, a->nd.n_nodes);
+    }
+
+    // Entry-side sums of a finished batch to the global FP64 arrays: value d
+    // of entry e goes to out_e[d * stride] (out_e = base array + entry index).
+    template <int NV>
+    __device__ __forceinline__ void flush(const R (&acc)[NV], uint32_t base, uint32_t nb,
+                                          uint32_t slot, double *out_e, int64_t stride) {
+        const uint32_t e = threadIdx.x;
+        __syncthreads();   // every lane is done reading the staged entries
+        if constexpr (kShuffle) {
+            const uint32_t held = base + (tl ^ gray(64u / k - 1));
+#pragma unroll
+            for (int v = 0; v < NV; ++v) stg[v][held] = acc[v];
+            __syncthreads();
+            if (e < nb)
+                for (int d = 0; d < NV; ++d) atomic_add_f64(out_e + d * stride, (double)stg[d][slot]);
+        } else {
+            if (e < nb)
+                for (int d = 0; d < NV; ++d) atomic_add_f64(out_e + d * stride, bacc[d][slot]);
+            __syncthreads();
+            for (int d = 0; d < NV; ++d) bacc[d][e] = 0.0;
         }
-        __syncthreads();
-        for (int d = 0; d < nv; ++d) bacc[d][e] = 0.0;
         __syncthreads();
     }
 
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        constexpr int NV = SOFT ? 5 : 4;
         const uint32_t e = threadIdx.x;
-        const uint32_t m = pad_steps(nb);
+        const uint32_t m = 64u / k;
         const uint32_t slot = (e % k) * m + e / k;
         int p = -1;
-        if (e < k * m) {
-            if (e < nb) {
-                p = L.slot[e];
-                stg[0][slot] = to_frame<FORM>(a->xs[p], cen[0]);
-                stg[1][slot] = to_frame<FORM>(a->ys[p], cen[1]);
-                stg[2][slot] = to_frame<FORM>(a->zs[p], cen[2]);
-                stg[3][slot] = (R)a->ms[p];
-                const R h = (R)a->hs[p];
-                stg[4][slot] = h * h;
-                stg[5][slot] = h;
-                sidx[slot] = p;
-            } else {
-                stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
-                stg[3][slot] = stg[4][slot] = stg[5][slot] = R(0);
-                sidx[slot] = -1;
-            }
+        if (e < nb) {
+            p = L.slot[e];
+            stg[0][slot] = to_frame<FORM>(a->xs[p], cen[0]);
+            stg[1][slot] = to_frame<FORM>(a->ys[p], cen[1]);
+            stg[2][slot] = to_frame<FORM>(a->zs[p], cen[2]);
+            stg[3][slot] = (R)a->ms[p];
+            const R h = (R)a->hs[p];
+            stg[4][slot] = h * h;
+            stg[5][slot] = h;
+            sidx[slot] = p;
+        } else {
+            stg[0][slot] = stg[1][slot] = stg[2][slot] = R(kFarB);
+            stg[3][slot] = stg[4][slot] = stg[5][slot] = R(0);
+            sidx[slot] = -1;
         }
         __syncthreads();
-        const uint32_t base = sub * m, t0 = tl & (m - 1);
+        const uint32_t base = sub * m;
+        R acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = R(0);
         R bx = 0, by = 0, bz = 0, bh = 0;
         for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = base + (t0 ^ s);
+            const uint32_t j = base + (tl ^ gray(s));
             R Sx, Sy, Sz, Tm, Th, sh;
             const R hj2 = SOFT ? stg[4][j] : R(0), hj = SOFT ? stg[5][j] : R(0);
             const bool self = SOFT && sidx[j] == me.idx;
@@ -592,28 +651,27 @@ struct GroupEvalB {
             bx -= Sx;
             by -= Sy;
             bz -= Sz;
-            lds_add(&bacc[0][j], (double)Sx);
-            lds_add(&bacc[1][j], (double)Sy);
-            lds_add(&bacc[2][j], (double)Sz);
-            lds_add(&bacc[3][j], (double)Tm);
-            if (SOFT) {
-                bh += sh * Th;
-                lds_add(&bacc[4][j], (double)((R(1) - sh) * Th));
+            if (SOFT) bh += sh * Th;
+            if constexpr (kShuffle) {
+                acc[0] += Sx;
+                acc[1] += Sy;
+                acc[2] += Sz;
+                acc[3] += Tm;
+                if (SOFT) acc[NV - 1] += (R(1) - sh) * Th;
+                if (s + 1 < m) pass_on<NV>(acc, s);
+            } else {
+                lds_add(&bacc[0][j], (double)Sx);
+                lds_add(&bacc[1][j], (double)Sy);
+                lds_add(&bacc[2][j], (double)Sz);
+                lds_add(&bacc[3][j], (double)Tm);
+                if (SOFT) lds_add(&bacc[NV - 1][j], (double)((R(1) - sh) * Th));
             }
         }
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
         if (SOFT) oh.fold(bh);
-        __syncthreads();
-        const int nv = SOFT ? 5 : 4;
-        if (e < nb) {
-            const int64_t n = a->n;
-            for (int d = 0; d < nv; ++d) atomic_add_f64(scat + d * n + p, bacc[d][slot]);
-        }
-        __syncthreads();
-        for (int d = 0; d < nv; ++d) bacc[d][e] = 0.0;
-        __syncthreads();
+        flush<NV>(acc, base, nb, slot, scat + p, a->n);
     }
 };
 
@@ -623,15 +681,16 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
     __shared__ WalkLds L;
     __shared__ R stg[9][64];
     __shared__ int32_t sidx[64];
-    __shared__ double bacc[9][64];
+    __shared__ BAccMem<R> bmem;
     const int lane = threadIdx.x;
-    for (int d = 0; d < 9; ++d) bacc[d][lane] = 0.0;
     const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
     GroupEvalB<T, FORM, ORDER> ev;
     ev.a = &a;
     ev.stg = stg;
     ev.sidx = sidx;
-    ev.bacc = bacc;
+    ev.bacc = bmem.ptr();
+    if (ev.bacc)
+        for (int d = 0; d < 9; ++d) ev.bacc[d][lane] = 0.0;
     const int xcd = xcd_id();
     ev.scat = a.scat + xcd * a.scat_stride;
     ev.nadj = a.nadj + xcd * a.nadj_stride;
