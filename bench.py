@@ -80,6 +80,88 @@ def stored_walk_traffic():
     return rec
 
 
+def fractal_leg(np, torch, L, cpu_targets, cotangents, subsample):
+    """Large run: fractal16m (16,777,216 gas in a 3-level Plummer-in-Plummer
+    hierarchy + 10,000 sinks, seed 4), forward and backward at theta 0.5 and
+    0.7, FP32C against FP64, with the force error on a random target sample."""
+    from synth import fractal_cloud
+    t0 = time.time()
+    ps = fractal_cloud(1 << 24, 5000, 2500, seed=4)
+    log(f"fractal16m: {ps.n} particles generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda", 0)
+    x, m, h = (torch.as_tensor(v).to(dev) for v in (ps.x, ps.m, ps.h))
+    ga, gp = cotangents(ps.n, seed=4, dtype=np.float32)
+    ga, gp = torch.as_tensor(ga).to(dev), torch.as_tensor(gp).to(dev)
+    acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
+    pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
+    sample = subsample(ps.n, cpu_targets, seed=4) if cpu_targets else None
+    ref = None
+    if sample is not None:
+        from oracle import direct as odirect
+        t0 = time.perf_counter()
+        ref, _ = odirect.direct(ps.x.astype(np.float64), ps.m.astype(np.float64),
+                                ps.h.astype(np.float64), targets=sample)
+        log(f"fractal16m oracle: {sample.size} targets in {time.perf_counter() - t0:.1f}s")
+
+    def ev_ms(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "seed": 4}
+    for theta in (0.5, 0.7):
+        for form in ("fp32c", "fp64"):
+            o = L.make_opts(form=form, theta=theta, n_gas=ps.n_gas, collect_stats=True)
+
+            def full():
+                t = L.sf_grav_build_tree(x, m, h, o)
+                L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
+                L.sf_grav_tree_free(t)
+            o.collect_stats = 0
+            step_ms = ev_ms(full, 3)
+            o.collect_stats = 1
+            t = L.sf_grav_build_tree(x, m, h, o)
+            L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
+            torch.cuda.synchronize()
+            r = {"step_ms": step_ms, "accels_per_s": ps.n / (step_ms * 1e-3)}
+            if form == "fp32c":
+                gf = L.sf_grav_tree_export(t, "group_first").numpy().astype(np.int64)
+                gc = L.sf_grav_tree_export(t, "group_count").numpy().astype(np.int64)
+                npc = L.sf_grav_tree_export(t, "group_npc").numpy().astype(np.int64)
+                npp = L.sf_grav_tree_export(t, "group_npp").numpy().astype(np.int64)
+                order = L.sf_grav_tree_export(t, "order").numpy()
+                csum = np.concatenate([[0], np.cumsum(order < ps.n_gas)])
+                active = csum[gf + gc] - csum[gf]
+                r["n_pc"], r["n_pp"] = int((active * npc).sum()), int((active * npp).sum())
+            o.collect_stats = 0
+            r["accel_ms"] = ev_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=acc,
+                                                            pot=pot), 2)
+            if ref is not None:
+                got = acc[torch.as_tensor(sample, device=dev)].double().cpu().numpy()
+                e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+                r["rel_err"] = {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99))}
+            r["backward_ms"] = ev_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga,
+                                                                      gp), 1)
+            r["backward_over_accel"] = r["backward_ms"] / r["accel_ms"]
+            L.sf_grav_tree_free(t)
+            key = f"theta{theta}_{form}"
+            out[key] = r
+            log(f"fractal16m {key}: step {step_ms:.1f} ms, accel {r['accel_ms']:.1f} ms, "
+                f"backward {r['backward_ms']:.1f} ms" +
+                (f", p99 {r['rel_err']['p99']:.2e}" if "rel_err" in r else ""))
+        fl = FLOP_PP * out[f"theta{theta}_fp32c"]["n_pp"] + FLOP_PC[2] * out[f"theta{theta}_fp32c"]["n_pc"]
+        out[f"theta{theta}_fp32c"]["accel_tflops"] = fl / (out[f"theta{theta}_fp32c"]["accel_ms"] * 1e-3) / 1e12
+        out[f"theta{theta}_fp32c_over_fp64"] = (out[f"theta{theta}_fp64"]["step_ms"] /
+                                                out[f"theta{theta}_fp32c"]["step_ms"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +177,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
+    ap.add_argument("--fractal", action="store_true",
+                    help="also run the 16M fractal workload (forward + backward, theta 0.5 and 0.7)")
     ap.add_argument("--leaf-cap", type=int, default=32)
     ap.add_argument("--group-cap", type=int, default=32)
     args = ap.parse_args()
@@ -342,6 +426,11 @@ def main():
         line["rel_err"] = errs
         if "tree_fp32c" in errs:
             line["rel_err_fp32c"] = errs["tree_fp32c"]
+    if args.fractal:
+        del x, m, h, acc, pot
+        torch.cuda.empty_cache()
+        line["fractal16m"] = fractal_leg(np, torch, L, 0 if args.no_cpu else 2048, cotangents,
+                                         subsample)
     print(json.dumps(line), flush=True)
 
 
