@@ -368,9 +368,13 @@ __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2
 }
 
 // Node term, r = x_i - c: g = dL/dr (the centre of mass gets -g), gM = dL/dM,
-// gq = dL/dQ as 5 numbers (xx - zz, yy - zz, xy, xz, yz; zero for monopoles).
-// Q is traceless, so dL/dQ matters only up to a multiple of the identity;
-// the zz component is removed by subtracting gzz I.
+// gq = dL/dQ as 5 numbers (zero for monopoles): Q is traceless, so dL/dQ
+// matters only up to a multiple of the identity, and with G = dL/dQ written
+// as (w r^T + r w^T) / 2, w = r^-5 a - k r, the numbers are
+// G_xx - G_zz, G_yy - G_zz, 2 G_xy, 2 G_xz, 2 G_yz.
+// With the forward term phi = -M/r - s/(2 r^5), a = -M r/r^3 + q/r^5
+// - 5 s r/(2 r^7) (q = Q r, s = r.q) and L = a_bar.a + phi_bar phi:
+//   g = c_r r + c_a a_bar + c_q q + Q a_bar / r^5.
 template <typename R, int ORDER>
 __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz,
                                            R qyz, R gax, R gay, R gaz, R gp, R &gx, R &gy,
@@ -381,44 +385,45 @@ __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, 
     const R ri3 = ri * ri2;
     const R ri5 = ri3 * ri2;
     const R ra = rx * gax + ry * gay + rz * gaz;
-    gM = -fma(ra, ri3, gp * ri);
-    // monopole part: -M ri3 a + (3 M ra ri5 + gp M ri3) r
+    const R gpri = gp * ri;
+    gM = -fma(ra, ri3, gpri);
     const R Mri3 = M * ri3;
-    const R cr = M * fma(R(3) * ra, ri5, gp * ri3);
-    gx = fma(cr, rx, -Mri3 * gax);
-    gy = fma(cr, ry, -Mri3 * gay);
-    gz = fma(cr, rz, -Mri3 * gaz);
-    if (ORDER == 2) {
-        const R qzz = -(qxx + qyy);
-        const R qx = qxx * rx + qxy * ry + qxz * rz;
-        const R qy = qxy * rx + qyy * ry + qyz * rz;
-        const R qz = qxz * rx + qyz * ry + qzz * rz;
-        const R Qax = qxx * gax + qxy * gay + qxz * gaz;
-        const R Qay = qxy * gax + qyy * gay + qyz * gaz;
-        const R Qaz = qxz * gax + qyz * gay + qzz * gaz;
-        const R q = qx * rx + qy * ry + qz * rz;
-        const R aQr = gax * qx + gay * qy + gaz * qz;
-        const R ri7 = ri5 * ri2;
-        // + ri5 Qa - 5 aQr ri7 r - 5 ra ri7 Qr - 2.5 q ri7 a + 17.5 q ra ri9 r
-        // - gp ri5 Qr + 2.5 gp q ri7 r
-        const R cr2 = ri7 * fma(R(17.5) * q * ra, ri2, fma(R(2.5) * gp, q, R(-5) * aQr));
-        const R cq = fma(R(-5) * ra, ri7, -gp * ri5);
-        const R ca = R(-2.5) * q * ri7;
-        gx = fma(ri5, Qax, fma(cr2, rx, fma(cq, qx, fma(ca, gax, gx))));
-        gy = fma(ri5, Qay, fma(cr2, ry, fma(cq, qy, fma(ca, gay, gy))));
-        gz = fma(ri5, Qaz, fma(cr2, rz, fma(cq, qz, fma(ca, gaz, gz))));
-        // dL/dQ = h5 (a r^T + r a^T) - k r r^T (diagonal: ri5 a_d r_d - k r_d^2)
-        const R k = fma(R(2.5) * ra, ri7, R(0.5) * gp * ri5);
-        const R h5 = R(0.5) * ri5;
-        const R gzz = fma(gaz * rz, ri5, -k * rz * rz);
-        gq[0] = fma(gax * rx, ri5, -k * rx * rx) - gzz;
-        gq[1] = fma(gay * ry, ri5, -k * ry * ry) - gzz;
-        gq[2] = fma(h5, fma(gax, ry, gay * rx), -k * rx * ry);
-        gq[3] = fma(h5, fma(gax, rz, gaz * rx), -k * rx * rz);
-        gq[4] = fma(h5, fma(gay, rz, gaz * ry), -k * ry * rz);
-    } else {
+    const R cm = M * fma(R(3) * ra, ri5, gpri * ri2);   // monopole part of c_r
+    if (ORDER != 2) {
+        gx = fma(cm, rx, -Mri3 * gax);
+        gy = fma(cm, ry, -Mri3 * gay);
+        gz = fma(cm, rz, -Mri3 * gaz);
         for (int d = 0; d < 5; ++d) gq[d] = R(0);
+        return;
     }
+    const R qzz = -(qxx + qyy);
+    const R qx = qxx * rx + qxy * ry + qxz * rz;
+    const R qy = qxy * rx + qyy * ry + qyz * rz;
+    const R qz = qxz * rx + qyz * ry + qzz * rz;
+    const R Qax = qxx * gax + qxy * gay + qxz * gaz;
+    const R Qay = qxy * gax + qyy * gay + qyz * gaz;
+    const R Qaz = qxz * gax + qyz * gay + qzz * gaz;
+    const R sq = qx * rx + qy * ry + qz * rz;
+    const R aQr = gax * qx + gay * qy + gaz * qz;
+    const R ri7 = ri5 * ri2;
+    const R gpri5 = gpri * ri2 * ri2;
+    // c_r = 3 M ra/r^5 + phi M/r^3 + (35/2 s ra/r^2 + 5/2 phi s - 5 aQr)/r^7
+    const R cr = fma(ri7, fma(R(17.5) * sq * ra, ri2, fma(R(2.5) * gp, sq, R(-5) * aQr)), cm);
+    const R ca = -fma(R(2.5) * sq, ri7, Mri3);   // -M/r^3 - 5/2 s/r^7
+    const R cq = -fma(R(5) * ra, ri7, gpri5);    // -5 ra/r^7 - phi/r^5
+    gx = fma(ri5, Qax, fma(cq, qx, fma(ca, gax, cr * rx)));
+    gy = fma(ri5, Qay, fma(cq, qy, fma(ca, gay, cr * ry)));
+    gz = fma(ri5, Qaz, fma(cq, qz, fma(ca, gaz, cr * rz)));
+    const R k = fma(R(2.5) * ra, ri7, R(0.5) * gpri5);
+    const R wx = fma(-k, rx, ri5 * gax);
+    const R wy = fma(-k, ry, ri5 * gay);
+    const R wz = fma(-k, rz, ri5 * gaz);
+    const R pz = wz * rz;
+    gq[0] = fma(wx, rx, -pz);
+    gq[1] = fma(wy, ry, -pz);
+    gq[2] = fma(wx, ry, wy * rx);
+    gq[3] = fma(wx, rz, wz * rx);
+    gq[4] = fma(wy, rz, wz * ry);
 }
 
 template <typename T>
@@ -926,9 +931,10 @@ __global__ void k_pushdown(int64_t n, int64_t n_gas, int64_t nn, const T *__rest
             double a9[9];
             for (int c = 0; c < 9; ++c) a9[c] = ad[c * nn + nd];
             const double y0 = x[0] - cs[3 * nd], y1 = x[1] - cs[3 * nd + 1], y2 = x[2] - cs[3 * nd + 2];
-            // dL/dQ up to a multiple of the identity (zz component 0)
-            const double gxx = a9[4], gyy = a9[5], gzz = 0.0, gxy = a9[6], gxz = a9[7],
-                         gyz = a9[8];
+            // dL/dQ up to a multiple of the identity (zz component 0); the
+            // off-diagonal numbers are stored doubled
+            const double gxx = a9[4], gyy = a9[5], gzz = 0.0, gxy = 0.5 * a9[6],
+                         gxz = 0.5 * a9[7], gyz = 0.5 * a9[8];
             const double tr = gxx + gyy + gzz;
             const double Gy0 = gxx * y0 + gxy * y1 + gxz * y2;
             const double Gy1 = gxy * y0 + gyy * y1 + gyz * y2;
