@@ -185,35 +185,38 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
     return v;
 }
 
-// Gather `want` particle indices from the front of a range ring into slot[].
-// Returns false (and flags err) if the ring runs dry, which the pending
-// counts rule out.
+// Gather `want` (<= 64) particle indices from the front of a range ring into
+// slot[], in one pass: lane l looks at ring entry head + l, an inclusive scan
+// of the entry sizes places every entry's particles, each lane writes its
+// entry's share, entries used up are dropped and a partly used one is
+// shortened in place.  Every entry holds at least one particle, so 64
+// entries always cover `want`; returns false (and flags err) if the pending
+// entries hold fewer particles, which the pending counts rule out.
 __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, int32_t *slot,
                                             uint32_t want, int32_t *err) {
-    const int lane = threadIdx.x;
-    uint32_t k = 0;
-    int guard = 0;
-    while (k < want) {
-        if (++guard > 130 || h == t) {
-            if (lane == 0) atomicOr(err, 4);
-            return false;
-        }
-        const int32_t f = __builtin_amdgcn_readfirstlane(R.f[h & 127]);
-        const int32_t c = __builtin_amdgcn_readfirstlane(R.c[h & 127]);
-        const uint32_t tk = (uint32_t)c < want - k ? (uint32_t)c : want - k;
-        if ((uint32_t)lane < tk) slot[k + lane] = f + lane;
-        k += tk;
-        __syncthreads();
-        if (tk < (uint32_t)c) {
-            if (lane == 0) {
-                R.f[h & 127] = f + (int32_t)tk;
-                R.c[h & 127] = c - (int32_t)tk;
-            }
-        } else {
-            ++h;
-        }
-        __syncthreads();
+    const uint32_t lane = threadIdx.x;
+    const bool have = h + lane < t;
+    const uint32_t q = (h + lane) & 127;
+    const int32_t f = have ? R.f[q] : 0;
+    const uint32_t c = have ? (uint32_t)R.c[q] : 0u;
+    const uint32_t incl = wave_scan_incl(c);
+    const uint32_t excl = incl - c;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (total < want) {
+        if (lane == 0) atomicOr(err, 4);
+        return false;
     }
+    if (excl < want) {
+        const uint32_t take = (incl < want ? incl : want) - excl;
+        for (uint32_t i = 0; i < take; ++i) slot[excl + i] = f + (int32_t)i;
+        if (incl > want) {   // the one entry that is used only in part
+            R.f[q] = f + (int32_t)take;
+            R.c[q] = (int32_t)(c - take);
+        }
+    }
+    // entries used up: those whose inclusive count is at most want
+    h += (uint32_t)popc64(__ballot(have && incl <= want));
+    __syncthreads();
     return true;
 }
 
