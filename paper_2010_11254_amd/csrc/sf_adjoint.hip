@@ -445,6 +445,7 @@ struct WalkArgsB {
     double *nadj;               // 9 per node: M, c(3), dQ(5)
     int64_t scat_stride, nadj_stride;   // elements between copies
     int32_t *task_ctr, *err;
+    uint32_t *gstack;           // kStack entries per block: stack overflow area
 };
 
 // Per-lane target of the group adjoint.
@@ -740,7 +741,8 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
         ev.oz.zero();
         ev.oh.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
+        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf, gf + gc,
+                  a.err, npc, npp);
         double v[4] = {ev.ox.value(), ev.oy.value(), ev.oz.value(), ev.oh.value()};
         for (uint32_t off = W; off < 64u; off <<= 1)
             for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
@@ -873,7 +875,8 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
         ev.oz.zero();
         ev.oh.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, ev, b, b, (double)a.hs[p], p, p + 1, a.err, npc, npp);
+        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b, (double)a.hs[p], p,
+                  p + 1, a.err, npc, npp);
         const double s0 = wave_sum_d(ev.ox.value()), s1 = wave_sum_d(ev.oy.value());
         const double s2 = wave_sum_d(ev.oz.value()), s4 = wave_sum_d(ev.oh.value());
         if (lane == 0) {
@@ -1005,15 +1008,17 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
 template <typename T, int FORM, int ORDER>
 static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
                            const void *g_pot, double *tgt, double *scat, double *nadj0,
-                           double *nadj1, int32_t *ctr) {
-    const unsigned grid = (unsigned)(device_cu_count() * 16);
+                           double *nadj1, int32_t *ctr, uint32_t *gstack) {
+    const unsigned grid = (unsigned)walk_grid();
     WalkArgsB<T> ag = make_args_b<T>(t, o, 0, g_acc, g_pot, tgt, scat, nadj0, ctr);
+    ag.gstack = gstack;
     phase_begin(t, 8);
     hipLaunchKernelGGL((k_walk_groups_b<T, FORM, ORDER>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 8);
     if (t->n_sink > 0) {
         WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + kCtrSinks);
         as.err = ctr + kCtrErr;
+        as.gstack = gstack;
         const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
         phase_begin(t, 9);
         hipLaunchKernelGGL((k_walk_sinks_b<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
@@ -1028,8 +1033,10 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     hipStream_t s = t->stream;
     const int64_t n = t->n, nn = t->n_nodes;
     int32_t *ctr;
+    uint32_t *gstack;
     double *tgt, *scat, *nadj0, *nadj1, *ssb = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
+    SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     SF_ALLOC_TMP(ar, tgt, 5 * n);
     SF_ALLOC_TMP(ar, scat, kXcd * 5 * n);
     SF_ALLOC_TMP(ar, nadj0, kXcd * 9 * nn);
@@ -1045,7 +1052,7 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
         sink_sink_backward<T>(t, g_acc, g_pot, ssb);
         phase_end(t, 7);
     }
-#define SF_WB(F, O) launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr)
+#define SF_WB(F, O) launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr, gstack)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_WB(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_WB(SF_FP32, 0);

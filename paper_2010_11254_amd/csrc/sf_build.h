@@ -79,6 +79,7 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
 void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4);
 
 int device_cu_count();
+int walk_grid();
 
 // Phase timer helpers: no-ops unless t->timing.
 void phase_begin(sf_grav_tree_s *t, int ph);

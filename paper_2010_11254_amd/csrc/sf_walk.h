@@ -5,7 +5,14 @@
 
 namespace sf {
 
+// Walk stack: kStack entries bound it (see the walk's header); the top
+// kStackLds of them live in LDS, older ones are moved, 64 at a time, to a
+// per-wave area in device memory when the window fills (rare at theta 0.5;
+// full-tree walks at theta 0 reach it) and brought back when the top runs
+// short.
 constexpr int kStack = 22 * 64 + 64;
+constexpr int kStackLds = 128;
+constexpr uint32_t kStackMask = kStackLds - 1;
 
 struct WalkNodes {
     int64_t n_nodes;
@@ -22,7 +29,7 @@ struct PPRing {
 };
 
 struct WalkLds {
-    uint32_t stack[kStack];
+    uint32_t stack[kStackLds];   // stack position p at index p & kStackMask
     int32_t pc[128];
     PPRing near;   // leaves that may hold softened pairs (incl. the task's own)
     PPRing far;    // leaves whose every pair with the task is Newtonian
@@ -223,13 +230,23 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
 // Walk one task.  Ev supplies pc_batch(L, head, nb) and
 // pp_batch<SOFT>(L, nb) (SOFT = false: every pair is Newtonian and none is a
 // self pair).
+// Stack entries moved out of and back into LDS: device-scope relaxed
+// atomics, so the wave reads back exactly what it wrote (no stale L1 line).
+__device__ __forceinline__ void stack_out(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t stack_in(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class Ev>
-__device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double blo[3],
-                          const double bhi[3], double hg, int64_t gf, int64_t gl, int32_t *err,
-                          uint32_t &n_pc, uint32_t &n_pp) {
+__device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev &ev,
+                          const double blo[3], const double bhi[3], double hg, int64_t gf,
+                          int64_t gl, int32_t *err, uint32_t &n_pc, uint32_t &n_pp) {
     const int lane = threadIdx.x;
     const uint64_t lt = lane_mask_lt();
-    uint32_t sp = 1;
+    uint32_t sp = 1;     // stack positions [0, sp)
+    uint32_t base = 0;   // positions [base, sp) in LDS, [0, base) in gstack
     if (lane == 0) L.stack[0] = 1u;   // root (node 0), one node
     uint32_t pc_h = 0, pc_t = 0;
     uint32_t nh = 0, nt = 0, npend = 0;   // near ring
@@ -245,9 +262,17 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
             if (lane == 0) atomicOr(err, 2);
             break;
         }
+        // the top 64 positions must be in LDS: bring back the 64 older ones
+        // (the window then holds at most 63 + 64 entries)
+        if (base > 0 && sp - base < 64u) {
+            const uint32_t nb = base - 64u;   // base is a multiple of 64
+            for (uint32_t p = nb + lane; p < base; p += 64u) L.stack[p & kStackMask] = stack_in(gstack + p);
+            base = nb;
+            __syncthreads();
+        }
         // pop whole entries from the top, at most 64 nodes
         const int ei = (int)sp - 1 - lane;
-        const uint32_t ent = ei >= 0 ? L.stack[ei] : 0u;
+        const uint32_t ent = ei >= 0 ? L.stack[ei & kStackMask] : 0u;
         const uint32_t cnt = ent & 15u;
         const uint32_t incl = wave_scan_incl(cnt);
         const bool take = ei >= 0 && incl <= 64u;
@@ -286,9 +311,16 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, Ev &ev, const double 
             if (lane == 0) atomicOr(err, 1);
             break;
         }
+        // room for the push: move the oldest 64 window entries out (they all
+        // exist: sp - base > kStackLds - 64 = 64 here)
+        while (sp + npush - base > (uint32_t)kStackLds) {
+            stack_out(gstack + base + lane, L.stack[(base + lane) & kStackMask]);
+            base += 64u;
+            __syncthreads();
+        }
         if (cls == 3) {
             const uint32_t r = (uint32_t)popc64(mint & lt);
-            L.stack[sp + npush - 1 - r] =
+            L.stack[(sp + npush - 1 - r) & kStackMask] =
                 ((uint32_t)nd.w[node].child << 4) | (uint32_t)(nd.w[node].lvl_nch & 255);
         }
         sp += npush;

@@ -45,6 +45,7 @@ struct WalkArgs {
     const double *ss;          // sink-sink sums (4 per sink), may be null
     int32_t *task_ctr;
     int32_t *err;
+    uint32_t *gstack;          // kStack entries per block: stack overflow area
     int32_t *gnpc, *gnpp;      // stats (group mode), may be null
     T *acc, *pot;
     double G;
@@ -197,7 +198,8 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.ay.zero();
             ev.az.zero();
             ev.ap.zero();
-            walk_task(a.nd, L, ev, blo, bhi, hg, gf, gf + gc, a.err, npc, npp);
+            walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
+                      gf + gc, a.err, npc, npp);
             double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
             for (uint32_t off = W; off < 64u; off <<= 1)
                 for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
@@ -313,7 +315,8 @@ __global__ __launch_bounds__(64) void k_walk_sinks(WalkArgs<T> a) {
         ev.az.zero();
         ev.ap.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, ev, b, b, (double)a.hs[p], p, p + 1, a.err, npc, npp);
+        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b, (double)a.hs[p], p,
+                  p + 1, a.err, npc, npp);
         double s[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
         for (int d = 0; d < 4; ++d) s[d] = wave_sum_f64(s[d]);
         if (lane == 0) {
@@ -379,6 +382,10 @@ void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss) {
 
 // ---------------------------------------------------------------- launch
 
+// Persistent grid of the walk kernels: 16 one-wave blocks per CU (the most
+// that run at once at their register use).
+int walk_grid() { return device_cu_count() * 16; }
+
 int device_cu_count() {
     static int cus = 0;
     if (cus == 0) {
@@ -392,7 +399,7 @@ int device_cu_count() {
 
 template <typename T>
 static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void *acc, void *pot,
-                             int32_t *ctr, double *ss) {
+                             int32_t *ctr, double *ss, uint32_t *gstack) {
     WalkArgs<T> a{};
     a.nd.n_nodes = t->n_nodes;
     a.nd.w = t->nw[set];
@@ -418,6 +425,7 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     a.ss = ss;
     a.task_ctr = ctr;
     a.err = ctr + kCtrErr;
+    a.gstack = gstack;
     a.gnpc = t->gnpc;
     a.gnpp = t->gnpp;
     a.acc = (T *)acc;
@@ -428,9 +436,9 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
 
 template <typename T, int FORM, int ORDER>
 static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, int32_t *ctr,
-                         double *ss) {
-    const unsigned grid = (unsigned)(device_cu_count() * 16);
-    WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss);
+                         double *ss, uint32_t *gstack) {
+    const unsigned grid = (unsigned)walk_grid();
+    WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss, gstack);
     phase_begin(t, 5);
     if (o.stats)
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, true>), dim3(grid), dim3(64), 0, t->stream, ag);
@@ -438,7 +446,7 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, false>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 5);
     if (t->n_sink > 0) {
-        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss);
+        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss, gstack);
         as.err = ctr + kCtrErr;
         const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
         phase_begin(t, 6);
@@ -449,8 +457,8 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
 
 template <typename T>
 static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
-                           int32_t *ctr, double *ss) {
-#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss)
+                           int32_t *ctr, double *ss, uint32_t *gstack) {
+#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss, gstack)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_W(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_W(SF_FP32, 0);
@@ -466,7 +474,9 @@ static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
     int32_t *ctr = nullptr;
     double *ss = nullptr;
+    uint32_t *gstack = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
+    SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
@@ -486,8 +496,8 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
         t->have_stats = true;
     }
-    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss);
-    else dispatch_walks<double>(t, o, acc, pot, ctr, ss);
+    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack);
+    else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack);
     SF_HIP(hipGetLastError());
     int32_t herr = 0;
     SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));

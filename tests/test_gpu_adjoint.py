@@ -147,3 +147,14 @@ def test_autograd_function_tree_backward():
     ref = oracle_tree_vjp(ps, ga, gp)
     for g, r, name in zip((x.grad, m.grad, h.grad), ref, ("x", "m", "h")):
         _close(g.cpu().numpy(), r, 1e-8, name)
+
+
+def test_tree_adjoint_theta_zero_deep_stack():
+    _say("tree adjoint theta 0, leaf 1, uniform 20000: deep stack")
+    from synth import uniform_sphere
+    ps = uniform_sphere(20000, seed=3)
+    ga, gp = cotangents(ps.n, seed=18)
+    got = gpu_backward(ps, ga, gp, "fp64", "tree", theta=0.0, leaf_cap=1, group_cap=8)
+    ref = odirect.direct_vjp(ps.x, ps.m, ps.h, ga, gp)
+    for g, r, name in zip(got, ref, ("x", "m", "h")):
+        _close(g, r, 1e-9, name)

@@ -216,3 +216,15 @@ def test_tree_uniform_sphere_monopole_error():
     a, p = gpu_tree(ps, "fp32c", order=0)
     ar, pr, _ = otree.tree_forward(ps.x, ps.m, ps.h, ps.n_gas, theta=0.5, order=0)
     assert np.median(_relerr(a, ar)) < 1e-6
+
+
+def test_tree_theta_zero_deep_stack_is_direct():
+    # leaf capacity 1 on a uniform cloud makes a near-full octree: a walk at
+    # theta 0 then holds more stack entries than the LDS window and moves the
+    # oldest ones out to device memory and back
+    _say("tree theta 0, leaf 1, uniform 20000: deep stack")
+    ps = uniform_sphere(20000, seed=3)
+    a, p = gpu_tree(ps, "fp64", theta=0.0, leaf_cap=1, group_cap=8)
+    ar, pr = odirect.direct(ps.x, ps.m, ps.h)
+    assert np.max(_relerr(a, ar)) < 1e-11
+    assert np.max(np.abs(p - pr) / np.abs(pr)) < 1e-11
