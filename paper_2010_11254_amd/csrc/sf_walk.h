@@ -112,31 +112,30 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
 
 // ---------------------------------------------------------------- walk core
 
-// Test one node against the task box; returns 0 skip, 1 accept, 2 open leaf
-// that may hold softened pairs, 3 open inner, 4 open leaf with only Newtonian
+// Test one node against the task box: cls 0 skip, 1 accept, 2 open leaf that
+// may hold softened pairs, 3 open inner, 4 open leaf with only Newtonian
 // pairs (gap to the box at least the larger max softening).  All FP64 steps
-// are separately rounded (no contraction).
-__device__ __forceinline__ int classify(const WalkNodes &nd, int node, const double blo[3],
-                                        const double bhi[3], double hg, int64_t gf, int64_t gl) {
-    const NodeW &w = nd.w[node];
-    const double M = w.M;
-    if (!(M > 0.0)) return 0;
+// are separately rounded (no contraction).  The node record is read once,
+// whole, and the fields the walk needs next are returned with the class, so
+// a step costs one memory round trip per node.
+struct NodeHit {
+    int cls;
+    int32_t first, count, child, lvl_nch;
+};
+
+__device__ __forceinline__ NodeHit classify(const WalkNodes &nd, int node, const double blo[3],
+                                            const double bhi[3], double hg, int64_t gf,
+                                            int64_t gl) {
+    const NodeW w = nd.w[node];
     const int64_t f = w.first, c = w.count;
-    bool open = (f < gl) && (gf < f + c);
-    double lo[3], hi[3], cm[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = w.clo[d];
-        hi[d] = w.chi[d];
-        cm[d] = w.com[d];
-    }
-    const bool meets = lo[0] <= bhi[0] && blo[0] <= hi[0] && lo[1] <= bhi[1] && blo[1] <= hi[1] &&
-                       lo[2] <= bhi[2] && blo[2] <= hi[2];
+    const bool open = (f < gl) && (gf < f + c);
+    const bool meets = w.clo[0] <= bhi[0] && blo[0] <= w.chi[0] && w.clo[1] <= bhi[1] &&
+                       blo[1] <= w.chi[1] && w.clo[2] <= bhi[2] && blo[2] <= w.chi[2];
     double g[3], e[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        g[d] = fmax(fmax(dsub(lo[d], bhi[d]), dsub(blo[d], hi[d])), 0.0);
-        e[d] = fmax(fmax(dsub(blo[d], cm[d]), dsub(cm[d], bhi[d])), 0.0);
+        g[d] = fmax(fmax(dsub(w.clo[d], bhi[d]), dsub(blo[d], w.chi[d])), 0.0);
+        e[d] = fmax(fmax(dsub(blo[d], w.com[d]), dsub(w.com[d], bhi[d])), 0.0);
     }
     const double dbb2 = dadd(dadd(dmul(g[0], g[0]), dmul(g[1], g[1])), dmul(g[2], g[2]));
     const double hm = fmax(w.hmax, hg);
@@ -144,10 +143,10 @@ __device__ __forceinline__ int classify(const WalkNodes &nd, int node, const dou
     const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
     const double L = ldexp(nd.side, -(w.lvl_nch >> 8));
     const bool angle = dmul(L, L) > dmul(nd.th2, r2);
-    const bool opened = open || meets || soft || angle;
-    if (!opened) return 1;
-    if ((w.lvl_nch & 255) != 0) return 3;
-    return (open || meets || soft) ? 2 : 4;
+    const bool near = open || meets || soft;
+    int cls = !(near || angle) ? 1 : ((w.lvl_nch & 255) != 0 ? 3 : (near ? 2 : 4));
+    if (!(w.M > 0.0)) cls = 0;
+    return {cls, w.first, w.count, w.child, w.lvl_nch};
 }
 
 // Next task index for the whole wave, as a scalar (SGPR) value: lane 0 takes
@@ -176,20 +175,37 @@ constexpr int kCtrSinks = kCtrStride;
 constexpr int kCtrErr = kCtrSinks + kCtrStride;
 constexpr int kCtrWords = kCtrErr + kCtrStride;
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// Prefix sums and totals over the wave of non-negative values, from one
+// ballot per bit: no cross-lane data movement, and the total is a scalar.
+// Values are usually below 2^BITS; the higher bits are visited only when a
+// lane has one set (a leaf at the depth limit can hold any number of
+// particles).
+__device__ __forceinline__ uint32_t bit_prefix(uint32_t v, int b) {
+    const uint32_t bit = (v >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    const uint32_t below =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return (below + bit) << b;
 }
 
+template <int BITS>
 __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
-    const int lane = threadIdx.x & 63;
+    uint32_t s = 0;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
-    return v;
+    for (int b = 0; b < BITS; ++b) s += bit_prefix(v, b);
+    if (__ballot(v >> BITS) != 0ull)
+        for (int b = BITS; b < 32; ++b) s += bit_prefix(v, b);
+    return s;
+}
+
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) s += (uint32_t)popc64(__ballot((v >> b) & 1u)) << b;
+    if (__ballot(v >> BITS) != 0ull)
+        for (int b = BITS; b < 32; ++b) s += (uint32_t)popc64(__ballot((v >> b) & 1u)) << b;
+    return s;
 }
 
 // Gather `want` (<= 64) particle indices from the front of a range ring into
@@ -206,7 +222,7 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
     const uint32_t q = (h + lane) & 127;
     const int32_t f = have ? R.f[q] : 0;
     const uint32_t c = have ? (uint32_t)R.c[q] : 0u;
-    const uint32_t incl = wave_scan_incl(c);
+    const uint32_t incl = wave_scan_incl<7>(c);
     const uint32_t excl = incl - c;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     if (total < want) {
@@ -274,7 +290,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         const int ei = (int)sp - 1 - lane;
         const uint32_t ent = ei >= 0 ? L.stack[ei & kStackMask] : 0u;
         const uint32_t cnt = ent & 15u;
-        const uint32_t incl = wave_scan_incl(cnt);
+        const uint32_t incl = wave_scan_incl<4>(cnt);   // an entry holds 1..8 nodes
         const bool take = ei >= 0 && incl <= 64u;
         const uint32_t ntake = (uint32_t)popc64(__ballot(take));
         const uint32_t nnodes = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ntake - 1);
@@ -283,8 +299,9 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         sp -= ntake;
         __syncthreads();
         const int node = lane < (int)nnodes ? L.slot[lane] : -1;
-        int cls = 0;
-        if (node >= 0) cls = classify(nd, node, blo, bhi, hg, gf, gl);
+        NodeHit hit{0, 0, 0, 0, 0};
+        if (node >= 0) hit = classify(nd, node, blo, bhi, hg, gf, gl);
+        const int cls = hit.cls;
         const uint64_t macc = __ballot(cls == 1), mnear = __ballot(cls == 2),
                        mint = __ballot(cls == 3), mfar = __ballot(cls == 4);
         if (cls == 1) L.pc[(pc_t + popc64(macc & lt)) & 127] = node;
@@ -292,20 +309,20 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         uint32_t lcn = 0, lcf = 0;
         if (cls == 2) {
             const uint32_t q = (nt + popc64(mnear & lt)) & 127;
-            lcn = (uint32_t)nd.w[node].count;
-            L.near.f[q] = nd.w[node].first;
-            L.near.c[q] = (int32_t)lcn;
+            lcn = (uint32_t)hit.count;
+            L.near.f[q] = hit.first;
+            L.near.c[q] = hit.count;
         }
         if (cls == 4) {
             const uint32_t q = (ft + popc64(mfar & lt)) & 127;
-            lcf = (uint32_t)nd.w[node].count;
-            L.far.f[q] = nd.w[node].first;
-            L.far.c[q] = (int32_t)lcf;
+            lcf = (uint32_t)hit.count;
+            L.far.f[q] = hit.first;
+            L.far.c[q] = hit.count;
         }
         nt += (uint32_t)popc64(mnear);
         ft += (uint32_t)popc64(mfar);
-        npend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lcn));
-        fpend += (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_sum_u32(lcf));
+        npend += wave_total<7>(lcn);
+        fpend += wave_total<7>(lcf);
         const uint32_t npush = (uint32_t)popc64(mint);
         if (sp + npush > (uint32_t)kStack) {   // cannot happen (see header); stop safely
             if (lane == 0) atomicOr(err, 1);
@@ -321,7 +338,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         if (cls == 3) {
             const uint32_t r = (uint32_t)popc64(mint & lt);
             L.stack[(sp + npush - 1 - r) & kStackMask] =
-                ((uint32_t)nd.w[node].child << 4) | (uint32_t)(nd.w[node].lvl_nch & 255);
+                ((uint32_t)hit.child << 4) | (uint32_t)(hit.lvl_nch & 255);
         }
         sp += npush;
         __syncthreads();
