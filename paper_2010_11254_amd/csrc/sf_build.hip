@@ -229,27 +229,40 @@ __global__ void k_topo_lcp(const uint64_t *__restrict__ keys, int64_t n, int cap
     if (s + cap < n) win[s] = (uint8_t)lcp_digits(k, keys[s + cap]);
 }
 
-// Leaf level lambda(s), node count of s, level histogram.
+// Leaf level lambda(s), node count of s, level histogram.  The block's window
+// bytes (positions base - cap .. base + 255, cap <= 64) are staged in LDS; the
+// histogram takes one ballot per level per wave.
 __global__ __launch_bounds__(256) void k_topo_count(const uint8_t *__restrict__ lcp,
                                                     const uint8_t *__restrict__ win, int64_t n,
                                                     int cap, uint8_t *__restrict__ lam,
                                                     uint32_t *__restrict__ nn,
                                                     uint32_t *__restrict__ levhist) {
+    __shared__ uint8_t sw[256 + 64];
     __shared__ uint32_t sh[kLevels + 1];
     if (threadIdx.x <= kLevels) sh[threadIdx.x] = 0;
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x;
+    for (int i = threadIdx.x; i < 256 + cap; i += 256) {
+        const int64_t t = base - cap + i;
+        sw[i] = (t >= 0 && t < n - cap) ? win[t] : 0;
+    }
     __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) {
-        int64_t t0 = s - cap > 0 ? s - cap : 0;
-        int64_t t1 = s < n - 1 - cap ? s : n - 1 - cap;
+    const int64_t s = base + threadIdx.x;
+    const bool valid = s < n;
+    int lo = 1, L = 0;
+    if (valid) {
+        // windows t in [max(s - cap, 0), min(s, n - 1 - cap)]: empty only when n <= cap
+        const int64_t t0 = s - cap > 0 ? s - cap : 0;
+        const int64_t t1 = s < n - 1 - cap ? s : n - 1 - cap;
         int mx = -1;
-        for (int64_t t = t0; t <= t1; ++t) mx = max(mx, (int)win[t]);
-        int L = mx < 0 ? 0 : min(kLevels, mx + 1);
-        int lo = s == 0 ? 0 : (int)lcp[s] + 1;
+        for (int64_t t = t0; t <= t1; ++t) mx = max(mx, (int)sw[t - (base - cap)]);
+        L = mx < 0 ? 0 : min(kLevels, mx + 1);
+        lo = s == 0 ? 0 : (int)lcp[s] + 1;
         lam[s] = (uint8_t)L;
-        int cnt = L >= lo ? L - lo + 1 : 0;
-        nn[s] = (uint32_t)cnt;
-        for (int l = lo; l <= L; ++l) atomicAdd(&sh[l], 1u);
+        nn[s] = (uint32_t)(L >= lo ? L - lo + 1 : 0);
+    }
+    for (int l = 0; l <= kLevels; ++l) {
+        const uint64_t b = __ballot(l >= lo && l <= L);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd(&sh[l], (uint32_t)__popcll(b));
     }
     __syncthreads();
     if (threadIdx.x <= kLevels && sh[threadIdx.x]) atomicAdd(&levhist[threadIdx.x], sh[threadIdx.x]);
@@ -301,19 +314,43 @@ __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nod
                               double *__restrict__ clo, double *__restrict__ chi,
                               uint32_t *__restrict__ stats /* [0]=max level, [1]=leaves */) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_nodes) return;
-    const uint64_t pk = packed[k];
+    const bool valid = k < n_nodes;
+    // per-wave statistics, one atomic per wave (ballots cover the lanes
+    // beyond n_nodes as zeros)
+    const uint64_t pk = valid ? packed[k] : 0ull;
     const int l = (int)(pk & 255);
     const int64_t s = (int64_t)(pk >> 8);
-    // end of the cell: first key beyond the largest key with this prefix
-    const uint64_t kmax = keys[s] | ((l == 0) ? ~0ull >> 1 : ((1ull << (3 * (kLevels - l))) - 1));
-    int64_t a = s + 1, b = n;
-    while (a < b) {
-        int64_t m = (a + b) >> 1;
-        if (keys[m] <= kmax) a = m + 1; else b = m;
+    int64_t end = s;
+    if (valid) {
+        // end of the cell: first key beyond the largest key with this prefix;
+        // galloping from s (most cells are small), then bisection
+        const uint64_t kmax = keys[s] | ((l == 0) ? ~0ull >> 1 : ((1ull << (3 * (kLevels - l))) - 1));
+        int64_t a = s + 1, step = 1;
+        while (a < n && keys[a] <= kmax) {
+            a = s + 1 + step;
+            step <<= 1;
+        }
+        // keys[lo - 1] <= kmax and (hi == n or keys[hi] > kmax)
+        int64_t lo = s + 1 + (step >> 2), hi = a < n ? a : n;
+        if (step == 1) lo = s + 1;
+        while (lo < hi) {
+            const int64_t m = (lo + hi) >> 1;
+            if (keys[m] <= kmax) lo = m + 1; else hi = m;
+        }
+        end = lo;
     }
-    const int64_t end = a;
     const int64_t cnt = end - s;
+    const bool leaf = cnt <= cap || l == kLevels;
+    {
+        const uint32_t nleaf = (uint32_t)__popcll(__ballot(valid && leaf));
+        int lmax = valid ? l : 0;
+        for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off, 64));
+        if ((threadIdx.x & 63) == 0) {
+            if (nleaf) atomicAdd(&stats[1], nleaf);
+            atomicMax(&stats[0], (uint32_t)lmax);
+        }
+    }
+    if (!valid) return;
     nlevel[k] = l;
     nfirst[k] = (int32_t)s;
     ncount[k] = (int32_t)cnt;
@@ -324,7 +361,6 @@ __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nod
     } else {
         nparent[k] = -1;
     }
-    const bool leaf = cnt <= cap || l == kLevels;
     if (!leaf) {
         int64_t c0 = lower_first(packed, level_off[l + 1], level_off[l + 2], (uint64_t)s);
         int64_t c1 = lower_first(packed, c0, level_off[l + 2], (uint64_t)end);
@@ -333,9 +369,7 @@ __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nod
     } else {
         nchild[k] = -1;
         nnchild[k] = 0;
-        atomicAdd(&stats[1], 1u);
     }
-    atomicMax(&stats[0], (uint32_t)l);
     // cube: lo + ix * cell, lo + (ix + 1) * cell with cell = side * 2^-l
     const uint64_t pre = l == 0 ? 0ull : (keys[s] >> (3 * (kLevels - l)));
     const double cell = ldexp(frame->side, -l);
@@ -467,52 +501,14 @@ __device__ __forceinline__ void centre(const double *clo, const double *chi, int
     for (int d = 0; d < 3; ++d) g[d] = 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
 }
 
-// Leaves: sums over their particles about the cube centre (and each
-// particle's leaf index, used by the adjoint).
-template <typename T>
-__global__ void k_moments_leaf(int64_t n_nodes, const int32_t *__restrict__ nfirst,
-                               const int32_t *__restrict__ ncount,
-                               const int32_t *__restrict__ nnchild, const double *__restrict__ clo,
-                               const double *__restrict__ chi, const T *__restrict__ xs,
-                               const T *__restrict__ ys, const T *__restrict__ zs,
-                               const T *__restrict__ ms, const T *__restrict__ hs,
-                               const int32_t *__restrict__ order, int64_t n_gas,
-                               double *__restrict__ raw0, double *__restrict__ raw1,
-                               int32_t *__restrict__ pleaf) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_nodes || nnchild[k] != 0) return;
-    double g[3];
-    centre(clo, chi, k, g);
-    RawMom ra, rg;
-    raw_zero(ra);
-    raw_zero(rg);
-    const int64_t f = nfirst[k], c = ncount[k];
-    for (int64_t p = f; p < f + c; ++p) {
-        pleaf[p] = (int32_t)k;
-        const double m = (double)ms[p], h = (double)hs[p];
-        const double y0 = (double)xs[p] - g[0], y1 = (double)ys[p] - g[1], y2 = (double)zs[p] - g[2];
-        raw_add_point(ra, m, y0, y1, y2, h);
-        if (order[p] < n_gas) raw_add_point(rg, m, y0, y1, y2, h);
-    }
-    raw_store(raw0, k, ra);
-    raw_store(raw1, k, rg);
-}
-
-__device__ __forceinline__ void raw_load(const double *raw, int64_t k, RawMom &r) {
-    const double *p = raw + 11 * k;
-    r.M = p[0];
-    for (int d = 0; d < 3; ++d) r.D[d] = p[1 + d];
-    for (int d = 0; d < 6; ++d) r.S[d] = p[4 + d];
-    r.h = p[10];
-}
-
-// Inner nodes of one level, from their children (one level down, final).
-__global__ void k_moments_level(int64_t k0, int64_t k1, const int32_t *__restrict__ nchild,
-                                const int32_t *__restrict__ nnchild,
-                                const double *__restrict__ clo, const double *__restrict__ chi,
-                                double *__restrict__ raw0, double *__restrict__ raw1) {
-    const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= k1 || nnchild[k] == 0) return;
+// Inner node k from its children, each shifted from its centre to k's
+// centre, in child order.  Children written by other workgroups of the same
+// kernel are read with device-scope loads after the caller's acquire fence.
+__device__ __forceinline__ void node_from_children(int64_t k, const int32_t *__restrict__ nchild,
+                                                   const int32_t *__restrict__ nnchild,
+                                                   const double *__restrict__ clo,
+                                                   const double *__restrict__ chi, double *raw0,
+                                                   double *raw1) {
     double gp[3];
     centre(clo, chi, k, gp);
     RawMom ra, rg;
@@ -524,17 +520,80 @@ __global__ void k_moments_level(int64_t k0, int64_t k1, const int32_t *__restric
         centre(clo, chi, ch, gc);
         for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
         RawMom cm;
-        raw_load(raw0, ch, cm);
+        raw_load_dev(raw0, ch, cm);
         raw_add_child(ra, cm, dl);
-        raw_load(raw1, ch, cm);
+        raw_load_dev(raw1, ch, cm);
         raw_add_child(rg, cm, dl);
     }
     raw_store(raw0, k, ra);
     raw_store(raw1, k, rg);
 }
 
-// Final per-node moments: com = g + D/M, S_com = S - D D^T / M,
-// Q = 3 S_com - tr(S_com) I.  Nodes with M = 0 keep com = g, Q = 0.
+// All raw moments in one pass.  A thread per leaf sums its particles about
+// the cube centre (and records each particle's leaf index, used by the
+// adjoint), then climbs: it counts itself in at the parent, and the child
+// that arrives last computes the parent from all children, in child order,
+// and climbs on.  Every inner node is computed once, by one thread, with the
+// same arithmetic whatever the arrival order.  arrive[] starts at zero.
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments_up(
+    int64_t n_nodes, const int32_t *__restrict__ nfirst, const int32_t *__restrict__ ncount,
+    const int32_t *__restrict__ nchild, const int32_t *__restrict__ nnchild,
+    const int32_t *__restrict__ nparent, const double *__restrict__ clo,
+    const double *__restrict__ chi, const T *__restrict__ xs, const T *__restrict__ ys,
+    const T *__restrict__ zs, const T *__restrict__ ms, const T *__restrict__ hs,
+    const int32_t *__restrict__ order, int64_t n_gas, double *raw0, double *raw1,
+    int32_t *__restrict__ pleaf, uint32_t *arrive) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes || nnchild[k] != 0) return;
+    {
+        double g[3];
+        centre(clo, chi, k, g);
+        RawMom ra, rg;
+        raw_zero(ra);
+        raw_zero(rg);
+        const int64_t f = nfirst[k], e = f + ncount[k];
+        // four particles' loads in flight at a time, added in particle order
+        for (int64_t p0 = f; p0 < e; p0 += 4) {
+            double m4[4], h4[4], y4[4][3];
+            bool gas[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t p = p0 + j;
+                if (p < e) {
+                    m4[j] = (double)ms[p];
+                    h4[j] = (double)hs[p];
+                    y4[j][0] = (double)xs[p] - g[0];
+                    y4[j][1] = (double)ys[p] - g[1];
+                    y4[j][2] = (double)zs[p] - g[2];
+                    gas[j] = order[p] < n_gas;
+                    pleaf[p] = (int32_t)k;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (p0 + j < e) {
+                    raw_add_point(ra, m4[j], y4[j][0], y4[j][1], y4[j][2], h4[j]);
+                    if (gas[j]) raw_add_point(rg, m4[j], y4[j][0], y4[j][1], y4[j][2], h4[j]);
+                }
+            }
+        }
+        raw_store(raw0, k, ra);
+        raw_store(raw1, k, rg);
+    }
+    for (int64_t c = k;;) {
+        const int64_t p = nparent[c];
+        if (p < 0) break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // c's moments before the count
+        const uint32_t before = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        if (before + 1 != (uint32_t)nnchild[p]) break;        // a sibling is still to come
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the siblings' moments
+        node_from_children(p, nchild, nnchild, clo, chi, raw0, raw1);
+        c = p;
+    }
+}
+
 __global__ void k_moments_final(int64_t n_nodes, const double *__restrict__ clo,
                                 const double *__restrict__ chi, const double *__restrict__ raw,
                                 double *__restrict__ M, double *__restrict__ com,
@@ -615,23 +674,21 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
         SF_ALLOC(ar, t->nw[set], nn);
         SF_ALLOC(ar, t->nq[set], nn);
     }
+    uint32_t *arrive;
+    SF_ALLOC_TMP(ar, arrive, nn);
+    fill_u32(arrive, nn, 0u, s);
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_moments_leaf<float>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
-                           t->ncount, t->nnchild, t->clo, t->chi, (const float *)t->xs,
-                           (const float *)t->ys, (const float *)t->zs, (const float *)t->ms,
-                           (const float *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
+        hipLaunchKernelGGL(k_moments_up<float>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
+                           t->ncount, t->nchild, t->nnchild, t->nparent, t->clo, t->chi,
+                           (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
+                           (const float *)t->ms, (const float *)t->hs, t->order, t->n_gas, raw0,
+                           raw1, t->pleaf, arrive);
     else
-        hipLaunchKernelGGL(k_moments_leaf<double>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
-                           t->ncount, t->nnchild, t->clo, t->chi, (const double *)t->xs,
-                           (const double *)t->ys, (const double *)t->zs, (const double *)t->ms,
-                           (const double *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
-    // inner nodes, deepest level first (level offsets are known on the host)
-    for (int l = kLevels - 1; l >= 0; --l) {
-        const int64_t k0 = t->level_off[l], k1 = t->level_off[l + 1];
-        if (k1 <= k0 || t->level_off[l + 2] == t->level_off[l + 1]) continue;   // no children below
-        hipLaunchKernelGGL(k_moments_level, dim3(nblk(k1 - k0)), dim3(256), 0, s, k0, k1, t->nchild,
-                           t->nnchild, t->clo, t->chi, raw0, raw1);
-    }
+        hipLaunchKernelGGL(k_moments_up<double>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
+                           t->ncount, t->nchild, t->nnchild, t->nparent, t->clo, t->chi,
+                           (const double *)t->xs, (const double *)t->ys, (const double *)t->zs,
+                           (const double *)t->ms, (const double *)t->hs, t->order, t->n_gas, raw0,
+                           raw1, t->pleaf, arrive);
     double *raws[2] = {raw0, raw1};
     for (int set = 0; set < 2; ++set)
         hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,
@@ -680,29 +737,32 @@ __global__ void k_grp_write(const uint32_t *__restrict__ mark, const uint32_t *_
 }
 
 // One wave per group: count, bounding box, max softening and centre.  The
-// centre is the box midpoint, rounded to the input precision.
+// extremes are taken in the input precision (exact), the centre is the box
+// midpoint in FP64 rounded to the input precision.
 template <typename T>
-__global__ __launch_bounds__(64) void k_grp_info(const int32_t *__restrict__ n_groups_dev, int64_t n,
-                                                 int32_t *__restrict__ gfirst,
-                                                 int32_t *__restrict__ gcount,
-                                                 const T *__restrict__ xs, const T *__restrict__ ys,
-                                                 const T *__restrict__ zs, const T *__restrict__ hs,
-                                                 double *__restrict__ gbox,
-                                                 double *__restrict__ ghmax,
-                                                 double *__restrict__ gcen) {
+__global__ __launch_bounds__(256) void k_grp_info(const int32_t *__restrict__ n_groups_dev, int64_t n,
+                                                  int32_t *__restrict__ gfirst,
+                                                  int32_t *__restrict__ gcount,
+                                                  const T *__restrict__ xs, const T *__restrict__ ys,
+                                                  const T *__restrict__ zs, const T *__restrict__ hs,
+                                                  double *__restrict__ gbox,
+                                                  double *__restrict__ ghmax,
+                                                  double *__restrict__ gcen) {
     const int64_t ng = *n_groups_dev;
-    const int lane = threadIdx.x;
-    for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; g < ng; g += nwaves) {
         const int64_t f = gfirst[g];
         const int64_t e = (g + 1 < ng) ? gfirst[g + 1] : n;
         const int64_t c = e - f;
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double hm = 0.0;
+        T lo[3] = {(T)INFINITY, (T)INFINITY, (T)INFINITY};
+        T hi[3] = {-(T)INFINITY, -(T)INFINITY, -(T)INFINITY};
+        T hm = (T)0;
         if (lane < c) {
             const int64_t p = f + lane;
-            double v[3] = {(double)xs[p], (double)ys[p], (double)zs[p]};
+            const T v[3] = {xs[p], ys[p], zs[p]};
             for (int d = 0; d < 3; ++d) { lo[d] = v[d]; hi[d] = v[d]; }
-            hm = (double)hs[p];
+            hm = hs[p];
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -715,11 +775,11 @@ __global__ __launch_bounds__(64) void k_grp_info(const int32_t *__restrict__ n_g
         if (lane == 0) {
             gcount[g] = (int32_t)c;
             for (int d = 0; d < 3; ++d) {
-                gbox[6 * g + d] = lo[d];
-                gbox[6 * g + 3 + d] = hi[d];
-                gcen[3 * g + d] = (double)(T)(0.5 * (lo[d] + hi[d]));
+                gbox[6 * g + d] = (double)lo[d];
+                gbox[6 * g + 3 + d] = (double)hi[d];
+                gcen[3 * g + d] = (double)(T)(0.5 * ((double)lo[d] + (double)hi[d]));
             }
-            ghmax[g] = hm;
+            ghmax[g] = (double)hm;
         }
     }
 }
@@ -747,13 +807,13 @@ sf_status build_groups(sf_grav_tree_s *t, DevArena &ar) {
                        t->nchild, t->nnchild, gcap, mark);
     scan_u32(mark, idx, n, scr, (uint32_t *)t->n_groups_dev, s);
     hipLaunchKernelGGL(k_grp_write, dim3(nblk(n)), dim3(256), 0, s, mark, idx, n, t->gfirst);
-    const int blocks = 4096;
+    const int blocks = 16384;   // four waves per block, one group per wave
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_grp_info<float>, dim3(blocks), dim3(64), 0, s, t->n_groups_dev, n,
+        hipLaunchKernelGGL(k_grp_info<float>, dim3(blocks), dim3(256), 0, s, t->n_groups_dev, n,
                            t->gfirst, t->gcount, (const float *)t->xs, (const float *)t->ys,
                            (const float *)t->zs, (const float *)t->hs, t->gbox, t->ghmax, t->gcen);
     else
-        hipLaunchKernelGGL(k_grp_info<double>, dim3(blocks), dim3(64), 0, s, t->n_groups_dev, n,
+        hipLaunchKernelGGL(k_grp_info<double>, dim3(blocks), dim3(256), 0, s, t->n_groups_dev, n,
                            t->gfirst, t->gcount, (const double *)t->xs, (const double *)t->ys,
                            (const double *)t->zs, (const double *)t->hs, t->gbox, t->ghmax,
                            t->gcen);
