@@ -255,9 +255,10 @@ __global__ __launch_bounds__(64) void k_sink_sink_b(const int32_t *__restrict__ 
 }
 
 template <typename T>
-static void sink_sink_backward(sf_grav_tree_s *t, const void *g_acc, const void *g_pot, double *ssb) {
+static void sink_sink_backward(sf_grav_tree_s *t, const void *g_acc, const void *g_pot, double *ssb,
+                               hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
-    hipLaunchKernelGGL(k_sink_sink_b<T>, dim3(blocks), dim3(64), 0, t->stream, t->sink_pos,
+    hipLaunchKernelGGL(k_sink_sink_b<T>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
                        t->n_sink, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
                        (const T *)t->ms, (const T *)t->hs, t->order, (const T *)g_acc,
                        (const T *)g_pot, ssb);
@@ -286,7 +287,7 @@ static sf_status direct_backward_run(sf_grav_tree_s *t, const EvalOpts &o, const
     double *ssb = nullptr;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
-        sink_sink_backward<T>(t, g_acc, g_pot, ssb);
+        sink_sink_backward<T>(t, g_acc, g_pot, ssb, s);
     }
     const unsigned blocks = (unsigned)((t->n_tiles + 3) / 4);
     hipLaunchKernelGGL((k_direct_b<T, FORM>), dim3(blocks), dim3(256), 0, s, n, ng, t->n_gas_tiles,
@@ -900,55 +901,111 @@ __global__ void k_sum_copies(double *__restrict__ base, int64_t len) {
     }
 }
 
-// Push node adjoints down to particles, add every part and write the output.
-// For each sorted particle: walk its leaf's ancestors; set 0 (all particles)
-// always, set 1 (gas only) for gas particles.
+// Node adjoints summed along each leaf's ancestor path (the leaf included).
+// For a node of mass Mn, centre of mass c and adjoint numbers a9 (dL/dM,
+// dL/dcom, and dL/dQ up to a multiple of the identity with the zz component
+// 0 and the off-diagonals stored doubled), a particle of mass m at x,
+// y = x - c, receives
+//   dL/dx += m (a/Mn + K y),   dL/dm += a0 + a.y/Mn + y'K y/2,
+// with K = 6 Gq - 2 tr(Gq) I and Gq the symmetric dL/dQ.  Writing y = u + e
+// with u = x - r (r the leaf's cube centre) and e = r - c, the sum over the
+// path is one quadratic in u:
+//   dL/dx += m (V + KK u),     dL/dm += S0 + V.u + u'KK u/2,
+//   V = sum(a/Mn + K e), KK = sum K, S0 = sum(a0 + a.e/Mn + e'K e/2).
+// poly holds per leaf and set: V (3), KK (xx yy zz xy xz yz), S0.
+constexpr int kPoly = 10;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_poly(
+    int64_t nn, const int32_t *__restrict__ nnchild, const int32_t *__restrict__ nparent,
+    const double *__restrict__ clo, const double *__restrict__ chi,
+    const double *__restrict__ M0, const double *__restrict__ com0,
+    const double *__restrict__ M1, const double *__restrict__ com1,
+    const double *__restrict__ nadj0, const double *__restrict__ nadj1, int sets,
+    double *__restrict__ poly) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn || nnchild[k] != 0) return;
+    double r[3];
+    for (int d = 0; d < 3; ++d) r[d] = 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
+    for (int set = 0; set < sets; ++set) {
+        const double *Ms = set ? M1 : M0;
+        const double *cs = set ? com1 : com0;
+        const double *ad = set ? nadj1 : nadj0;
+        double V[3] = {0.0, 0.0, 0.0}, KK[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, S0 = 0.0;
+        for (int64_t nd = k; nd >= 0; nd = nparent[nd]) {
+            const double Mn = Ms[nd];
+            if (!(Mn > 0.0)) continue;
+            double a9[9];
+            for (int c = 0; c < 9; ++c) a9[c] = ad[c * nn + nd];
+            const double e0 = r[0] - cs[3 * nd], e1 = r[1] - cs[3 * nd + 1], e2 = r[2] - cs[3 * nd + 2];
+            const double gxx = a9[4], gyy = a9[5], gxy = 0.5 * a9[6], gxz = 0.5 * a9[7],
+                         gyz = 0.5 * a9[8];
+            const double tr2 = 2.0 * (gxx + gyy);
+            // K = 6 Gq - 2 tr I (Gq zz = 0)
+            const double kxx = 6.0 * gxx - tr2, kyy = 6.0 * gyy - tr2, kzz = -tr2;
+            const double kxy = 6.0 * gxy, kxz = 6.0 * gxz, kyz = 6.0 * gyz;
+            const double Ke0 = kxx * e0 + kxy * e1 + kxz * e2;
+            const double Ke1 = kxy * e0 + kyy * e1 + kyz * e2;
+            const double Ke2 = kxz * e0 + kyz * e1 + kzz * e2;
+            const double inv = 1.0 / Mn;
+            V[0] += a9[1] * inv + Ke0;
+            V[1] += a9[2] * inv + Ke1;
+            V[2] += a9[3] * inv + Ke2;
+            KK[0] += kxx;
+            KK[1] += kyy;
+            KK[2] += kzz;
+            KK[3] += kxy;
+            KK[4] += kxz;
+            KK[5] += kyz;
+            S0 += a9[0] + (a9[1] * e0 + a9[2] * e1 + a9[3] * e2) * inv +
+                  0.5 * (e0 * Ke0 + e1 * Ke1 + e2 * Ke2);
+        }
+        double *q = poly + ((int64_t)set * nn + k) * kPoly;
+        for (int d = 0; d < 3; ++d) q[d] = V[d];
+        for (int d = 0; d < 6; ++d) q[3 + d] = KK[d];
+        q[9] = S0;
+    }
+}
+
+// Every part of each particle's adjoint, added and written in input order:
+// target part, source part (all per-XCD copies), the leaf polynomials of set
+// 0 (all particles) and set 1 (gas only), and the sink-sink part.
 template <typename T>
 __global__ void k_pushdown(int64_t n, int64_t n_gas, int64_t nn, const T *__restrict__ xs,
                            const T *__restrict__ ys, const T *__restrict__ zs,
                            const T *__restrict__ ms, const int32_t *__restrict__ order,
-                           const int32_t *__restrict__ pleaf, const int32_t *__restrict__ nparent,
-                           const double *__restrict__ M0, const double *__restrict__ com0,
-                           const double *__restrict__ M1, const double *__restrict__ com1,
-                           const double *__restrict__ nadj0, const double *__restrict__ nadj1,
-                           const double *__restrict__ tgt, const double *__restrict__ scat,
+                           const int32_t *__restrict__ pleaf, const double *__restrict__ clo,
+                           const double *__restrict__ chi, const double *__restrict__ poly,
+                           int sets, const double *__restrict__ tgt, const double *__restrict__ scat,
                            const int32_t *__restrict__ sink_pos, int64_t n_sink,
                            const double *__restrict__ ssb, double G, T *__restrict__ g_pos,
                            T *__restrict__ g_mass, T *__restrict__ g_soft) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const double x[3] = {(double)xs[s], (double)ys[s], (double)zs[s]};
     const double m = (double)ms[s];
     const int64_t o = order[s];
     const bool gas = o < n_gas;
     double g[5];
-    for (int d = 0; d < 5; ++d) g[d] = tgt[5 * s + d] + scat[d * n + s];
+    for (int d = 0; d < 5; ++d) {
+        double v = tgt[5 * s + d];
+#pragma unroll
+        for (int x = 0; x < kXcd; ++x) v += scat[(int64_t)x * 5 * n + d * n + s];
+        g[d] = v;
+    }
+    const int64_t lf = pleaf[s];
+    const double u0 = (double)xs[s] - 0.5 * (clo[3 * lf] + chi[3 * lf]);
+    const double u1 = (double)ys[s] - 0.5 * (clo[3 * lf + 1] + chi[3 * lf + 1]);
+    const double u2 = (double)zs[s] - 0.5 * (clo[3 * lf + 2] + chi[3 * lf + 2]);
     for (int set = 0; set < 2; ++set) {
-        if (set == 1 && !gas) break;
-        const double *Ms = set ? M1 : M0;
-        const double *cs = set ? com1 : com0;
-        const double *ad = set ? nadj1 : nadj0;
-        for (int64_t nd = pleaf[s]; nd >= 0; nd = nparent[nd]) {
-            const double Mn = Ms[nd];
-            if (!(Mn > 0.0)) continue;
-            double a9[9];
-            for (int c = 0; c < 9; ++c) a9[c] = ad[c * nn + nd];
-            const double y0 = x[0] - cs[3 * nd], y1 = x[1] - cs[3 * nd + 1], y2 = x[2] - cs[3 * nd + 2];
-            // dL/dQ up to a multiple of the identity (zz component 0); the
-            // off-diagonal numbers are stored doubled
-            const double gxx = a9[4], gyy = a9[5], gzz = 0.0, gxy = 0.5 * a9[6],
-                         gxz = 0.5 * a9[7], gyz = 0.5 * a9[8];
-            const double tr = gxx + gyy + gzz;
-            const double Gy0 = gxx * y0 + gxy * y1 + gxz * y2;
-            const double Gy1 = gxy * y0 + gyy * y1 + gyz * y2;
-            const double Gy2 = gxz * y0 + gyz * y1 + gzz * y2;
-            const double w = m / Mn;
-            g[0] += w * a9[1] + m * (6.0 * Gy0 - 2.0 * tr * y0);
-            g[1] += w * a9[2] + m * (6.0 * Gy1 - 2.0 * tr * y1);
-            g[2] += w * a9[3] + m * (6.0 * Gy2 - 2.0 * tr * y2);
-            g[3] += a9[0] + (a9[1] * y0 + a9[2] * y1 + a9[3] * y2) / Mn +
-                    3.0 * (y0 * Gy0 + y1 * Gy1 + y2 * Gy2) - (y0 * y0 + y1 * y1 + y2 * y2) * tr;
-        }
+        if (set >= sets || (set == 1 && !gas)) break;
+        const double *q = poly + ((int64_t)set * nn + lf) * kPoly;
+        const double Ku0 = q[3] * u0 + q[6] * u1 + q[7] * u2;
+        const double Ku1 = q[6] * u0 + q[4] * u1 + q[8] * u2;
+        const double Ku2 = q[7] * u0 + q[8] * u1 + q[5] * u2;
+        g[0] += m * (q[0] + Ku0);
+        g[1] += m * (q[1] + Ku1);
+        g[2] += m * (q[2] + Ku2);
+        g[3] += q[9] + q[0] * u0 + q[1] * u1 + q[2] * u2 + 0.5 * (u0 * Ku0 + u1 * Ku1 + u2 * Ku2);
     }
     if (!gas && ssb) {
         int64_t lo = 0, hi = n_sink;   // rank of s among the sorted sink positions
@@ -1005,25 +1062,29 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
     return a;
 }
 
+// The sink walk goes on the side stream first (after the sink-sink part),
+// the group walk on the caller's stream; each has its own task counter and
+// stack area.
 template <typename T, int FORM, int ORDER>
 static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
                            const void *g_pot, double *tgt, double *scat, double *nadj0,
-                           double *nadj1, int32_t *ctr, uint32_t *gstack) {
+                           double *nadj1, int32_t *ctr, uint32_t *gstack, uint32_t *sstack,
+                           hipStream_t side) {
     const unsigned grid = (unsigned)walk_grid();
+    if (t->n_sink > 0) {
+        WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + kCtrSinks);
+        as.err = ctr + kCtrErr;
+        as.gstack = sstack;
+        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
+        phase_begin(t, 9, side);
+        hipLaunchKernelGGL((k_walk_sinks_b<T, FORM, ORDER>), dim3(gs), dim3(64), 0, side, as);
+        phase_end(t, 9, side);
+    }
     WalkArgsB<T> ag = make_args_b<T>(t, o, 0, g_acc, g_pot, tgt, scat, nadj0, ctr);
     ag.gstack = gstack;
     phase_begin(t, 8);
     hipLaunchKernelGGL((k_walk_groups_b<T, FORM, ORDER>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 8);
-    if (t->n_sink > 0) {
-        WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + kCtrSinks);
-        as.err = ctr + kCtrErr;
-        as.gstack = gstack;
-        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
-        phase_begin(t, 9);
-        hipLaunchKernelGGL((k_walk_sinks_b<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
-        phase_end(t, 9);
-    }
 }
 
 template <typename T>
@@ -1041,18 +1102,27 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     SF_ALLOC_TMP(ar, scat, kXcd * 5 * n);
     SF_ALLOC_TMP(ar, nadj0, kXcd * 9 * nn);
     SF_ALLOC_TMP(ar, nadj1, kXcd * 9 * nn);
+    double *poly;
+    SF_ALLOC_TMP(ar, poly, 2 * kPoly * nn);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, s);
     fill_u32((uint32_t *)tgt, 10 * n, 0u, s);
     fill_u32((uint32_t *)scat, kXcd * 10 * n, 0u, s);
     fill_u32((uint32_t *)nadj0, kXcd * 18 * nn, 0u, s);
     fill_u32((uint32_t *)nadj1, kXcd * 18 * nn, 0u, s);
+    uint32_t *sstack = nullptr;
+    hipStream_t side = s;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
-        phase_begin(t, 7);
-        sink_sink_backward<T>(t, g_acc, g_pot, ssb);
-        phase_end(t, 7);
+        SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
+        if (hipStream_t sd = side_stream(t->device)) side = sd;
+        sf_status st = side_fork(t, side);
+        if (st != SF_OK) return st;
+        phase_begin(t, 7, side);
+        sink_sink_backward<T>(t, g_acc, g_pot, ssb, side);
+        phase_end(t, 7, side);
     }
-#define SF_WB(F, O) launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr, gstack)
+#define SF_WB(F, O)                                                                                \
+    launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr, gstack, sstack, side)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_WB(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_WB(SF_FP32, 0);
@@ -1063,17 +1133,23 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
         else SF_WB(SF_FP64, 2);
     }
 #undef SF_WB
+    if (t->n_sink > 0) {
+        sf_status st = side_join(t, side);
+        if (st != SF_OK) return st;
+    }
     phase_begin(t, 10);
-    const unsigned rb = (unsigned)std::min<int64_t>(8192, (10 * nn + 255) / 256);
-    hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, scat, (int64_t)5 * n);
+    const unsigned rb = (unsigned)std::min<int64_t>(8192, (9 * nn + 255) / 256);
+    const int sets = t->n_sink > 0 ? 2 : 1;   // set 1 adjoints come from the sink walk only
     hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj0, (int64_t)9 * nn);
     if (t->n_sink > 0)
         hipLaunchKernelGGL(k_sum_copies, dim3(rb), dim3(256), 0, s, nadj1, (int64_t)9 * nn);
+    hipLaunchKernelGGL(k_leaf_poly<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, nn,
+                       t->nnchild, t->nparent, t->clo, t->chi, t->M[0], t->com[0], t->M[1],
+                       t->com[1], nadj0, nadj1, sets, poly);
     hipLaunchKernelGGL(k_pushdown<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        t->n_gas, nn, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
-                       (const T *)t->ms, t->order, t->pleaf, t->nparent, t->M[0], t->com[0],
-                       t->M[1], t->com[1], nadj0, nadj1, tgt, scat, t->sink_pos, t->n_sink, ssb,
-                       o.G, (T *)g_pos, (T *)g_mass, (T *)g_soft);
+                       (const T *)t->ms, t->order, t->pleaf, t->clo, t->chi, poly, sets, tgt, scat,
+                       t->sink_pos, t->n_sink, ssb, o.G, (T *)g_pos, (T *)g_mass, (T *)g_soft);
     phase_end(t, 10);
     SF_HIP(hipGetLastError());
     int32_t herr = 0;

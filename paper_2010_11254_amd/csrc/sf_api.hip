@@ -146,7 +146,7 @@ static void event_put(hipEvent_t e) {
     g_events.push_back(e);
 }
 
-void phase_begin(sf_grav_tree_s *t, int ph) {
+void phase_begin(sf_grav_tree_s *t, int ph, hipStream_t st) {
     if (!t->timing) return;
     if (!t->ev0[ph]) {
         t->ev0[ph] = event_get();
@@ -158,13 +158,65 @@ void phase_begin(sf_grav_tree_s *t, int ph) {
             return;
         }
     }
-    (void)hipEventRecord(t->ev0[ph], t->stream);
+    (void)hipEventRecord(t->ev0[ph], st ? st : t->stream);
 }
 
-void phase_end(sf_grav_tree_s *t, int ph) {
+void phase_end(sf_grav_tree_s *t, int ph, hipStream_t st) {
     if (!t->timing || !t->ev0[ph]) return;
-    (void)hipEventRecord(t->ev1[ph], t->stream);
+    (void)hipEventRecord(t->ev1[ph], st ? st : t->stream);
     t->ev_used[ph] = true;
+}
+
+// One side stream per device, created on first use (default priority,
+// non-blocking) and kept until the process ends.
+static std::mutex g_side_mu;
+static hipStream_t g_side[64] = {};
+
+hipStream_t side_stream(int device) {
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+        if (cur != device && hipSetDevice(device) != hipSuccess) return nullptr;
+        hipStream_t st = nullptr;
+        const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_side[device] = st;
+    }
+    return g_side[device];
+}
+
+static sf_status ensure_event(hipEvent_t *e) {
+    if (*e) return SF_OK;
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        *e = nullptr;
+        return sf_fail(SF_E_INTERNAL, "hipEventCreateWithFlags failed");
+    }
+    return SF_OK;
+}
+
+sf_status side_fork(sf_grav_tree_s *t, hipStream_t side) {
+    if (side == t->stream) return SF_OK;
+    sf_status st = ensure_event(&t->ev_fork);
+    if (st != SF_OK) return st;
+    SF_HIP(hipEventRecord(t->ev_fork, t->stream));
+    SF_HIP(hipStreamWaitEvent(side, t->ev_fork, 0));
+    return SF_OK;
+}
+
+sf_status side_join(sf_grav_tree_s *t, hipStream_t side) {
+    if (side == t->stream) return SF_OK;
+    sf_status st = ensure_event(&t->ev_join);
+    if (st != SF_OK) return st;
+    SF_HIP(hipEventRecord(t->ev_join, side));
+    SF_HIP(hipStreamWaitEvent(t->stream, t->ev_join, 0));
+    return SF_OK;
 }
 
 static void phase_reset(sf_grav_tree_s *t, int lo, int hi) {
@@ -220,6 +272,9 @@ static void free_handle_memory(sf_grav_tree_s *t) {
         sf::event_put(t->ev1[p]);
         t->ev0[p] = t->ev1[p] = nullptr;
     }
+    if (t->ev_fork) (void)hipEventDestroy(t->ev_fork);
+    if (t->ev_join) (void)hipEventDestroy(t->ev_join);
+    t->ev_fork = t->ev_join = nullptr;
 }
 
 extern "C" {

@@ -75,14 +75,23 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
                           const void *g_pot, void *g_pos, void *g_mass, void *g_soft,
                           DevArena &ar);
 
-// FP64 sink-sink direct sum into acc4 (4 doubles per sink: ax ay az phi).
-void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4);
+// FP64 sink-sink direct sum into acc4 (4 doubles per sink: ax ay az phi),
+// launched on stream st.
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4, hipStream_t st);
+
+// Second stream of the device for the sink work, which runs beside the group
+// walk: side_fork makes it wait for the work queued so far on t->stream,
+// side_join makes t->stream wait for the work queued so far on it.
+hipStream_t side_stream(int device);
+sf_status side_fork(sf_grav_tree_s *t, hipStream_t side);
+sf_status side_join(sf_grav_tree_s *t, hipStream_t side);
 
 int device_cu_count();
 int walk_grid();
 
-// Phase timer helpers: no-ops unless t->timing.
-void phase_begin(sf_grav_tree_s *t, int ph);
-void phase_end(sf_grav_tree_s *t, int ph);
+// Phase timer helpers: no-ops unless t->timing.  Events go on st (t->stream
+// when null).
+void phase_begin(sf_grav_tree_s *t, int ph, hipStream_t st = nullptr);
+void phase_end(sf_grav_tree_s *t, int ph, hipStream_t st = nullptr);
 
 }  // namespace sf

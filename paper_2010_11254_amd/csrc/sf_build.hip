@@ -229,14 +229,15 @@ __global__ void k_topo_lcp(const uint64_t *__restrict__ keys, int64_t n, int cap
     if (s + cap < n) win[s] = (uint8_t)lcp_digits(k, keys[s + cap]);
 }
 
-// Leaf level lambda(s), node count of s, level histogram.  The block's window
+// Leaf level lambda(s), node count of s, and the block's level histogram,
+// written to column l of part (part[l * nb + block]).  The block's window
 // bytes (positions base - cap .. base + 255, cap <= 64) are staged in LDS; the
 // histogram takes one ballot per level per wave.
 __global__ __launch_bounds__(256) void k_topo_count(const uint8_t *__restrict__ lcp,
                                                     const uint8_t *__restrict__ win, int64_t n,
                                                     int cap, uint8_t *__restrict__ lam,
                                                     uint32_t *__restrict__ nn,
-                                                    uint32_t *__restrict__ levhist) {
+                                                    uint32_t *__restrict__ part) {
     __shared__ uint8_t sw[256 + 64];
     __shared__ uint32_t sh[kLevels + 1];
     if (threadIdx.x <= kLevels) sh[threadIdx.x] = 0;
@@ -265,20 +266,36 @@ __global__ __launch_bounds__(256) void k_topo_count(const uint8_t *__restrict__ 
         if ((threadIdx.x & 63) == 0 && b) atomicAdd(&sh[l], (uint32_t)__popcll(b));
     }
     __syncthreads();
-    if (threadIdx.x <= kLevels && sh[threadIdx.x]) atomicAdd(&levhist[threadIdx.x], sh[threadIdx.x]);
+    if (threadIdx.x <= kLevels) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x];
+}
+
+// Block b writes the sum of part[b * nb .. b * nb + nb) to out[b] (the level
+// histogram from the per-block columns; the leaf count from per-block counts).
+__global__ __launch_bounds__(256) void k_topo_levsum(const uint32_t *__restrict__ part, int64_t nb,
+                                                     uint32_t *__restrict__ out) {
+    __shared__ uint32_t sw[4];
+    const uint32_t *col = part + (int64_t)blockIdx.x * nb;
+    uint32_t v = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 256) v += col[i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = sw[0] + sw[1] + sw[2] + sw[3];
 }
 
 // level_off[0..22] (exclusive prefix of the level histogram) and the 256-entry
 // digit-offset table for the counting pass by level.
 __global__ void k_topo_levoff(const uint32_t *__restrict__ levhist, uint32_t *__restrict__ level_off,
-                              uint32_t *__restrict__ digit_off) {
+                              uint32_t *__restrict__ digit_off, uint32_t *__restrict__ max_level) {
     if (threadIdx.x != 0) return;
-    uint32_t run = 0;
+    uint32_t run = 0, lmax = 0;
     for (int l = 0; l <= kLevels; ++l) {
         level_off[l] = run;
         digit_off[l] = run;
         run += levhist[l];
+        if (levhist[l]) lmax = (uint32_t)l;
     }
+    *max_level = lmax;
     level_off[kLevels + 1] = run;
     for (int d = kLevels + 1; d < 256; ++d) digit_off[d] = run;
 }
@@ -295,28 +312,37 @@ __global__ void k_topo_emit(const uint8_t *__restrict__ lcp, const uint8_t *__re
     for (int l = lo; l <= L; ++l) packed[o + (l - lo)] = ((uint64_t)s << 8) | (uint64_t)l;
 }
 
-// first index in [a, b) of the packed array whose first particle is >= s
-__device__ __forceinline__ int64_t lower_first(const uint64_t *__restrict__ p, int64_t a, int64_t b,
-                                               uint64_t s) {
-    while (a < b) {
-        int64_t m = (a + b) >> 1;
-        if ((p[m] >> 8) < s) a = m + 1; else b = m;
-    }
-    return a;
+// DFS position of every BFS node: node (s, l) was emitted at
+// dfs_off[s] + l - lo(s), lo(s) = lcp[s] + 1 (0 for s = 0).
+__global__ void k_topo_inv(const uint64_t *__restrict__ packed, int64_t n_nodes,
+                           const uint8_t *__restrict__ lcp, const uint32_t *__restrict__ dfs_off,
+                           uint32_t *__restrict__ inv) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_nodes) return;
+    const uint64_t pk = packed[k];
+    const int l = (int)(pk & 255);
+    const int64_t s = (int64_t)(pk >> 8);
+    const int lo = s == 0 ? 0 : (int)lcp[s] + 1;
+    inv[dfs_off[s] + (l - lo)] = (uint32_t)k;
 }
 
+// Node fields from the BFS array.  The cell end comes from a galloping search
+// of the keys; an inner node (s, l) has first child (s, l + 1), the next DFS
+// entry of particle s, and its children are the consecutive level-(l + 1)
+// nodes whose first particle lies before the end.  Each inner node writes its
+// own child fields and its children's parent links.
 __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nodes,
                               const uint64_t *__restrict__ keys, int64_t n, int cap,
                               const uint32_t *__restrict__ level_off, const Frame *__restrict__ frame,
+                              const uint8_t *__restrict__ lcp, const uint32_t *__restrict__ dfs_off,
+                              const uint32_t *__restrict__ inv,
                               int32_t *__restrict__ nlevel, int32_t *__restrict__ nfirst,
                               int32_t *__restrict__ ncount, int32_t *__restrict__ nparent,
                               int32_t *__restrict__ nchild, int32_t *__restrict__ nnchild,
                               double *__restrict__ clo, double *__restrict__ chi,
-                              uint32_t *__restrict__ stats /* [0]=max level, [1]=leaves */) {
+                              uint32_t *__restrict__ leaf_part) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = k < n_nodes;
-    // per-wave statistics, one atomic per wave (ballots cover the lanes
-    // beyond n_nodes as zeros)
     const uint64_t pk = valid ? packed[k] : 0ull;
     const int l = (int)(pk & 255);
     const int64_t s = (int64_t)(pk >> 8);
@@ -332,7 +358,6 @@ __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nod
         }
         // keys[lo - 1] <= kmax and (hi == n or keys[hi] > kmax)
         int64_t lo = s + 1 + (step >> 2), hi = a < n ? a : n;
-        if (step == 1) lo = s + 1;
         while (lo < hi) {
             const int64_t m = (lo + hi) >> 1;
             if (keys[m] <= kmax) lo = m + 1; else hi = m;
@@ -341,31 +366,30 @@ __global__ void k_topo_fields(const uint64_t *__restrict__ packed, int64_t n_nod
     }
     const int64_t cnt = end - s;
     const bool leaf = cnt <= cap || l == kLevels;
-    {
+    {   // the block's leaf count (summed over blocks by a later launch)
+        __shared__ uint32_t sl[4];
         const uint32_t nleaf = (uint32_t)__popcll(__ballot(valid && leaf));
-        int lmax = valid ? l : 0;
-        for (int off = 32; off > 0; off >>= 1) lmax = max(lmax, __shfl_xor(lmax, off, 64));
-        if ((threadIdx.x & 63) == 0) {
-            if (nleaf) atomicAdd(&stats[1], nleaf);
-            atomicMax(&stats[0], (uint32_t)lmax);
-        }
+        if ((threadIdx.x & 63) == 0) sl[threadIdx.x >> 6] = nleaf;
+        __syncthreads();
+        if (threadIdx.x == 0) leaf_part[blockIdx.x] = sl[0] + sl[1] + sl[2] + sl[3];
     }
     if (!valid) return;
     nlevel[k] = l;
     nfirst[k] = (int32_t)s;
     ncount[k] = (int32_t)cnt;
-    // parent: last node of level l-1 whose first particle is <= s
-    if (l > 0) {
-        int64_t p = lower_first(packed, level_off[l - 1], level_off[l], (uint64_t)s + 1) - 1;
-        nparent[k] = (int32_t)p;
-    } else {
-        nparent[k] = -1;
-    }
+    if (l == 0) nparent[k] = -1;
     if (!leaf) {
-        int64_t c0 = lower_first(packed, level_off[l + 1], level_off[l + 2], (uint64_t)s);
-        int64_t c1 = lower_first(packed, c0, level_off[l + 2], (uint64_t)end);
+        const int lo = s == 0 ? 0 : (int)lcp[s] + 1;
+        const int64_t di = (int64_t)dfs_off[s] + (l - lo) + 1;   // below n_nodes by construction
+        const int64_t c0 = di < n_nodes ? (int64_t)inv[di] : n_nodes;
+        const int64_t cend = level_off[l + 2];
+        int64_t c = c0;
+        while (c < cend && (int64_t)(packed[c] >> 8) < end) {
+            nparent[c] = (int32_t)k;
+            ++c;
+        }
         nchild[k] = (int32_t)c0;
-        nnchild[k] = (int32_t)(c1 - c0);
+        nnchild[k] = (int32_t)(c - c0);
     } else {
         nchild[k] = -1;
         nnchild[k] = 0;
@@ -399,10 +423,14 @@ sf_status build_topology(sf_grav_tree_s *t, DevArena &ar) {
     SF_HIP(hipMemsetAsync(misc, 0, 320 * sizeof(uint32_t), s));
     SF_ALLOC_TMP(ar, scr, scan_scratch_words(n));
     hipLaunchKernelGGL(k_topo_lcp, dim3(nblk(n)), dim3(256), 0, s, t->keys, n, cap, lcp, win);
-    hipLaunchKernelGGL(k_topo_count, dim3(nblk(n)), dim3(256), 0, s, lcp, win, n, cap, lam, nn,
-                       levhist);
+    const int64_t nb = nblk(n);
+    uint32_t *part;
+    SF_ALLOC_TMP(ar, part, (kLevels + 1) * nb);
+    hipLaunchKernelGGL(k_topo_count, dim3(nb), dim3(256), 0, s, lcp, win, n, cap, lam, nn, part);
+    hipLaunchKernelGGL(k_topo_levsum, dim3(kLevels + 1), dim3(256), 0, s, part, nb, levhist);
     scan_u32(nn, dfs, n, scr, misc + 304, s);
-    hipLaunchKernelGGL(k_topo_levoff, dim3(1), dim3(64), 0, s, levhist, misc + 24, misc + 48);
+    hipLaunchKernelGGL(k_topo_levoff, dim3(1), dim3(64), 0, s, levhist, misc + 24, misc + 48,
+                       misc + 305);
     uint32_t hmisc[24 + 23];
     SF_HIP(hipMemcpyAsync(hmisc, misc + 24, 23 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     SF_HIP(hipStreamSynchronize(s));
@@ -424,9 +452,16 @@ sf_status build_topology(sf_grav_tree_s *t, DevArena &ar) {
     SF_ALLOC(ar, t->nnchild, nn_total);
     SF_ALLOC(ar, t->clo, 3 * nn_total);
     SF_ALLOC(ar, t->chi, 3 * nn_total);
+    uint32_t *inv, *leaf_part;
+    SF_ALLOC_TMP(ar, inv, nn_total);
+    SF_ALLOC_TMP(ar, leaf_part, nblk(nn_total));
+    hipLaunchKernelGGL(k_topo_inv, dim3(nblk(nn_total)), dim3(256), 0, s, pbfs, nn_total, lcp, dfs,
+                       inv);
     hipLaunchKernelGGL(k_topo_fields, dim3(nblk(nn_total)), dim3(256), 0, s, pbfs, nn_total,
-                       t->keys, n, cap, misc + 24, t->frame, t->nlevel, t->nfirst, t->ncount,
-                       t->nparent, t->nchild, t->nnchild, t->clo, t->chi, misc + 305);
+                       t->keys, n, cap, misc + 24, t->frame, lcp, dfs, inv, t->nlevel, t->nfirst,
+                       t->ncount, t->nparent, t->nchild, t->nnchild, t->clo, t->chi, leaf_part);
+    hipLaunchKernelGGL(k_topo_levsum, dim3(1), dim3(256), 0, s, leaf_part, (int64_t)nblk(nn_total),
+                       misc + 306);
     SF_HIP(hipGetLastError());
     SF_HIP(hipMemcpyAsync(t->info_dev, misc + 305, 2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     return SF_OK;
@@ -473,12 +508,12 @@ __device__ __forceinline__ void raw_store(double *raw, int64_t k, const RawMom &
     p[10] = r.h;
 }
 
-__device__ __forceinline__ void raw_load_dev(const double *raw, int64_t k, RawMom &r) {
+__device__ __forceinline__ void raw_load(const double *raw, int64_t k, RawMom &r) {
     const double *p = raw + 11 * k;
-    r.M = ld_dev(p);
-    for (int d = 0; d < 3; ++d) r.D[d] = ld_dev(p + 1 + d);
-    for (int d = 0; d < 6; ++d) r.S[d] = ld_dev(p + 4 + d);
-    r.h = ld_dev(p + 10);
+    r.M = p[0];
+    for (int d = 0; d < 3; ++d) r.D[d] = p[1 + d];
+    for (int d = 0; d < 6; ++d) r.S[d] = p[4 + d];
+    r.h = p[10];
 }
 
 // Shift child moments from its centre gc to the parent centre g and add.
@@ -501,96 +536,136 @@ __device__ __forceinline__ void centre(const double *clo, const double *chi, int
     for (int d = 0; d < 3; ++d) g[d] = 0.5 * (clo[3 * k + d] + chi[3 * k + d]);
 }
 
-// Inner node k from its children, each shifted from its centre to k's
-// centre, in child order.  Children written by other workgroups of the same
-// kernel are read with device-scope loads after the caller's acquire fence.
-__device__ __forceinline__ void node_from_children(int64_t k, const int32_t *__restrict__ nchild,
-                                                   const int32_t *__restrict__ nnchild,
-                                                   const double *__restrict__ clo,
-                                                   const double *__restrict__ chi, double *raw0,
-                                                   double *raw1) {
-    double gp[3];
-    centre(clo, chi, k, gp);
+// Lane exchange inside rows of the wave (DPP, a VALU operation): CTRL 0xB1
+// swaps lanes 2i and 2i+1, 0x4E swaps pairs within each quad, 0x141 mirrors
+// each group of eight lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void raw_dpp_add(RawMom &r) {
+    r.M += dpp_d<CTRL>(r.M);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) r.D[d] += dpp_d<CTRL>(r.D[d]);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) r.S[d] += dpp_d<CTRL>(r.S[d]);
+    r.h = fmax(r.h, dpp_d<CTRL>(r.h));
+}
+
+// Sum of the raw moments held by each aligned group of eight lanes (every
+// lane of a group active): pairs, quads, then the mirrored quad.  Lane 0 of
+// the group holds the sum, in the same order on every run.
+__device__ __forceinline__ void raw_group_sum8(RawMom &r) {
+    raw_dpp_add<0xB1>(r);
+    raw_dpp_add<0x4E>(r);
+    raw_dpp_add<0x141>(r);
+}
+
+// Leaves: sums over their particles about the cube centre (and each
+// particle's leaf index, used by the adjoint).  Eight lanes per node, lane j
+// taking particles j, j + 8, ...; the whole group leaves together for inner
+// nodes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_moments_leaf(
+    int64_t n_nodes, const int32_t *__restrict__ nfirst, const int32_t *__restrict__ ncount,
+    const int32_t *__restrict__ nnchild, const double *__restrict__ clo,
+    const double *__restrict__ chi, const T *__restrict__ xs, const T *__restrict__ ys,
+    const T *__restrict__ zs, const T *__restrict__ ms, const T *__restrict__ hs,
+    const int32_t *__restrict__ order, int64_t n_gas, double *__restrict__ raw0,
+    double *__restrict__ raw1, int32_t *__restrict__ pleaf) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = gid >> 3;
+    const int j = (int)(gid & 7);
+    if (k >= n_nodes || nnchild[k] != 0) return;
+    double g[3];
+    centre(clo, chi, k, g);
     RawMom ra, rg;
     raw_zero(ra);
     raw_zero(rg);
-    const int64_t c0 = nchild[k], c1 = c0 + nnchild[k];
-    for (int64_t ch = c0; ch < c1; ++ch) {
-        double gc[3], dl[3];
-        centre(clo, chi, ch, gc);
-        for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
-        RawMom cm;
-        raw_load_dev(raw0, ch, cm);
-        raw_add_child(ra, cm, dl);
-        raw_load_dev(raw1, ch, cm);
-        raw_add_child(rg, cm, dl);
+    const int64_t f = nfirst[k], e = f + ncount[k];
+    for (int64_t p = f + j; p < e; p += 8) {
+        pleaf[p] = (int32_t)k;
+        const double m = (double)ms[p], h = (double)hs[p];
+        const double y0 = (double)xs[p] - g[0], y1 = (double)ys[p] - g[1], y2 = (double)zs[p] - g[2];
+        raw_add_point(ra, m, y0, y1, y2, h);
+        if (order[p] < n_gas) raw_add_point(rg, m, y0, y1, y2, h);
     }
-    raw_store(raw0, k, ra);
-    raw_store(raw1, k, rg);
-}
-
-// All raw moments in one pass.  A thread per leaf sums its particles about
-// the cube centre (and records each particle's leaf index, used by the
-// adjoint), then climbs: it counts itself in at the parent, and the child
-// that arrives last computes the parent from all children, in child order,
-// and climbs on.  Every inner node is computed once, by one thread, with the
-// same arithmetic whatever the arrival order.  arrive[] starts at zero.
-template <typename T>
-__global__ __launch_bounds__(256) void k_moments_up(
-    int64_t n_nodes, const int32_t *__restrict__ nfirst, const int32_t *__restrict__ ncount,
-    const int32_t *__restrict__ nchild, const int32_t *__restrict__ nnchild,
-    const int32_t *__restrict__ nparent, const double *__restrict__ clo,
-    const double *__restrict__ chi, const T *__restrict__ xs, const T *__restrict__ ys,
-    const T *__restrict__ zs, const T *__restrict__ ms, const T *__restrict__ hs,
-    const int32_t *__restrict__ order, int64_t n_gas, double *raw0, double *raw1,
-    int32_t *__restrict__ pleaf, uint32_t *arrive) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_nodes || nnchild[k] != 0) return;
-    {
-        double g[3];
-        centre(clo, chi, k, g);
-        RawMom ra, rg;
-        raw_zero(ra);
-        raw_zero(rg);
-        const int64_t f = nfirst[k], e = f + ncount[k];
-        // four particles' loads in flight at a time, added in particle order
-        for (int64_t p0 = f; p0 < e; p0 += 4) {
-            double m4[4], h4[4], y4[4][3];
-            bool gas[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t p = p0 + j;
-                if (p < e) {
-                    m4[j] = (double)ms[p];
-                    h4[j] = (double)hs[p];
-                    y4[j][0] = (double)xs[p] - g[0];
-                    y4[j][1] = (double)ys[p] - g[1];
-                    y4[j][2] = (double)zs[p] - g[2];
-                    gas[j] = order[p] < n_gas;
-                    pleaf[p] = (int32_t)k;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (p0 + j < e) {
-                    raw_add_point(ra, m4[j], y4[j][0], y4[j][1], y4[j][2], h4[j]);
-                    if (gas[j]) raw_add_point(rg, m4[j], y4[j][0], y4[j][1], y4[j][2], h4[j]);
-                }
-            }
-        }
+    raw_group_sum8(ra);
+    raw_group_sum8(rg);
+    if (j == 0) {
         raw_store(raw0, k, ra);
         raw_store(raw1, k, rg);
     }
-    for (int64_t c = k;;) {
-        const int64_t p = nparent[c];
-        if (p < 0) break;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // c's moments before the count
-        const uint32_t before = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-        if (before + 1 != (uint32_t)nnchild[p]) break;        // a sibling is still to come
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the siblings' moments
-        node_from_children(p, nchild, nnchild, clo, chi, raw0, raw1);
-        c = p;
+}
+
+// Inner node k from its children, eight lanes per node, lane j shifting child
+// j from its centre to k's centre; lane 0 stores the group's sum.
+__device__ __forceinline__ void node_from_children8(int64_t k, int j, const int32_t *__restrict__ nchild,
+                                                    const int32_t *__restrict__ nnchild,
+                                                    const double *__restrict__ clo,
+                                                    const double *__restrict__ chi, double *raw0,
+                                                    double *raw1) {
+    RawMom ra, rg;
+    raw_zero(ra);
+    raw_zero(rg);
+    if (j < nnchild[k]) {
+        const int64_t ch = nchild[k] + j;
+        double gp[3], gc[3], dl[3];
+        centre(clo, chi, k, gp);
+        centre(clo, chi, ch, gc);
+        for (int d = 0; d < 3; ++d) dl[d] = gc[d] - gp[d];
+        RawMom cm;
+        raw_load(raw0, ch, cm);
+        raw_add_child(ra, cm, dl);
+        raw_load(raw1, ch, cm);
+        raw_add_child(rg, cm, dl);
+    }
+    raw_group_sum8(ra);
+    raw_group_sum8(rg);
+    if (j == 0) {
+        raw_store(raw0, k, ra);
+        raw_store(raw1, k, rg);
+    }
+}
+
+// Inner nodes of one level (their children were done by earlier launches).
+__global__ __launch_bounds__(256) void k_moments_level(int64_t k0, int64_t k1,
+                                                       const int32_t *__restrict__ nchild,
+                                                       const int32_t *__restrict__ nnchild,
+                                                       const double *__restrict__ clo,
+                                                       const double *__restrict__ chi,
+                                                       double *raw0, double *raw1) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = k0 + (gid >> 3);
+    if (k >= k1 || nnchild[k] == 0) return;
+    node_from_children8(k, (int)(gid & 7), nchild, nnchild, clo, chi, raw0, raw1);
+}
+
+struct LevelRange {
+    int64_t off[kLevels + 2];
+};
+
+// Inner nodes of the small levels l_hi, l_hi - 1, ..., l_lo in one workgroup,
+// deepest first, a barrier between levels (one launch instead of one per
+// level where a level has few nodes).
+__global__ __launch_bounds__(1024) void k_moments_levels(LevelRange lr, int l_hi, int l_lo,
+                                                         const int32_t *__restrict__ nchild,
+                                                         const int32_t *__restrict__ nnchild,
+                                                         const double *__restrict__ clo,
+                                                         const double *__restrict__ chi,
+                                                         double *raw0, double *raw1) {
+    for (int l = l_hi; l >= l_lo; --l) {
+        for (int64_t base = lr.off[l]; base < lr.off[l + 1]; base += blockDim.x / 8) {
+            const int64_t k = base + (threadIdx.x >> 3);
+            if (k < lr.off[l + 1] && nnchild[k] != 0)   // uniform over each group of 8
+                node_from_children8(k, threadIdx.x & 7, nchild, nnchild, clo, chi, raw0, raw1);
+        }
+        __syncthreads();
     }
 }
 
@@ -674,21 +749,37 @@ sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
         SF_ALLOC(ar, t->nw[set], nn);
         SF_ALLOC(ar, t->nq[set], nn);
     }
-    uint32_t *arrive;
-    SF_ALLOC_TMP(ar, arrive, nn);
-    fill_u32(arrive, nn, 0u, s);
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_moments_up<float>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
-                           t->ncount, t->nchild, t->nnchild, t->nparent, t->clo, t->chi,
-                           (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
-                           (const float *)t->ms, (const float *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, t->pleaf, arrive);
+        hipLaunchKernelGGL(k_moments_leaf<float>, dim3(nblk(8 * nn)), dim3(256), 0, s, nn,
+                           t->nfirst, t->ncount, t->nnchild, t->clo, t->chi, (const float *)t->xs,
+                           (const float *)t->ys, (const float *)t->zs, (const float *)t->ms,
+                           (const float *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
     else
-        hipLaunchKernelGGL(k_moments_up<double>, dim3(nblk(nn)), dim3(256), 0, s, nn, t->nfirst,
-                           t->ncount, t->nchild, t->nnchild, t->nparent, t->clo, t->chi,
-                           (const double *)t->xs, (const double *)t->ys, (const double *)t->zs,
-                           (const double *)t->ms, (const double *)t->hs, t->order, t->n_gas, raw0,
-                           raw1, t->pleaf, arrive);
+        hipLaunchKernelGGL(k_moments_leaf<double>, dim3(nblk(8 * nn)), dim3(256), 0, s, nn,
+                           t->nfirst, t->ncount, t->nnchild, t->clo, t->chi, (const double *)t->xs,
+                           (const double *)t->ys, (const double *)t->zs, (const double *)t->ms,
+                           (const double *)t->hs, t->order, t->n_gas, raw0, raw1, t->pleaf);
+    // inner nodes, deepest level first (level offsets are known on the host);
+    // runs of consecutive small levels share one single-workgroup launch
+    constexpr int64_t kSmallLevel = 128;   // one pass of the 1024-lane workgroup
+    LevelRange lr;
+    for (int l = 0; l <= kLevels + 1; ++l) lr.off[l] = t->level_off[l];
+    for (int l = kLevels - 1; l >= 0;) {
+        const int64_t k0 = t->level_off[l], k1 = t->level_off[l + 1];
+        if (k1 - k0 > kSmallLevel) {
+            if (t->level_off[l + 2] > t->level_off[l + 1])   // some children below
+                hipLaunchKernelGGL(k_moments_level, dim3(nblk(8 * (k1 - k0))), dim3(256), 0, s, k0, k1,
+                                   t->nchild, t->nnchild, t->clo, t->chi, raw0, raw1);
+            --l;
+            continue;
+        }
+        int lo = l;
+        while (lo > 0 && t->level_off[lo] - t->level_off[lo - 1] <= kSmallLevel) --lo;
+        if (t->level_off[l + 1] > t->level_off[lo])   // some nodes in the run
+            hipLaunchKernelGGL(k_moments_levels, dim3(1), dim3(1024), 0, s, lr, l, lo, t->nchild,
+                               t->nnchild, t->clo, t->chi, raw0, raw1);
+        l = lo - 1;
+    }
     double *raws[2] = {raw0, raw1};
     for (int set = 0; set < 2; ++set)
         hipLaunchKernelGGL(k_moments_final, dim3(nblk(nn)), dim3(256), 0, s, nn, t->clo, t->chi,

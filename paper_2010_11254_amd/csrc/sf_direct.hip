@@ -211,7 +211,7 @@ static sf_status direct_run(sf_grav_tree_s *t, const EvalOpts &o, void *acc, voi
     double *ss = nullptr;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
-        sink_sink_accel(t, o.G, ss);
+        sink_sink_accel(t, o.G, ss, t->stream);
     }
     const unsigned blocks = (unsigned)((t->n_tiles + 3) / 4);
     hipLaunchKernelGGL((k_direct<T, FORM>), dim3(blocks), dim3(256), 0, s, n, ng, t->n_gas_tiles,

@@ -184,5 +184,6 @@ struct sf_grav_tree_s {
     hipEvent_t ev0[kPhases] = {}, ev1[kPhases] = {};
     bool ev_used[kPhases] = {};
     bool timing = false;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // side-stream fork and join
     std::vector<void *> allocs;                       // device memory owned here
 };

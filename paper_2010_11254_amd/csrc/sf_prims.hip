@@ -170,7 +170,9 @@ __global__ void k_rs_offsets(uint32_t *hist, int passes) {
 // One stable scatter pass by the digit (key >> shift) & 255.  Within a tile,
 // wave w owns the contiguous segment [w*1024, (w+1)*1024) read in rounds of
 // 64 consecutive keys, so (round, lane) order is input order; ranks among
-// equal digits come from ballots, per-wave running counts live in LDS.
+// equal digits come from ballots, per-wave running counts live in LDS.  The
+// tile is reordered by digit in LDS first, so that the writes of each
+// digit's run go out from consecutive lanes to consecutive addresses.
 template <bool kHasVal>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
@@ -178,7 +180,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
     uint32_t *status, uint32_t *tile_ctr) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_cnt[kRsWaves][256];
-    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_base[256];     // global start of the tile's run of each digit
+    __shared__ uint32_t s_start[256];    // start of each digit's run within the tile
+    __shared__ uint32_t s_wsum[kRsWaves];
+    __shared__ uint64_t s_key[kRsTile];
+    __shared__ uint32_t s_val[kHasVal ? kRsTile : 1];
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
     for (int i = threadIdx.x; i < kRsWaves * 256; i += kRsThreads) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
@@ -212,7 +218,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
         if (!valid) rank[r] = 0xffffffffu;
     }
     __syncthreads();
-    // one thread per digit: per-wave exclusive offsets, tile total, look-back
+    // one thread per digit: per-wave exclusive offsets, tile total, the run
+    // starts within the tile (a scan over digits), look-back
     {
         const int d = threadIdx.x;
         uint32_t tot = 0;
@@ -222,6 +229,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
             s_cnt[w][d] = tot;
             tot += c;
         }
+        const uint32_t incl = wave_incl_scan(tot);
+        if (lane == 63) s_wsum[wid] = incl;
         uint32_t prefix = 0;
         if (tile == 0) {
             st_dev_u32(&status[d], kFlagPre | tot);
@@ -231,15 +240,31 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
             st_dev_u32(&status[tile * 256 + d], kFlagPre | ((prefix + tot) & kValMask));
         }
         s_base[d] = digit_off[d] + prefix;
+        __syncthreads();
+        uint32_t woff = 0;
+#pragma unroll
+        for (int w = 0; w < kRsWaves; ++w)
+            if (w < wid) woff += s_wsum[w];
+        s_start[d] = woff + incl - tot;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRsItems; ++r) {
         if (rank[r] == 0xffffffffu) continue;
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-        const uint32_t pos = s_base[d] + s_cnt[wid][d] + rank[r];
-        kout[pos] = key[r];
-        if (kHasVal) vout[pos] = val[r];
+        const uint32_t lp = s_start[d] + s_cnt[wid][d] + rank[r];
+        s_key[lp] = key[r];
+        if (kHasVal) s_val[lp] = val[r];
+    }
+    __syncthreads();
+    const int64_t left = n - tile * kRsTile;
+    const int tn = left < kRsTile ? (int)left : kRsTile;
+    for (int i = threadIdx.x; i < tn; i += kRsThreads) {
+        const uint64_t k = s_key[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = s_base[d] + (uint32_t)i - s_start[d];
+        kout[pos] = k;
+        if (kHasVal) vout[pos] = s_val[i];
     }
 }
 

@@ -366,16 +366,16 @@ __global__ __launch_bounds__(64) void k_sink_sink(const int32_t *__restrict__ si
     }
 }
 
-void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss) {
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss, hipStream_t st) {
     (void)G;
     if (t->n_sink <= 0) return;
     const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_sink_sink<float>, dim3(blocks), dim3(64), 0, t->stream, t->sink_pos,
+        hipLaunchKernelGGL(k_sink_sink<float>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
                            t->n_sink, (const float *)t->xs, (const float *)t->ys,
                            (const float *)t->zs, (const float *)t->ms, (const float *)t->hs, ss);
     else
-        hipLaunchKernelGGL(k_sink_sink<double>, dim3(blocks), dim3(64), 0, t->stream, t->sink_pos,
+        hipLaunchKernelGGL(k_sink_sink<double>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
                            t->n_sink, (const double *)t->xs, (const double *)t->ys,
                            (const double *)t->zs, (const double *)t->ms, (const double *)t->hs, ss);
 }
@@ -434,10 +434,21 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     return a;
 }
 
+// The sink walk (with the sink-sink sum before it) goes on the side stream
+// first, so that its waves share the device with the group walk; each walk
+// has its own task counter and stack area.
 template <typename T, int FORM, int ORDER>
 static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, int32_t *ctr,
-                         double *ss, uint32_t *gstack) {
+                         double *ss, uint32_t *gstack, uint32_t *sstack, hipStream_t side) {
     const unsigned grid = (unsigned)walk_grid();
+    if (t->n_sink > 0) {
+        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss, sstack);
+        as.err = ctr + kCtrErr;
+        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
+        phase_begin(t, 6, side);
+        hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, side, as);
+        phase_end(t, 6, side);
+    }
     WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss, gstack);
     phase_begin(t, 5);
     if (o.stats)
@@ -445,20 +456,13 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
     else
         hipLaunchKernelGGL((k_walk_groups<T, FORM, ORDER, false>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 5);
-    if (t->n_sink > 0) {
-        WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss, gstack);
-        as.err = ctr + kCtrErr;
-        const unsigned gs = (unsigned)std::min<int64_t>(t->n_sink, grid);
-        phase_begin(t, 6);
-        hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, t->stream, as);
-        phase_end(t, 6);
-    }
 }
 
 template <typename T>
 static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
-                           int32_t *ctr, double *ss, uint32_t *gstack) {
-#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss, gstack)
+                           int32_t *ctr, double *ss, uint32_t *gstack, uint32_t *sstack,
+                           hipStream_t side) {
+#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss, gstack, sstack, side)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_W(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_W(SF_FP32, 0);
@@ -474,15 +478,20 @@ static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
     int32_t *ctr = nullptr;
     double *ss = nullptr;
-    uint32_t *gstack = nullptr;
+    uint32_t *gstack = nullptr, *sstack = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
+    hipStream_t side = t->stream;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
-        phase_begin(t, 4);
-        sink_sink_accel(t, o.G, ss);
-        phase_end(t, 4);
+        SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
+        if (hipStream_t sd = side_stream(t->device)) side = sd;
+        sf_status st = side_fork(t, side);
+        if (st != SF_OK) return st;
+        phase_begin(t, 4, side);
+        sink_sink_accel(t, o.G, ss, side);
+        phase_end(t, 4, side);
     }
     if (o.stats) {
         if (!t->gnpc) {
@@ -496,9 +505,13 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
         t->have_stats = true;
     }
-    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack);
-    else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack);
+    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
+    else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
     SF_HIP(hipGetLastError());
+    if (t->n_sink > 0) {
+        sf_status st = side_join(t, side);
+        if (st != SF_OK) return st;
+    }
     int32_t herr = 0;
     SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));
     SF_HIP(hipStreamSynchronize(t->stream));
