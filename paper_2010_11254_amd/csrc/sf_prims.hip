@@ -24,8 +24,8 @@ void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
 // ---------------------------------------------------------------- scan
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 4096 values per tile
 
 // Wave-level inclusive scan of 32-bit values (64 lanes).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -57,6 +57,36 @@ __device__ __forceinline__ uint32_t look_back(uint32_t *status, int64_t tile, in
     return prefix;
 }
 
+// Look-back by one wave: lane i reads the status of tile t - i.  The nearest
+// tile with an inclusive prefix ends the walk once every tile between is
+// published; otherwise, with all 64 published, their aggregates are added and
+// the window moves 64 tiles back.  Tiles start in counter order, so every
+// earlier tile belongs to a running workgroup that will publish.
+__device__ __forceinline__ uint32_t wave_look_back(uint32_t *status, int64_t tile) {
+    const int lane = threadIdx.x & 63;
+    uint32_t prefix = 0;
+    int64_t t = tile - 1;
+    while (true) {
+        const int64_t j = t - lane;
+        const uint32_t v = j >= 0 ? ld_dev_u32(&status[j]) : kFlagPre;
+        const uint64_t wait = __ballot((v & ~kValMask) == 0);
+        const uint64_t pre = __ballot((v & kFlagPre) != 0);
+        if (pre) {
+            const int lp = __ffsll((long long)pre) - 1;
+            const uint64_t upto = lp == 63 ? ~0ull : ((1ull << (lp + 1)) - 1);
+            if (wait & upto) continue;
+            uint32_t x = lane <= lp ? (v & kValMask) : 0u;
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            return (prefix + x) & kValMask;
+        }
+        if (wait) continue;
+        uint32_t x = v & kValMask;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        prefix += x;
+        t -= 64;
+    }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_u32(const uint32_t *__restrict__ in,
                                                            uint32_t *__restrict__ out, int64_t n,
                                                            uint32_t *status, uint32_t *tile_ctr,
@@ -69,15 +99,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_u32(const uint32_t *__res
     const int64_t tile = s_tile;
     const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
+    if (base + kScanItems <= n) {   // whole run in range: four 16-byte loads
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q) {
+            const uint4 w = p[q];
+            v[4 * q] = w.x;
+            v[4 * q + 1] = w.y;
+            v[4 * q + 2] = w.z;
+            v[4 * q + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? in[base + k] : 0u;
+    }
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        v[k] = (i < n) ? in[i] : 0u;
-        sum += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t incl = wave_incl_scan(sum);
+    const uint32_t incl = wave_incl_scan(sum);
     if (lane == 63) s_wave[wid] = incl;
     __syncthreads();
     uint32_t wave_off = 0, tile_sum = 0;
@@ -86,26 +126,38 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_u32(const uint32_t *__res
         if (w < wid) wave_off += s_wave[w];
         tile_sum += s_wave[w];
     }
-    if (threadIdx.x == 0) {
+    if (wid == 0) {
+        uint32_t p = 0;
         if (tile == 0) {
-            st_dev_u32(&status[0], kFlagPre | tile_sum);
-            s_prefix = 0;
+            if (lane == 0) st_dev_u32(&status[0], kFlagPre | tile_sum);
         } else {
-            st_dev_u32(&status[tile], kFlagAgg | tile_sum);
-            uint32_t p = look_back(status, tile, 1, 0);
-            st_dev_u32(&status[tile], kFlagPre | ((p + tile_sum) & kValMask));
-            s_prefix = p;
+            if (lane == 0) st_dev_u32(&status[tile], kFlagAgg | tile_sum);
+            p = wave_look_back(status, tile);
+            if (lane == 0) st_dev_u32(&status[tile], kFlagPre | ((p + tile_sum) & kValMask));
         }
-        int64_t tiles = (n + kScanTile - 1) / kScanTile;
-        if (tile == tiles - 1 && total) *total = s_prefix + tile_sum;
+        if (lane == 0) {
+            s_prefix = p;
+            const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+            if (tile == tiles - 1 && total) *total = p + tile_sum;
+        }
     }
     __syncthreads();
     uint32_t run = s_prefix + wave_off + incl - sum;
+    uint32_t o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t i = base + k;
-        if (i < n) out[i] = run;
+        o[k] = run;
         run += v[k];
+    }
+    if (base + kScanItems <= n) {
+        uint4 *q4 = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+        for (int q = 0; q < kScanItems / 4; ++q)
+            q4[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < n) out[base + k] = o[k];
     }
 }
 
