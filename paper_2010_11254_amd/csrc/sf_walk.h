@@ -43,6 +43,8 @@ template <typename R> union StageBuf {
     PPStage<R> pp[64];
     PCStage<R> pc[64];
 };
+// The group walk sums its per-lane partials (4 doubles per lane) in the stage.
+static_assert(sizeof(StageBuf<float>) >= 4 * 64 * sizeof(double), "stage too small for the sums");
 
 // Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
 template <typename R>

@@ -54,11 +54,9 @@ struct WalkArgs {
 // ---------------------------------------------------------------- group mode
 
 // Batch staging for lane splitting: entry e of a batch (e < nb <= 64) goes to
-// LDS slot (e mod k) m + e / k with m = ceil(nb / k), so copy `sub` finds its
-// entries sub, sub + k, ... in the consecutive slots [sub m, sub m + m) and
-// every lane runs the same m steps.  Slots of entries e in [nb, k m) hold
-// zero-mass dummies far away, whose terms are exactly zero.
-constexpr float kFar = 1e15f;
+// LDS slot e; copy `sub` of a target (k copies) takes entries sub, sub + k, ...
+// in floor(nb / k) steps that every lane runs, plus one step for the copies
+// with an entry left over.
 
 template <typename T, int FORM, int ORDER>
 struct GroupEval {
@@ -74,35 +72,37 @@ struct GroupEval {
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
         const uint32_t e = threadIdx.x;
-        const uint32_t m = (nb + k - 1) / k;
-        if (e < k * m) {
+        if (e < nb) {
             PCStage<R> s;
-            if (e < nb) {
-                const int node = L.pc[(head + e) & 127];
-                const WalkNodes &nd = a->nd;
-                s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
-                s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
-                s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
-                s.M = (R)nd.w[node].M;
-                s.qxx = s.qyy = s.qxy = s.qxz = s.qyz = R(0);
-                if (ORDER == 2) {
-                    s.qxx = (R)nd.q[node].q[0];
-                    s.qyy = (R)nd.q[node].q[1];
-                    s.qxy = (R)nd.q[node].q[2];
-                    s.qxz = (R)nd.q[node].q[3];
-                    s.qyz = (R)nd.q[node].q[4];
-                }
-            } else {
-                s.x = s.y = s.z = R(kFar);
-                s.M = s.qxx = s.qyy = s.qxy = s.qxz = s.qyz = R(0);
+            const int node = L.pc[(head + e) & 127];
+            const WalkNodes &nd = a->nd;
+            s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            s.M = (R)nd.w[node].M;
+            s.qxx = s.qyy = s.qxy = s.qxz = s.qyz = R(0);
+            if (ORDER == 2) {
+                s.qxx = (R)nd.q[node].q[0];
+                s.qyy = (R)nd.q[node].q[1];
+                s.qxy = (R)nd.q[node].q[2];
+                s.qxz = (R)nd.q[node].q[3];
+                s.qyz = (R)nd.q[node].q[4];
             }
-            spc[(e % k) * m + e / k] = s;
+            spc[e] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        const PCStage<R> *src = spc + sub * m;
-        for (uint32_t j = 0; j < m; ++j) {
-            const PCStage<R> s = src[j];
+        // entries sub, sub + k, ...: nb / k steps with an entry on every lane,
+        // then one step for the lanes whose entry is left over
+        const uint32_t mf = nb / k;
+        const PCStage<R> *src = spc + sub;
+        for (uint32_t j = 0; j < mf; ++j) {
+            const PCStage<R> s = src[j * k];
+            multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
+                                s.qyz, bx, by, bz, bp);
+        }
+        if (sub + mf * k < nb) {
+            const PCStage<R> s = src[mf * k];
             multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
                                 s.qyz, bx, by, bz, bp);
         }
@@ -114,38 +114,35 @@ struct GroupEval {
     }
 
     template <bool SOFT>
+    __device__ __forceinline__ void pp_one(const PPStage<R> &s, R &bx, R &by, R &bz, R &bp) const {
+        if (SOFT)
+            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx, by,
+                    bz, bp);
+        else
+            pair_newton<R>(s.x - tx, s.y - ty, s.z - tz, s.m, bx, by, bz, bp);
+    }
+
+    template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const uint32_t e = threadIdx.x;
-        const uint32_t m = (nb + k - 1) / k;
-        if (e < k * m) {
+        if (e < nb) {
             PPStage<R> s;
-            if (e < nb) {
-                const int p = L.slot[e];
-                s.x = to_frame<FORM>(a->xs[p], cen[0]);
-                s.y = to_frame<FORM>(a->ys[p], cen[1]);
-                s.z = to_frame<FORM>(a->zs[p], cen[2]);
-                s.m = (R)a->ms[p];
-                s.h = (R)a->hs[p];
-                s.h2 = s.h * s.h;
-                s.idx = p;
-            } else {
-                s.x = s.y = s.z = R(kFar);
-                s.m = s.h = s.h2 = R(0);
-                s.idx = -1;
-            }
-            spp[(e % k) * m + e / k] = s;
+            const int p = L.slot[e];
+            s.x = to_frame<FORM>(a->xs[p], cen[0]);
+            s.y = to_frame<FORM>(a->ys[p], cen[1]);
+            s.z = to_frame<FORM>(a->zs[p], cen[2]);
+            s.m = (R)a->ms[p];
+            s.h = (R)a->hs[p];
+            s.h2 = s.h * s.h;
+            s.idx = p;
+            spp[e] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        const PPStage<R> *src = spp + sub * m;
-        for (uint32_t j = 0; j < m; ++j) {
-            const PPStage<R> s = src[j];
-            if (SOFT)
-                pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx,
-                        by, bz, bp);
-            else
-                pair_newton<R>(s.x - tx, s.y - ty, s.z - tz, s.m, bx, by, bz, bp);
-        }
+        const uint32_t mf = nb / k;
+        const PPStage<R> *src = spp + sub;
+        for (uint32_t j = 0; j < mf; ++j) pp_one<SOFT>(src[j * k], bx, by, bz, bp);
+        if (sub + mf * k < nb) pp_one<SOFT>(src[mf * k], bx, by, bz, bp);
         ax.fold(bx);
         ay.fold(by);
         az.fold(bz);
@@ -175,17 +172,18 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.cen[d] = a.gcen[3 * g + d];
         }
         const double hg = a.ghmax[g];
-        // Lane splitting: W = smallest power of two >= group size; each target
-        // gets k = 64/W lanes that share every batch's sources.
-        uint32_t W = 1;
-        while (W < (uint32_t)gc) W <<= 1;
-        const uint32_t k = 64u / W;
-        const uint32_t tl = (uint32_t)lane & (W - 1);
-        ev.sub = (uint32_t)lane / W;
+        // Lane splitting: each target gets k = floor(64 / group size) lanes;
+        // lane t + gc*s (s < k) takes target t's batch entries s, s + k, ...
+        // Lanes from k*gc on repeat the first copy and are left out of the sums.
+        const uint32_t gcu = (uint32_t)gc;
+        const uint32_t k = 64u / gcu;
+        const uint32_t tl = (uint32_t)lane % gcu;
+        const uint32_t sub = (uint32_t)lane / gcu;
+        const bool copy = sub < k;
+        ev.sub = copy ? sub : 0u;
         ev.k = k;
-        const bool has = tl < (uint32_t)gc;
-        const int64_t i = gf + (has ? tl : 0);
-        const bool active = has && a.order[i] < a.n_gas;
+        const int64_t i = gf + tl;
+        const bool active = a.order[i] < a.n_gas;
         uint32_t npc = 0, npp = 0;
         if (__ballot(active) != 0ull) {   // groups of sinks only are left to the sink walk
             ev.tx = to_frame<FORM>(a.xs[i], ev.cen[0]);
@@ -193,7 +191,7 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.tz = to_frame<FORM>(a.zs[i], ev.cen[2]);
             ev.th = (R)a.hs[i];
             ev.th2 = ev.th * ev.th;
-            ev.tidx = has ? (int32_t)i : -1;
+            ev.tidx = (int32_t)i;
             ev.ax.zero();
             ev.ay.zero();
             ev.az.zero();
@@ -201,9 +199,16 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
                       gf + gc, a.err, npc, npp);
             double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
-            for (uint32_t off = W; off < 64u; off <<= 1)
-                for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
-            if (active && ev.sub == 0) {
+            // sum the k copies of each target in a fixed order, through LDS
+            // (the stage is free once the task's batches are done)
+            double(*red)[64] = reinterpret_cast<double(*)[64]>(&stage);
+            for (int d = 0; d < 4; ++d) red[d][lane] = v[d];
+            __syncthreads();
+            if ((uint32_t)lane < gcu)
+                for (uint32_t c = 1; c < k; ++c)
+                    for (int d = 0; d < 4; ++d) v[d] += red[d][lane + c * gcu];
+            __syncthreads();
+            if (active && (uint32_t)lane < gcu) {
                 const int64_t o = a.order[i];
                 a.acc[3 * o] = (T)(a.G * v[0]);
                 a.acc[3 * o + 1] = (T)(a.G * v[1]);
