@@ -20,18 +20,21 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
 // Softened force and potential factors for r^2 < h^2 (M4 cubic spline with
 // support h): F = q(u)/r^3, P = psi(u)/h, u = r/h; both branches evaluated,
-// the inner one selected for u < 1/2.
+// the inner one selected for u < 1/2.  Taken from quantities the pair
+// evaluation already holds: ri = rsq(r2), h and its reciprocal hinv; the outer
+// branch's 1/u is h ri (2 at u <= 1/2, and at r = 0 where ri is infinite), so
+// no further reciprocal or square root is needed.
 template <typename R>
-__device__ __forceinline__ void soft_FP(R r2, R h, R &F, R &P) {
-    const R hinv = rcp(h);
-    const R r = r2 > R(0) ? r2 * rsq(r2) : R(0);
+__device__ __forceinline__ void soft_FP_ri(R r2, R ri, R h, R hinv, R &F, R &P) {
+    const R r = r2 > R(0) ? r2 * ri : R(0);
     const R u = r * hinv;
     const R u2 = u * u;
     const R hinv3 = hinv * hinv * hinv;
     const R Fi = R(32.0 / 3.0) + u2 * (R(-192.0 / 5.0) + R(32.0) * u);
     const R Pi = R(14.0 / 5.0) + u2 * (R(-16.0 / 3.0) + u2 * (R(48.0 / 5.0) + R(-32.0 / 5.0) * u));
     const R us = u > R(0.5) ? u : R(0.5);
-    const R iu = rcp(us);
+    const R hr = h * ri;
+    const R iu = hr < R(2) ? hr : R(2);
     const R Fo = R(64.0 / 3.0) + us * (R(-48.0) + us * (R(192.0 / 5.0) + us * R(-32.0 / 3.0))) -
                  R(1.0 / 15.0) * iu * iu * iu;
     const R Po = R(16.0 / 5.0) - R(1.0 / 15.0) * iu +

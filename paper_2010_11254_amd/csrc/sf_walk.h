@@ -36,7 +36,7 @@ struct WalkLds {
     int32_t slot[64];
 };
 
-template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h; int32_t idx; };
+template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h, hinv; int32_t idx; };
 template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz; };
 // One batch is staged at a time, so the particle and node stages share LDS.
 template <typename R> union StageBuf {
@@ -47,16 +47,18 @@ template <typename R> union StageBuf {
 static_assert(sizeof(StageBuf<float>) >= 4 * 64 * sizeof(double), "stage too small for the sums");
 
 // Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
+// hjinv, tiinv are the reciprocals of the two softening lengths (the support's
+// reciprocal is the smaller one).
 template <typename R>
-__device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R ti2, R ti, bool self,
-                                     R &bx, R &by, R &bz, R &bp) {
+__device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R hjinv, R ti2, R ti,
+                                     R tiinv, bool self, R &bx, R &by, R &bz, R &bp) {
     const R r2 = dx * dx + dy * dy + dz * dz;
     const R ri = rsq(r2);
     R P = ri;
     R F = ri * ri * ri;
     const R hh2 = hj2 > ti2 ? hj2 : ti2;
     if (r2 < hh2) {
-        soft_FP<R>(r2, hj > ti ? hj : ti, F, P);
+        soft_FP_ri<R>(r2, ri, hj > ti ? hj : ti, hjinv < tiinv ? hjinv : tiinv, F, P);
         if (self) { F = R(0); P = R(0); }
     }
     const R mF = m * F;

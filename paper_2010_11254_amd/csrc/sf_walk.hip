@@ -65,7 +65,8 @@ struct GroupEval {
     PPStage<R> *spp;
     PCStage<R> *spc;
     double cen[3];
-    R tx, ty, tz, th, th2;
+    R tx, ty, tz, th, th2, thinv;
+    R bl[3], bh[3], hg2;        // group box in the form's frame, largest h squared
     int32_t tidx;
     uint32_t sub, k;            // lane splitting: lane handles entries sub, sub+k, ...
     Acc<FORM> ax, ay, az, ap;
@@ -116,17 +117,35 @@ struct GroupEval {
     template <bool SOFT>
     __device__ __forceinline__ void pp_one(const PPStage<R> &s, R &bx, R &by, R &bz, R &bp) const {
         if (SOFT)
-            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, th2, th, s.idx == tidx, bx, by,
-                    bz, bp);
+            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, s.hinv, th2, th, thinv,
+                    s.idx == tidx, bx, by, bz, bp);
         else
             pair_newton<R>(s.x - tx, s.y - ty, s.z - tz, s.m, bx, by, bz, bp);
     }
 
+    // Entries [lo, lo + n) of the stage, copy `sub` taking lo + sub, lo + sub + k, ...
+    template <bool SOFT>
+    __device__ __forceinline__ void pp_run(uint32_t lo, uint32_t n, R &bx, R &by, R &bz,
+                                           R &bp) const {
+        const uint32_t mf = n / k;
+        const PPStage<R> *src = spp + lo + sub;
+        for (uint32_t j = 0; j < mf; ++j) pp_one<SOFT>(src[j * k], bx, by, bz, bp);
+        if (sub + mf * k < n) pp_one<SOFT>(src[mf * k], bx, by, bz, bp);
+    }
+
+    // SOFT batches (leaves that may hold softened pairs) are split once more
+    // per source particle: a source farther from the group box than
+    // max(its h, the group's largest h), with a relative margin that covers
+    // the rounding of both distances, has only Newtonian pairs with the
+    // group and runs the short loop; the rest (the task's own particles
+    // among them) run the softened one.  Target coordinates lie inside the
+    // box in the form's frame too, since rounding is monotone.
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const uint32_t e = threadIdx.x;
+        PPStage<R> s;
+        bool soft = false;
         if (e < nb) {
-            PPStage<R> s;
             const int p = L.slot[e];
             s.x = to_frame<FORM>(a->xs[p], cen[0]);
             s.y = to_frame<FORM>(a->ys[p], cen[1]);
@@ -134,15 +153,36 @@ struct GroupEval {
             s.m = (R)a->ms[p];
             s.h = (R)a->hs[p];
             s.h2 = s.h * s.h;
+            s.hinv = rcp(s.h);
             s.idx = p;
+            if (SOFT) {
+                const R gx = fmax(fmax(bl[0] - s.x, s.x - bh[0]), R(0));
+                const R gy = fmax(fmax(bl[1] - s.y, s.y - bh[1]), R(0));
+                const R gz = fmax(fmax(bl[2] - s.z, s.z - bh[2]), R(0));
+                const R d2 = gx * gx + gy * gy + gz * gz;
+                const R h2 = s.h2 > hg2 ? s.h2 : hg2;
+                soft = !(d2 > h2 * R(1.0001));
+            }
+        }
+        uint32_t ns = 0;
+        if (SOFT) {
+            const uint64_t msoft = __ballot(e < nb && soft);
+            ns = (uint32_t)popc64(msoft);
+            if (e < nb) {
+                const uint32_t below = (uint32_t)popc64(msoft & lane_mask_lt());
+                spp[soft ? below : ns + (e - below)] = s;   // softened part first
+            }
+        } else if (e < nb) {
             spp[e] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        const uint32_t mf = nb / k;
-        const PPStage<R> *src = spp + sub;
-        for (uint32_t j = 0; j < mf; ++j) pp_one<SOFT>(src[j * k], bx, by, bz, bp);
-        if (sub + mf * k < nb) pp_one<SOFT>(src[mf * k], bx, by, bz, bp);
+        if (SOFT) {
+            pp_run<false>(ns, nb - ns, bx, by, bz, bp);
+            pp_run<true>(0, ns, bx, by, bz, bp);
+        } else {
+            pp_run<false>(0, nb, bx, by, bz, bp);
+        }
         ax.fold(bx);
         ay.fold(by);
         az.fold(bz);
@@ -191,7 +231,17 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.tz = to_frame<FORM>(a.zs[i], ev.cen[2]);
             ev.th = (R)a.hs[i];
             ev.th2 = ev.th * ev.th;
+            ev.thinv = rcp(ev.th);
             ev.tidx = (int32_t)i;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                ev.bl[d] = dto_frame<FORM>(blo[d], ev.cen[d]);
+                ev.bh[d] = dto_frame<FORM>(bhi[d], ev.cen[d]);
+            }
+            {
+                const R hgr = (R)hg;
+                ev.hg2 = hgr * hgr;
+            }
             ev.ax.zero();
             ev.ay.zero();
             ev.az.zero();
@@ -279,8 +329,8 @@ struct SinkEval {
                 const R tz = FormT<FORM>::rel ? R(0) : (R)cen[2];
                 const R h = (R)a->hs[p];
                 if (SOFT)
-                    pair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, th2, th, p == tidx,
-                            bx, by, bz, bp);
+                    pair<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], h * h, h, rcp(h), th2, th,
+                            rcp(th), p == tidx, bx, by, bz, bp);
                 else
                     pair_newton<R>(sx - tx, sy - ty, sz - tz, (R)a->ms[p], bx, by, bz, bp);
             }
@@ -356,7 +406,7 @@ __global__ __launch_bounds__(64) void k_sink_sink(const int32_t *__restrict__ si
             const int64_t q = sink_pos[j];
             const double h = (double)hs[q];
             pair<double>((double)xs[q] - tx, (double)ys[q] - ty, (double)zs[q] - tz, (double)ms[q],
-                         h * h, h, th * th, th, false, bx, by, bz, bp);
+                         h * h, h, 1.0 / h, th * th, th, 1.0 / th, false, bx, by, bz, bp);
         }
         bx = wave_sum_f64(bx);
         by = wave_sum_f64(by);
