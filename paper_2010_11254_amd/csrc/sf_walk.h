@@ -33,14 +33,16 @@ struct WalkLds {
     int32_t pc[128];
     PPRing near;   // leaves that may hold softened pairs (incl. the task's own)
     PPRing far;    // leaves whose every pair with the task is Newtonian
-    int32_t slot[64];
+    int32_t slot[128];
 };
 
 template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h, hinv; int32_t idx; };
 template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz; };
 // One batch is staged at a time, so the particle and node stages share LDS.
+// Particle batches of the FP32 forms hold up to 128 entries.
+template <typename R> constexpr uint32_t kPPBatch = sizeof(R) == 4 ? 128u : 64u;
 template <typename R> union StageBuf {
-    PPStage<R> pp[64];
+    PPStage<R> pp[kPPBatch<R>];
     PCStage<R> pc[64];
 };
 // The group walk sums its per-lane partials (4 doubles per lane) in the stage.
@@ -247,9 +249,18 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
     return true;
 }
 
-// Walk one task.  Ev supplies pc_batch(L, head, nb) and
-// pp_batch<SOFT>(L, nb) (SOFT = false: every pair is Newtonian and none is a
-// self pair).
+// Gather up to 128 particle indices: ring_gather in passes of at most 64.
+__device__ __forceinline__ bool ring_gather_n(PPRing &R, uint32_t &h, uint32_t t, int32_t *slot,
+                                              uint32_t want, int32_t *err) {
+    if (want <= 64u) return ring_gather(R, h, t, slot, want, err);
+    if (!ring_gather(R, h, t, slot, 64u, err)) return false;
+    return ring_gather(R, h, t, slot + 64, want - 64u, err);
+}
+
+// Walk one task.  Ev supplies pc_batch(L, head, nb) (nb <= 64) and
+// pp_batch<SOFT>(L, nb) (nb <= ppb <= 128; SOFT = false: every pair is
+// Newtonian and none is a self pair).  A range ring is drained before it
+// holds more than 64 entries, so the next step's (at most 64) new entries fit.
 // Stack entries moved out of and back into LDS: device-scope relaxed
 // atomics, so the wave reads back exactly what it wrote (no stale L1 line).
 __device__ __forceinline__ void stack_out(uint32_t *p, uint32_t v) {
@@ -262,7 +273,8 @@ __device__ __forceinline__ uint32_t stack_in(const uint32_t *p) {
 template <class Ev>
 __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev &ev,
                           const double blo[3], const double bhi[3], double hg, int64_t gf,
-                          int64_t gl, int32_t *err, uint32_t &n_pc, uint32_t &n_pp) {
+                          int64_t gl, int32_t *err, uint32_t &n_pc, uint32_t &n_pp,
+                          uint32_t ppb = 64u) {
     const int lane = threadIdx.x;
     const uint64_t lt = lane_mask_lt();
     uint32_t sp = 1;     // stack positions [0, sp)
@@ -351,17 +363,19 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
             pc_h += 64;
             n_pc += 64;
         }
-        while (fpend >= 64u) {
-            if (!ring_gather(L.far, fh, ft, L.slot, 64, err)) { fpend = 0; break; }
-            ev.template pp_batch<false>(L, 64);
-            fpend -= 64;
-            n_pp += 64;
+        while (fpend >= ppb || ft - fh > 64u) {
+            const uint32_t nb = fpend < ppb ? fpend : ppb;
+            if (!ring_gather_n(L.far, fh, ft, L.slot, nb, err)) { fpend = 0; break; }
+            ev.template pp_batch<false>(L, nb);
+            fpend -= nb;
+            n_pp += nb;
         }
-        while (npend >= 64u) {
-            if (!ring_gather(L.near, nh, nt, L.slot, 64, err)) { npend = 0; break; }
-            ev.template pp_batch<true>(L, 64);
-            npend -= 64;
-            n_pp += 64;
+        while (npend >= ppb || nt - nh > 64u) {
+            const uint32_t nb = npend < ppb ? npend : ppb;
+            if (!ring_gather_n(L.near, nh, nt, L.slot, nb, err)) { npend = 0; break; }
+            ev.template pp_batch<true>(L, nb);
+            npend -= nb;
+            n_pp += nb;
         }
     }
     if (pc_t > pc_h) {
@@ -369,13 +383,13 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         n_pc += pc_t - pc_h;
     }
     if (fpend > 0) {
-        if (ring_gather(L.far, fh, ft, L.slot, fpend, err)) {
+        if (ring_gather_n(L.far, fh, ft, L.slot, fpend, err)) {
             ev.template pp_batch<false>(L, fpend);
             n_pp += fpend;
         }
     }
     if (npend > 0) {
-        if (ring_gather(L.near, nh, nt, L.slot, npend, err)) {
+        if (ring_gather_n(L.near, nh, nt, L.slot, npend, err)) {
             ev.template pp_batch<true>(L, npend);
             n_pp += npend;
         }

@@ -67,6 +67,7 @@ struct GroupEval {
     double cen[3];
     R tx, ty, tz, th, th2, thinv;
     R bl[3], bh[3], hg2;        // group box in the form's frame, largest h squared
+    uint32_t nsoft, nnewt;      // partition counts of the particle batch being staged
     int32_t tidx;
     uint32_t sub, k;            // lane splitting: lane handles entries sub, sub+k, ...
     Acc<FORM> ax, ay, az, ap;
@@ -142,7 +143,29 @@ struct GroupEval {
     // box in the form's frame too, since rounding is monotone.
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
-        const uint32_t e = threadIdx.x;
+        nsoft = nnewt = 0;
+        for (uint32_t r = 0; r < nb; r += 64u) stage_pp<SOFT>(L, r + threadIdx.x, nb);
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        if (SOFT) {
+            const uint32_t ns = nsoft;
+            pp_run<false>(ns, nb - ns, bx, by, bz, bp);
+            pp_run<true>(0, ns, bx, by, bz, bp);
+        } else {
+            pp_run<false>(0, nb, bx, by, bz, bp);
+        }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+
+    // Stage entry e of a particle batch; all lanes call it once per round of
+    // 64 entries (SOFT: the possibly softened entries first, the Newtonian-only
+    // ones after them).
+    template <bool SOFT>
+    __device__ __forceinline__ void stage_pp(WalkLds &L, uint32_t e, uint32_t nb) {
         PPStage<R> s;
         bool soft = false;
         if (e < nb) {
@@ -164,30 +187,21 @@ struct GroupEval {
                 soft = !(d2 > h2 * R(1.0001));
             }
         }
-        uint32_t ns = 0;
         if (SOFT) {
+            // softened entries of earlier rounds of 64 are counted in nsoft,
+            // Newtonian ones fill the stage from the end
             const uint64_t msoft = __ballot(e < nb && soft);
-            ns = (uint32_t)popc64(msoft);
+            const uint64_t mnewt = __ballot(e < nb && !soft);
+            const uint64_t lt = lane_mask_lt();
             if (e < nb) {
-                const uint32_t below = (uint32_t)popc64(msoft & lane_mask_lt());
-                spp[soft ? below : ns + (e - below)] = s;   // softened part first
+                if (soft) spp[nsoft + (uint32_t)popc64(msoft & lt)] = s;
+                else spp[nb - 1 - (nnewt + (uint32_t)popc64(mnewt & lt))] = s;
             }
+            nsoft += (uint32_t)popc64(msoft);
+            nnewt += (uint32_t)popc64(mnewt);
         } else if (e < nb) {
             spp[e] = s;
         }
-        __syncthreads();
-        R bx = 0, by = 0, bz = 0, bp = 0;
-        if (SOFT) {
-            pp_run<false>(ns, nb - ns, bx, by, bz, bp);
-            pp_run<true>(0, ns, bx, by, bz, bp);
-        } else {
-            pp_run<false>(0, nb, bx, by, bz, bp);
-        }
-        ax.fold(bx);
-        ay.fold(by);
-        az.fold(bz);
-        ap.fold(bp);
-        __syncthreads();
     }
 };
 
@@ -247,7 +261,7 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.az.zero();
             ev.ap.zero();
             walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
-                      gf + gc, a.err, npc, npp);
+                      gf + gc, a.err, npc, npp, kPPBatch<R>);
             double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
             // sum the k copies of each target in a fixed order, through LDS
             // (the stage is free once the task's batches are done)
