@@ -14,7 +14,7 @@ import torch
 
 from oracle import direct as odirect
 from oracle import tree as otree
-from synth import clustered_cloud, uniform_sphere
+from synth import ParticleSet, clustered_cloud, uniform_sphere
 
 pytestmark = pytest.mark.gpu
 
@@ -228,3 +228,43 @@ def test_tree_theta_zero_deep_stack_is_direct():
     ar, pr = odirect.direct(ps.x, ps.m, ps.h)
     assert np.max(_relerr(a, ar)) < 1e-11
     assert np.max(np.abs(p - pr) / np.abs(pr)) < 1e-11
+
+
+def _lattice(side, h_cells, jitter, seed, dtype):
+    """side^3 lattice points at multiples of 1/16 (exact in FP32), masses
+    around 1/n, softening h_cells/16 times (1 + jitter * U(-1, 1))."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(side, dtype=np.float64) / 16.0
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    n = x.shape[0]
+    m = rng.uniform(0.5, 1.5, n) / n
+    h = (h_cells / 16.0) * (1.0 + jitter * rng.uniform(-1.0, 1.0, n))
+    return ParticleSet(x=x.astype(dtype), m=m.astype(dtype), h=h.astype(dtype), n_gas=n)
+
+
+@pytest.mark.parametrize("h_cells,jitter", [(1.0, 0.0), (2.5, 0.3)])
+def test_tree_lattice_softening_boundary(h_cells, jitter):
+    # A lattice puts many pairs exactly at (h_cells = 1) or around the
+    # softening radius and many near-leaf particles right at max(h) from a
+    # group box, where the walk decides per particle between the softened
+    # and the Newtonian-only evaluation; both forms must match the oracle
+    # tree, and the same lists must be formed.
+    _say("tree lattice 12^3, h =", h_cells, "cells, jitter", jitter)
+    for form, dt, tol in (("fp64", np.float64, 1e-10), ("fp32c", np.float32, 2e-5)):
+        ps = _lattice(12, h_cells, jitter, seed=11, dtype=dt)
+        a, p, t = gpu_tree(ps, form, leaf_cap=8, group_cap=32, stats=True, keep=True)
+        x64, m64, h64 = (v.astype(np.float64) for v in (ps.x, ps.m, ps.h))
+        ar, pr, lists = otree.tree_forward(x64, m64, h64, ps.n_gas, theta=0.5, order=2,
+                                           leaf_cap=8, group_cap=32)
+        L = _lib()
+        npc = L.sf_grav_tree_export(t, "group_npc").numpy()
+        npp = L.sf_grav_tree_export(t, "group_npp").numpy()
+        L.sf_grav_tree_free(t)
+        for g, (pc, pp) in lists.gas_lists.items():
+            assert npc[g] == pc.size and npp[g] == pp.size, (form, g)
+        # errors against the RMS field (lattice symmetry leaves some targets
+        # with a nearly cancelled acceleration)
+        e = np.linalg.norm(a - ar, axis=1) / np.sqrt(np.mean(np.sum(ar * ar, axis=1)))
+        ep = np.abs(p - pr) / np.sqrt(np.mean(pr * pr))
+        assert np.max(e) < tol and np.max(ep) < tol, (form, np.max(e), np.max(ep))
+
