@@ -181,37 +181,23 @@ constexpr int kCtrSinks = kCtrStride;
 constexpr int kCtrErr = kCtrSinks + kCtrStride;
 constexpr int kCtrWords = kCtrErr + kCtrStride;
 
-// Prefix sums and totals over the wave of non-negative values, from one
-// ballot per bit: no cross-lane data movement, and the total is a scalar.
-// Values are usually below 2^BITS; the higher bits are visited only when a
-// lane has one set (a leaf at the depth limit can hold any number of
-// particles).
-__device__ __forceinline__ uint32_t bit_prefix(uint32_t v, int b) {
-    const uint32_t bit = (v >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    const uint32_t below =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    return (below + bit) << b;
-}
-
-template <int BITS>
+// Prefix sums and totals over the wave (called with all 64 lanes active):
+// an inclusive scan by DPP, one VALU add per stage -- row shifts by 1, 2, 4
+// and 8 lanes (lanes without a source add 0), then the last lane of rows 0
+// and 2 added to rows 1 and 3, and the last lane of row 1 to rows 2 and 3.
+// The total is lane 63's value, read into a scalar register.
 __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) s += bit_prefix(v, b);
-    if (__ballot(v >> BITS) != 0ull)
-        for (int b = BITS; b < 32; ++b) s += bit_prefix(v, b);
-    return s;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return v;
 }
 
-template <int BITS>
 __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) s += (uint32_t)popc64(__ballot((v >> b) & 1u)) << b;
-    if (__ballot(v >> BITS) != 0ull)
-        for (int b = BITS; b < 32; ++b) s += (uint32_t)popc64(__ballot((v >> b) & 1u)) << b;
-    return s;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(v), 63);
 }
 
 // Gather `want` (<= 64) particle indices from the front of a range ring into
@@ -228,7 +214,7 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
     const uint32_t q = (h + lane) & 127;
     const int32_t f = have ? R.f[q] : 0;
     const uint32_t c = have ? (uint32_t)R.c[q] : 0u;
-    const uint32_t incl = wave_scan_incl<7>(c);
+    const uint32_t incl = wave_scan_incl(c);
     const uint32_t excl = incl - c;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     if (total < want) {
@@ -306,7 +292,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         const int ei = (int)sp - 1 - lane;
         const uint32_t ent = ei >= 0 ? L.stack[ei & kStackMask] : 0u;
         const uint32_t cnt = ent & 15u;
-        const uint32_t incl = wave_scan_incl<4>(cnt);   // an entry holds 1..8 nodes
+        const uint32_t incl = wave_scan_incl(cnt);   // an entry holds 1..8 nodes
         const bool take = ei >= 0 && incl <= 64u;
         const uint32_t ntake = (uint32_t)popc64(__ballot(take));
         const uint32_t nnodes = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ntake - 1);
@@ -337,8 +323,8 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         }
         nt += (uint32_t)popc64(mnear);
         ft += (uint32_t)popc64(mfar);
-        npend += wave_total<7>(lcn);
-        fpend += wave_total<7>(lcf);
+        npend += wave_total(lcn);
+        fpend += wave_total(lcf);
         const uint32_t npush = (uint32_t)popc64(mint);
         if (sp + npush > (uint32_t)kStack) {   // cannot happen (see header); stop safely
             if (lane == 0) atomicOr(err, 1);
