@@ -213,35 +213,49 @@ __global__ __launch_bounds__(256) void k_direct_b(int64_t n, int64_t n_gas, int6
     if (g_soft) g_soft[o] = (T)(G * v[4]);
 }
 
-// FP64 sink-sink adjoint: one wave per sink target, lanes stride the sources.
+// Sink records for the sink-sink adjoint, gathered once into one contiguous
+// FP64 array: x y z m h and the cotangents a_x a_y a_z phi of the sink.
+constexpr int kSinkRecB = 9;
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_sink_sink_b(const int32_t *__restrict__ sink_pos,
-                                                    int64_t n_sink, const T *__restrict__ xs,
-                                                    const T *__restrict__ ys,
-                                                    const T *__restrict__ zs,
-                                                    const T *__restrict__ ms,
-                                                    const T *__restrict__ hs,
-                                                    const int32_t *__restrict__ order,
-                                                    const T *__restrict__ g_acc,
-                                                    const T *__restrict__ g_pot,
-                                                    double *__restrict__ ssb) {
+__global__ void k_sink_gather_b(const int32_t *__restrict__ sink_pos, int64_t n_sink,
+                                const T *__restrict__ xs, const T *__restrict__ ys,
+                                const T *__restrict__ zs, const T *__restrict__ ms,
+                                const T *__restrict__ hs, const int32_t *__restrict__ order,
+                                const T *__restrict__ g_acc, const T *__restrict__ g_pot,
+                                double *__restrict__ rec) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_sink) return;
+    const int64_t p = sink_pos[k];
+    const int64_t o = order[p];
+    double *r = rec + kSinkRecB * k;
+    r[0] = (double)xs[p];
+    r[1] = (double)ys[p];
+    r[2] = (double)zs[p];
+    r[3] = (double)ms[p];
+    r[4] = (double)hs[p];
+    r[5] = (double)g_acc[3 * o];
+    r[6] = (double)g_acc[3 * o + 1];
+    r[7] = (double)g_acc[3 * o + 2];
+    r[8] = g_pot ? (double)g_pot[o] : 0.0;
+}
+
+// FP64 sink-sink adjoint: one wave per sink target, lanes stride the sources.
+__global__ __launch_bounds__(64) void k_sink_sink_b(const double *__restrict__ rec,
+                                                    int64_t n_sink, double *__restrict__ ssb) {
     const int lane = threadIdx.x;
     for (int64_t k = blockIdx.x; k < n_sink; k += gridDim.x) {
-        const int64_t p = sink_pos[k];
-        const int64_t ok = order[p];
-        const double tx = xs[p], ty = ys[p], tz = zs[p], th = hs[p], mk = ms[p];
-        const double gkx = g_acc[3 * ok], gky = g_acc[3 * ok + 1], gkz = g_acc[3 * ok + 2];
-        const double gpk = g_pot ? (double)g_pot[ok] : 0.0;
+        const double *t = rec + kSinkRecB * k;
+        const double tx = t[0], ty = t[1], tz = t[2], mk = t[3], th = t[4];
+        const double gkx = t[5], gky = t[6], gkz = t[7], gpk = t[8];
         double v[5] = {0, 0, 0, 0, 0};
         for (int64_t j = lane; j < n_sink; j += 64) {
             if (j == k) continue;
-            const int64_t q = sink_pos[j];
-            const int64_t oq = order[q];
+            const double *q = rec + kSinkRecB * j;
             SrcRecB<double> r;
-            r.x = xs[q]; r.y = ys[q]; r.z = zs[q]; r.m = ms[q]; r.h = hs[q]; r.h2 = r.h * r.h;
-            r.gx = g_acc[3 * oq]; r.gy = g_acc[3 * oq + 1]; r.gz = g_acc[3 * oq + 2];
-            r.gp = g_pot ? (double)g_pot[oq] : 0.0;
-            r.idx = (int32_t)q;
+            r.x = q[0]; r.y = q[1]; r.z = q[2]; r.m = q[3]; r.h = q[4]; r.h2 = r.h * r.h;
+            r.gx = q[5]; r.gy = q[6]; r.gz = q[7]; r.gp = q[8];
+            r.idx = -1;
             adj_pair<double, true>(r.x - tx, r.y - ty, r.z - tz, r, mk, gkx, gky, gkz, gpk,
                                    th * th, th, false, v[0], v[1], v[2], v[3], v[4]);
         }
@@ -254,14 +268,17 @@ __global__ __launch_bounds__(64) void k_sink_sink_b(const int32_t *__restrict__ 
     }
 }
 
+// rec: scratch for kSinkRecB doubles per sink.
 template <typename T>
 static void sink_sink_backward(sf_grav_tree_s *t, const void *g_acc, const void *g_pot, double *ssb,
-                               hipStream_t st) {
+                               double *rec, hipStream_t st) {
+    const unsigned gb = (unsigned)((t->n_sink + 255) / 256);
+    hipLaunchKernelGGL(k_sink_gather_b<T>, dim3(gb), dim3(256), 0, st, t->sink_pos, t->n_sink,
+                       (const T *)t->xs, (const T *)t->ys, (const T *)t->zs, (const T *)t->ms,
+                       (const T *)t->hs, t->order, (const T *)g_acc, (const T *)g_pot, rec);
     const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
-    hipLaunchKernelGGL(k_sink_sink_b<T>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
-                       t->n_sink, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
-                       (const T *)t->ms, (const T *)t->hs, t->order, (const T *)g_acc,
-                       (const T *)g_pot, ssb);
+    hipLaunchKernelGGL(k_sink_sink_b, dim3(blocks), dim3(64), 0, st, (const double *)rec,
+                       t->n_sink, ssb);
 }
 
 template <typename T, int FORM>
@@ -286,8 +303,10 @@ static sf_status direct_backward_run(sf_grav_tree_s *t, const EvalOpts &o, const
                        (const T *)g_pot, t->tfirst, t->tcount, t->tbox, t->tcen, rec);
     double *ssb = nullptr;
     if (t->n_sink > 0) {
+        double *srec;
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
-        sink_sink_backward<T>(t, g_acc, g_pot, ssb, s);
+        SF_ALLOC_TMP(ar, srec, kSinkRecB * t->n_sink);
+        sink_sink_backward<T>(t, g_acc, g_pot, ssb, srec, s);
     }
     const unsigned blocks = (unsigned)((t->n_tiles + 3) / 4);
     hipLaunchKernelGGL((k_direct_b<T, FORM>), dim3(blocks), dim3(256), 0, s, n, ng, t->n_gas_tiles,
@@ -1112,13 +1131,15 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     uint32_t *sstack = nullptr;
     hipStream_t side = s;
     if (t->n_sink > 0) {
+        double *srec;
         SF_ALLOC_TMP(ar, ssb, 5 * t->n_sink);
+        SF_ALLOC_TMP(ar, srec, kSinkRecB * t->n_sink);
         SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
         if (hipStream_t sd = side_stream(t->device)) side = sd;
         sf_status st = side_fork(t, side);
         if (st != SF_OK) return st;
         phase_begin(t, 7, side);
-        sink_sink_backward<T>(t, g_acc, g_pot, ssb, side);
+        sink_sink_backward<T>(t, g_acc, g_pot, ssb, srec, side);
         phase_end(t, 7, side);
     }
 #define SF_WB(F, O)                                                                                \

@@ -76,8 +76,9 @@ sf_status direct_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_ac
                           DevArena &ar);
 
 // FP64 sink-sink direct sum into acc4 (4 doubles per sink: ax ay az phi),
-// launched on stream st.
-void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4, hipStream_t st);
+// launched on stream st; rec is scratch for kSinkRec doubles per sink.
+constexpr int kSinkRec = 6;
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *acc4, double *rec, hipStream_t st);
 
 // Second stream of the device for the sink work, which runs beside the group
 // walk: side_fork makes it wait for the work queued so far on t->stream,

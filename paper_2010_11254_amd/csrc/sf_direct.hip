@@ -208,10 +208,11 @@ static sf_status direct_run(sf_grav_tree_s *t, const EvalOpts &o, void *acc, voi
                        t->n_tiles, (const T *)t->xs, (const T *)t->ys, (const T *)t->zs,
                        (const T *)t->ms, (const T *)t->hs, t->tfirst, t->tcount, t->tbox, t->tcen,
                        rec);
-    double *ss = nullptr;
+    double *ss = nullptr, *srec = nullptr;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
-        sink_sink_accel(t, o.G, ss, t->stream);
+        SF_ALLOC_TMP(ar, srec, kSinkRec * t->n_sink);
+        sink_sink_accel(t, o.G, ss, srec, t->stream);
     }
     const unsigned blocks = (unsigned)((t->n_tiles + 3) / 4);
     hipLaunchKernelGGL((k_direct<T, FORM>), dim3(blocks), dim3(256), 0, s, n, ng, t->n_gas_tiles,

@@ -402,25 +402,41 @@ __global__ __launch_bounds__(64) void k_walk_sinks(WalkArgs<T> a) {
 
 // ---------------------------------------------------------------- sink-sink
 
+// Sink records gathered once into one contiguous FP64 array (x y z m h 1/h),
+// so the pair loop issues independent, coalesced loads.
+template <typename T>
+__global__ void k_sink_gather(const int32_t *__restrict__ sink_pos, int64_t n_sink,
+                              const T *__restrict__ xs, const T *__restrict__ ys,
+                              const T *__restrict__ zs, const T *__restrict__ ms,
+                              const T *__restrict__ hs, double *__restrict__ rec) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_sink) return;
+    const int64_t p = sink_pos[k];
+    const double h = (double)hs[p];
+    double *r = rec + kSinkRec * k;
+    r[0] = (double)xs[p];
+    r[1] = (double)ys[p];
+    r[2] = (double)zs[p];
+    r[3] = (double)ms[p];
+    r[4] = h;
+    r[5] = 1.0 / h;
+}
+
 // FP64 direct sum over sink pairs; one wave per sink target, lanes stride the
 // sources; results unscaled by G.
-template <typename T>
-__global__ __launch_bounds__(64) void k_sink_sink(const int32_t *__restrict__ sink_pos,
-                                                  int64_t n_sink, const T *__restrict__ xs,
-                                                  const T *__restrict__ ys, const T *__restrict__ zs,
-                                                  const T *__restrict__ ms, const T *__restrict__ hs,
+__global__ __launch_bounds__(64) void k_sink_sink(const double *__restrict__ rec, int64_t n_sink,
                                                   double *__restrict__ ss) {
     const int lane = threadIdx.x;
     for (int64_t k = blockIdx.x; k < n_sink; k += gridDim.x) {
-        const int64_t p = sink_pos[k];
-        const double tx = xs[p], ty = ys[p], tz = zs[p], th = hs[p];
+        const double *t = rec + kSinkRec * k;
+        const double tx = t[0], ty = t[1], tz = t[2], th = t[4], thi = t[5];
         double bx = 0, by = 0, bz = 0, bp = 0;
         for (int64_t j = lane; j < n_sink; j += 64) {
             if (j == k) continue;
-            const int64_t q = sink_pos[j];
-            const double h = (double)hs[q];
-            pair<double>((double)xs[q] - tx, (double)ys[q] - ty, (double)zs[q] - tz, (double)ms[q],
-                         h * h, h, 1.0 / h, th * th, th, 1.0 / th, false, bx, by, bz, bp);
+            const double *r = rec + kSinkRec * j;
+            const double h = r[4];
+            pair<double>(r[0] - tx, r[1] - ty, r[2] - tz, r[3], h * h, h, r[5], th * th, th, thi,
+                         false, bx, by, bz, bp);
         }
         bx = wave_sum_f64(bx);
         by = wave_sum_f64(by);
@@ -435,18 +451,22 @@ __global__ __launch_bounds__(64) void k_sink_sink(const int32_t *__restrict__ si
     }
 }
 
-void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss, hipStream_t st) {
+void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss, double *rec, hipStream_t st) {
     (void)G;
     if (t->n_sink <= 0) return;
-    const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
+    const unsigned gb = (unsigned)((t->n_sink + 255) / 256);
     if (t->dt == SF_F32)
-        hipLaunchKernelGGL(k_sink_sink<float>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
-                           t->n_sink, (const float *)t->xs, (const float *)t->ys,
-                           (const float *)t->zs, (const float *)t->ms, (const float *)t->hs, ss);
+        hipLaunchKernelGGL(k_sink_gather<float>, dim3(gb), dim3(256), 0, st, t->sink_pos, t->n_sink,
+                           (const float *)t->xs, (const float *)t->ys, (const float *)t->zs,
+                           (const float *)t->ms, (const float *)t->hs, rec);
     else
-        hipLaunchKernelGGL(k_sink_sink<double>, dim3(blocks), dim3(64), 0, st, t->sink_pos,
+        hipLaunchKernelGGL(k_sink_gather<double>, dim3(gb), dim3(256), 0, st, t->sink_pos,
                            t->n_sink, (const double *)t->xs, (const double *)t->ys,
-                           (const double *)t->zs, (const double *)t->ms, (const double *)t->hs, ss);
+                           (const double *)t->zs, (const double *)t->ms, (const double *)t->hs,
+                           rec);
+    const unsigned blocks = (unsigned)std::min<int64_t>(t->n_sink, 8192);
+    hipLaunchKernelGGL(k_sink_sink, dim3(blocks), dim3(64), 0, st, (const double *)rec, t->n_sink,
+                       ss);
 }
 
 // ---------------------------------------------------------------- launch
@@ -546,7 +566,7 @@ static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void
 
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
     int32_t *ctr = nullptr;
-    double *ss = nullptr;
+    double *ss = nullptr, *srec = nullptr;
     uint32_t *gstack = nullptr, *sstack = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
@@ -554,12 +574,13 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     hipStream_t side = t->stream;
     if (t->n_sink > 0) {
         SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
+        SF_ALLOC_TMP(ar, srec, kSinkRec * t->n_sink);
         SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
         if (hipStream_t sd = side_stream(t->device)) side = sd;
         sf_status st = side_fork(t, side);
         if (st != SF_OK) return st;
         phase_begin(t, 4, side);
-        sink_sink_accel(t, o.G, ss, side);
+        sink_sink_accel(t, o.G, ss, srec, side);
         phase_end(t, 4, side);
     }
     if (o.stats) {
