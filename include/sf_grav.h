@@ -25,8 +25,14 @@
  * Conventions shared by every entry point
  *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
  *     tensors).  `stream` is a hipStream_t passed as void* (NULL = the null
- *     stream); every kernel is enqueued on it, in order.  The caller keeps
- *     the buffers alive until the stream has finished the work.
+ *     stream); every kernel is enqueued on it, in order, except that a tree
+ *     evaluation with sinks runs its sink-sink sum and sink walk on a second
+ *     stream of the device (created by the library on first use, default
+ *     priority), forked from `stream` with an event after the work queued
+ *     before it and joined back into `stream` with an event before the call
+ *     returns; to the caller the call behaves as if all of it ran on
+ *     `stream`.  The caller keeps the buffers alive until the stream has
+ *     finished the work.
  *   - pos is row-major n x 3 (x0,y0,z0,x1,...), mass and soft have n entries.
  *     All caller arrays of one call share the dtype `dt` (SF_F32 or SF_F64).
  *     Particles [0, n_gas) are gas, [n_gas, n) are sinks.
@@ -200,6 +206,9 @@ sf_status sf_grav_tree_export(sf_grav_tree tree, int32_t what, void *host_dst,
  *   accel:    [4] sink-sink FP64  [5] group walk  [6] sink walk
  *   backward: [7] sink-sink FP64  [8] group walk  [9] sink walk
  *             [10] push-down and output
+ * Phases 4, 6, 7 and 9 run on the library's second stream beside the group
+ * walk; their times include waiting for execution slots that the group walk
+ * holds.
  * Errors: SF_E_INVALID (NULL, struct_size), SF_E_DEVICE. */
 typedef struct {
     uint32_t struct_size;   /* = sizeof(sf_grav_timings) */
