@@ -326,6 +326,33 @@ def main():
             log(f"adjoint {form}: accel {fwd:.2f} ms, backward {bwd:.2f} ms, ratio {bwd / fwd:.2f}")
         del ga, gp
 
+    # the same ratio on the differentiation workload (2^18 clustered gas,
+    # per-particle h, seed 7; cotangents N(0, 1)); the build is timed with
+    # events too, for the ratio that includes it
+    adj_diff = {}
+    if not args.no_backward:
+        from synth import differentiation_cloud
+        dcl = differentiation_cloud(1 << 18, seed=7)
+        dx, dm, dh = (torch.as_tensor(v).to(dev) for v in (dcl.x, dcl.m, dcl.h))
+        dga, dgp = cotangents(dcl.n, seed=7, dtype=np.float32)
+        dga, dgp = torch.as_tensor(dga).to(dev), torch.as_tensor(dgp).to(dev)
+        dacc = torch.empty((dcl.n, 3), dtype=torch.float32, device=dev)
+        dpot = torch.empty(dcl.n, dtype=torch.float32, device=dev)
+        for form in ("fp32c",) + (() if args.no_fp64 else ("fp64",)):
+            o = L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=args.leaf_cap,
+                            group_cap=args.group_cap, n_gas=dcl.n_gas)
+            bld = event_ms(lambda: L.sf_grav_tree_free(L.sf_grav_build_tree(dx, dm, dh, o)), 5)
+            t = L.sf_grav_build_tree(dx, dm, dh, o)
+            fwd = event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=dacc, pot=dpot), 10)
+            bwd = event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, dga, dgp), 5)
+            L.sf_grav_tree_free(t)
+            adj_diff[form] = {"build_ms": bld, "accel_ms": fwd, "backward_ms": bwd,
+                              "backward_over_accel": bwd / fwd,
+                              "with_build": (bwd + bld) / (fwd + bld)}
+            log(f"diff256k adjoint {form}: build {bld:.2f} ms, accel {fwd:.2f} ms, backward "
+                f"{bwd:.2f} ms, ratio {bwd / fwd:.2f} ({(bwd + bld) / (fwd + bld):.2f} with the build)")
+        del dx, dm, dh, dga, dgp, dacc, dpot
+
     # direct path: one evaluation per form over all pairs
     direct = {}
     if not args.no_direct:
@@ -418,6 +445,8 @@ def main():
         line["fp32c_over_fp64"] = res["fp64"]["ms_per_step"] / (wall32 * 1e3)
     if adj:
         line["adjoint"] = adj
+    if adj_diff:
+        line["adjoint_diff256k"] = adj_diff
     if direct:
         line["direct"] = direct
         if "fp64" in direct:
