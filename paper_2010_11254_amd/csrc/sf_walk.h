@@ -34,6 +34,7 @@ struct WalkLds {
     PPRing near;   // leaves that may hold softened pairs (incl. the task's own)
     PPRing far;    // leaves whose every pair with the task is Newtonian
     int32_t slot[128];
+    uint32_t mark[64];   // pop: 1 + lane of the entry whose nodes start at this slot, else 0
 };
 
 template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h, hinv; int32_t idx; };
@@ -200,6 +201,22 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_incl(v), 63);
 }
 
+// Inclusive prefix maximum over the wave, by the same DPP stages.
+__device__ __forceinline__ uint32_t wave_max_incl(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Value of v in lane src (0..63).
+__device__ __forceinline__ uint32_t lane_value(uint32_t src, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+
 // Gather `want` (<= 64) particle indices from the front of a range ring into
 // slot[], in one pass: lane l looks at ring entry head + l, an inclusive scan
 // of the entry sizes places every entry's particles, each lane writes its
@@ -266,6 +283,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
     uint32_t sp = 1;     // stack positions [0, sp)
     uint32_t base = 0;   // positions [base, sp) in LDS, [0, base) in gstack
     if (lane == 0) L.stack[0] = 1u;   // root (node 0), one node
+    L.mark[lane] = 0u;
     uint32_t pc_h = 0, pc_t = 0;
     uint32_t nh = 0, nt = 0, npend = 0;   // near ring
     uint32_t fh = 0, ft = 0, fpend = 0;   // far ring
@@ -296,11 +314,19 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         const bool take = ei >= 0 && incl <= 64u;
         const uint32_t ntake = (uint32_t)popc64(__ballot(take));
         const uint32_t nnodes = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)ntake - 1);
-        if (take)
-            for (uint32_t o = 0; o < cnt; ++o) L.slot[incl - cnt + o] = (int32_t)((ent >> 4) + o);
+        // slot l takes node (first of entry e) + (l - start of e) for the
+        // taken entry e whose slot range [incl - cnt, incl) holds l: each
+        // entry marks its first slot, a prefix maximum spreads the marks
+        if (take) L.mark[incl - cnt] = (uint32_t)lane + 1u;
         sp -= ntake;
         __syncthreads();
-        const int node = lane < (int)nnodes ? L.slot[lane] : -1;
+        const uint32_t mk = wave_max_incl(L.mark[lane]);
+        L.mark[lane] = 0u;   // read above by this lane only; clear for the next step
+        const uint32_t e = mk > 0u ? mk - 1u : 0u;
+        const uint32_t ent_e = lane_value(e, ent), incl_e = lane_value(e, incl);
+        const int node = lane < (int)nnodes
+                             ? (int)((ent_e >> 4) + ((uint32_t)lane - (incl_e - (ent_e & 15u))))
+                             : -1;
         NodeHit hit{0, 0, 0, 0, 0};
         if (node >= 0) hit = classify(nd, node, blo, bhi, hg, gf, gl);
         const int cls = hit.cls;
