@@ -219,13 +219,13 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t src, uint32_t v) {
 
 // Gather `want` (<= 64) particle indices from the front of a range ring into
 // slot[], in one pass: lane l looks at ring entry head + l, an inclusive scan
-// of the entry sizes places every entry's particles, each lane writes its
-// entry's share, entries used up are dropped and a partly used one is
-// shortened in place.  Every entry holds at least one particle, so 64
-// entries always cover `want`; returns false (and flags err) if the pending
-// entries hold fewer particles, which the pending counts rule out.
+// of the entry sizes places every entry's particles, entries used up are
+// dropped and a partly used one is shortened in place.  Every entry holds at
+// least one particle, so 64 entries always cover `want`; returns false (and
+// flags err) if the pending entries hold fewer particles, which the pending
+// counts rule out.
 __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, int32_t *slot,
-                                            uint32_t want, int32_t *err) {
+                                            uint32_t *mark, uint32_t want, int32_t *err) {
     const uint32_t lane = threadIdx.x;
     const bool have = h + lane < t;
     const uint32_t q = (h + lane) & 127;
@@ -238,14 +238,23 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
         if (lane == 0) atomicOr(err, 4);
         return false;
     }
-    if (excl < want) {
-        const uint32_t take = (incl < want ? incl : want) - excl;
-        for (uint32_t i = 0; i < take; ++i) slot[excl + i] = f + (int32_t)i;
+    // slot l takes particle f + (l - excl) of the entry whose range
+    // [excl, incl) holds l: each entry marks its first slot (mark[] is zero
+    // between calls), a prefix maximum spreads the marks
+    if (have && excl < want) {
+        mark[excl] = lane + 1u;
         if (incl > want) {   // the one entry that is used only in part
+            const uint32_t take = want - excl;
             R.f[q] = f + (int32_t)take;
             R.c[q] = (int32_t)(c - take);
         }
     }
+    __syncthreads();
+    const uint32_t mk = wave_max_incl(mark[lane]);
+    mark[lane] = 0u;   // read above by this lane only
+    const uint32_t e = mk > 0u ? mk - 1u : 0u;
+    const uint32_t f_e = lane_value(e, (uint32_t)f), excl_e = lane_value(e, excl);
+    if (lane < want) slot[lane] = (int32_t)(f_e + (lane - excl_e));
     // entries used up: those whose inclusive count is at most want
     h += (uint32_t)popc64(__ballot(have && incl <= want));
     __syncthreads();
@@ -254,10 +263,10 @@ __device__ __forceinline__ bool ring_gather(PPRing &R, uint32_t &h, uint32_t t, 
 
 // Gather up to 128 particle indices: ring_gather in passes of at most 64.
 __device__ __forceinline__ bool ring_gather_n(PPRing &R, uint32_t &h, uint32_t t, int32_t *slot,
-                                              uint32_t want, int32_t *err) {
-    if (want <= 64u) return ring_gather(R, h, t, slot, want, err);
-    if (!ring_gather(R, h, t, slot, 64u, err)) return false;
-    return ring_gather(R, h, t, slot + 64, want - 64u, err);
+                                              uint32_t *mark, uint32_t want, int32_t *err) {
+    if (want <= 64u) return ring_gather(R, h, t, slot, mark, want, err);
+    if (!ring_gather(R, h, t, slot, mark, 64u, err)) return false;
+    return ring_gather(R, h, t, slot + 64, mark, want - 64u, err);
 }
 
 // Walk one task.  Ev supplies pc_batch(L, head, nb) (nb <= 64) and
@@ -377,14 +386,14 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         }
         while (fpend >= ppb || ft - fh > 64u) {
             const uint32_t nb = fpend < ppb ? fpend : ppb;
-            if (!ring_gather_n(L.far, fh, ft, L.slot, nb, err)) { fpend = 0; break; }
+            if (!ring_gather_n(L.far, fh, ft, L.slot, L.mark, nb, err)) { fpend = 0; break; }
             ev.template pp_batch<false>(L, nb);
             fpend -= nb;
             n_pp += nb;
         }
         while (npend >= ppb || nt - nh > 64u) {
             const uint32_t nb = npend < ppb ? npend : ppb;
-            if (!ring_gather_n(L.near, nh, nt, L.slot, nb, err)) { npend = 0; break; }
+            if (!ring_gather_n(L.near, nh, nt, L.slot, L.mark, nb, err)) { npend = 0; break; }
             ev.template pp_batch<true>(L, nb);
             npend -= nb;
             n_pp += nb;
@@ -395,13 +404,13 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         n_pc += pc_t - pc_h;
     }
     if (fpend > 0) {
-        if (ring_gather_n(L.far, fh, ft, L.slot, fpend, err)) {
+        if (ring_gather_n(L.far, fh, ft, L.slot, L.mark, fpend, err)) {
             ev.template pp_batch<false>(L, fpend);
             n_pp += fpend;
         }
     }
     if (npend > 0) {
-        if (ring_gather_n(L.near, nh, nt, L.slot, npend, err)) {
+        if (ring_gather_n(L.near, nh, nt, L.slot, L.mark, npend, err)) {
             ev.template pp_batch<true>(L, npend);
             n_pp += npend;
         }
