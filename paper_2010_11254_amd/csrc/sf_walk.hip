@@ -3,10 +3,10 @@
 // node; Sec. 2.2.1: softened pairs r < max(h_i, h_j), Newtonian beyond).
 //
 // One wavefront per walk task.  A task is either a target group (up to 64
-// Morton-consecutive particles, one target per lane, node moments over all
-// particles) or one sink target (node moments over gas only, lanes spread
-// over the sources, sink sources skipped -- sinks see other sinks through the
-// FP64 sink-sink sum).
+// Morton-consecutive particles, floor(64 / group size) lanes per target, node
+// moments over all particles) or one sink target (node moments over gas only,
+// lanes spread over the sources, sink sources skipped -- sinks see other
+// sinks through the FP64 sink-sink sum).
 //
 // Walk: an LDS stack of child ranges (<= 8 nodes each).  Each step pops whole
 // entries from the top, up to 64 nodes, one node per lane, and tests each
@@ -20,7 +20,8 @@
 // from bottom to top of the stack; a new level-L entry is only pushed when a
 // level L-1 node is popped, which pops every level-L entry above it first,
 // so at most 64 entries per level are ever stored: 22 * 64 bounds the stack.
-// Interactions are evaluated in batches of 64 as the rings fill.
+// Interactions are evaluated in batches as the rings fill: 64 nodes, and up
+// to 128 particles in the FP32 forms of the group walk (64 otherwise).
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
