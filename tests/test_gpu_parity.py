@@ -268,3 +268,32 @@ def test_tree_lattice_softening_boundary(h_cells, jitter):
         ep = np.abs(p - pr) / np.sqrt(np.mean(pr * pr))
         assert np.max(e) < tol and np.max(ep) < tol, (form, np.max(e), np.max(ep))
 
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_tree_edge_sizes(form):
+    # tiny trees: a single leaf (n <= leaf capacity), one split, a few
+    # levels, the group and particle-batch boundaries; topology bit-exact
+    # and forces against the oracle tree (same lists)
+    L = _lib()
+    dt = np.float64 if form == "fp64" else np.float32
+    tol = 1e-10 if form == "fp64" else 2e-5
+    for n in (1, 2, 3, 16, 17, 33, 65, 129, 200):
+        _say("tree", form, "n =", n)
+        ps = uniform_sphere(n, seed=100 + n, dtype=dt, h=0.05)
+        a, p, t = gpu_tree(ps, form, leaf_cap=16, group_cap=32, stats=True, keep=True)
+        x64, m64, h64 = (v.astype(np.float64) for v in (ps.x, ps.m, ps.h))
+        ref = otree.build_tree(x64, 16)
+        for name, arr in [("node_level", ref.level), ("node_first", ref.first),
+                          ("node_count", ref.count), ("node_parent", ref.parent),
+                          ("node_child", ref.child_first), ("node_nchild", ref.n_child)]:
+            assert np.array_equal(L.sf_grav_tree_export(t, name).numpy(), arr), (n, name)
+        L.sf_grav_tree_free(t)
+        if n == 1:
+            assert np.all(a == 0.0)
+            continue
+        ar, pr, _ = otree.tree_forward(x64, m64, h64, ps.n_gas, theta=0.5, order=2, leaf_cap=16,
+                                       group_cap=32)
+        e = np.linalg.norm(a - ar, axis=1) / np.sqrt(np.mean(np.sum(ar * ar, axis=1)))
+        ep = np.abs(p - pr) / np.sqrt(np.mean(pr * pr))
+        assert np.max(e) < tol and np.max(ep) < tol, (n, np.max(e), np.max(ep))
+
