@@ -183,8 +183,8 @@ def main():
     ap.add_argument("--group-cap", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described but not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how the walk would shard over GPUs is a design, not code)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
