@@ -1136,8 +1136,7 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
         SF_ALLOC_TMP(ar, srec, kSinkRecB * t->n_sink);
         SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
         if (hipStream_t sd = side_stream(t->device)) side = sd;
-        sf_status st = side_fork(t, side);
-        if (st != SF_OK) return st;
+        if (side_fork(t, side) != SF_OK) side = t->stream;   // nothing queued there: run serially
         phase_begin(t, 7, side);
         sink_sink_backward<T>(t, g_acc, g_pot, ssb, srec, side);
         phase_end(t, 7, side);

@@ -203,7 +203,10 @@ static sf_status ensure_event(hipEvent_t *e) {
 
 sf_status side_fork(sf_grav_tree_s *t, hipStream_t side) {
     if (side == t->stream) return SF_OK;
+    // both events exist before anything is queued on the side stream, so the
+    // join cannot fail for want of an event
     sf_status st = ensure_event(&t->ev_fork);
+    if (st == SF_OK) st = ensure_event(&t->ev_join);
     if (st != SF_OK) return st;
     SF_HIP(hipEventRecord(t->ev_fork, t->stream));
     SF_HIP(hipStreamWaitEvent(side, t->ev_fork, 0));
@@ -212,10 +215,15 @@ sf_status side_fork(sf_grav_tree_s *t, hipStream_t side) {
 
 sf_status side_join(sf_grav_tree_s *t, hipStream_t side) {
     if (side == t->stream) return SF_OK;
-    sf_status st = ensure_event(&t->ev_join);
-    if (st != SF_OK) return st;
-    SF_HIP(hipEventRecord(t->ev_join, side));
-    SF_HIP(hipStreamWaitEvent(t->stream, t->ev_join, 0));
+    hipError_t e = hipEventRecord(t->ev_join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(t->stream, t->ev_join, 0);
+    if (e != hipSuccess) {
+        // the caller's stream cannot wait for the side work: finish it here,
+        // before the caller releases the scratch it uses
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(side);
+        return sf_fail(SF_E_DEVICE, "joining the side stream failed: %s", hipGetErrorString(e));
+    }
     return SF_OK;
 }
 

@@ -572,18 +572,6 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
-    hipStream_t side = t->stream;
-    if (t->n_sink > 0) {
-        SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
-        SF_ALLOC_TMP(ar, srec, kSinkRec * t->n_sink);
-        SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
-        if (hipStream_t sd = side_stream(t->device)) side = sd;
-        sf_status st = side_fork(t, side);
-        if (st != SF_OK) return st;
-        phase_begin(t, 4, side);
-        sink_sink_accel(t, o.G, ss, srec, side);
-        phase_end(t, 4, side);
-    }
     if (o.stats) {
         if (!t->gnpc) {
             DevArena keep(t->stream);
@@ -596,13 +584,26 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
         t->have_stats = true;
     }
+    // every allocation precedes the fork: no early return between the fork
+    // and the join
+    hipStream_t side = t->stream;
+    if (t->n_sink > 0) {
+        SF_ALLOC_TMP(ar, ss, 4 * t->n_sink);
+        SF_ALLOC_TMP(ar, srec, kSinkRec * t->n_sink);
+        SF_ALLOC_TMP(ar, sstack, std::min<int64_t>(t->n_sink, walk_grid()) * kStack);
+        if (hipStream_t sd = side_stream(t->device)) side = sd;
+        if (side_fork(t, side) != SF_OK) side = t->stream;   // nothing queued there: run serially
+        phase_begin(t, 4, side);
+        sink_sink_accel(t, o.G, ss, srec, side);
+        phase_end(t, 4, side);
+    }
     if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
     else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
-    SF_HIP(hipGetLastError());
-    if (t->n_sink > 0) {
+    if (t->n_sink > 0) {   // joined before any early return, so scratch outlives the side work
         sf_status st = side_join(t, side);
         if (st != SF_OK) return st;
     }
+    SF_HIP(hipGetLastError());
     int32_t herr = 0;
     SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, t->stream));
     SF_HIP(hipStreamSynchronize(t->stream));
