@@ -22,6 +22,8 @@
 // so at most 64 entries per level are ever stored: 22 * 64 bounds the stack.
 // Interactions are evaluated in batches as the rings fill: 64 nodes, and up
 // to 128 particles in the FP32 forms of the group walk (64 otherwise).
+#include <atomic>
+
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
@@ -476,15 +478,20 @@ void sink_sink_accel(sf_grav_tree_s *t, double G, double *ss, double *rec, hipSt
 // that run at once at their register use).
 int walk_grid() { return device_cu_count() * 16; }
 
+// CU count of the current device, queried once per device (MI355X: 256, also
+// the value taken if the query fails; it only sizes persistent grids).
 int device_cu_count() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (cus <= 0) cus = 256;
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c == 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0)
+            c = 256;
+        cus[dev].store(c, std::memory_order_relaxed);
     }
-    return cus;
+    return c;
 }
 
 template <typename T>
