@@ -627,8 +627,14 @@ struct GroupEvalB {
 #pragma unroll
             for (int v = 0; v < NV; ++v) stg[v][held] = acc[v];
             __syncthreads();
-            if (e < nb)
-                for (int d = 0; d < NV; ++d) atomic_add_f64(out_e + d * stride, (double)stg[d][slot]);
+            if (e < nb) {
+                // all values read before the first add, so the LDS reads overlap
+                R w[NV];
+#pragma unroll
+                for (int d = 0; d < NV; ++d) w[d] = stg[d][slot];
+#pragma unroll
+                for (int d = 0; d < NV; ++d) atomic_add_f64(out_e + d * stride, (double)w[d]);
+            }
         } else {
             if (e < nb)
                 for (int d = 0; d < NV; ++d) atomic_add_f64(out_e + d * stride, bacc[d][slot]);
