@@ -1120,20 +1120,22 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     const int64_t n = t->n, nn = t->n_nodes;
     int32_t *ctr;
     uint32_t *gstack;
-    double *tgt, *scat, *nadj0, *nadj1, *ssb = nullptr;
+    double *tgt, *scat, *nadj0, *nadj1 = nullptr, *ssb = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     SF_ALLOC_TMP(ar, tgt, 5 * n);
     SF_ALLOC_TMP(ar, scat, kXcd * 5 * n);
     SF_ALLOC_TMP(ar, nadj0, kXcd * 9 * nn);
-    SF_ALLOC_TMP(ar, nadj1, kXcd * 9 * nn);
+    if (t->n_sink > 0) SF_ALLOC_TMP(ar, nadj1, kXcd * 9 * nn);   // the sink walk's node adjoints
     double *poly;
     SF_ALLOC_TMP(ar, poly, 2 * kPoly * nn);
-    fill_u32((uint32_t *)ctr, kCtrWords, 0u, s);
-    fill_u32((uint32_t *)tgt, 10 * n, 0u, s);
-    fill_u32((uint32_t *)scat, kXcd * 10 * n, 0u, s);
-    fill_u32((uint32_t *)nadj0, kXcd * 18 * nn, 0u, s);
-    fill_u32((uint32_t *)nadj1, kXcd * 18 * nn, 0u, s);
+    FillRanges zero;   // one launch; set 1 node adjoints exist only with sinks
+    zero.add(ctr, kCtrWords);
+    zero.add(tgt, 10 * n);
+    zero.add(scat, kXcd * 10 * n);
+    zero.add(nadj0, kXcd * 18 * nn);
+    if (t->n_sink > 0) zero.add(nadj1, kXcd * 18 * nn);
+    fill_ranges_u32(zero, 0u, s);
     uint32_t *sstack = nullptr;
     hipStream_t side = s;
     if (t->n_sink > 0) {

@@ -6,6 +6,22 @@ namespace sf {
 
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
+// Up to kFillRanges ranges (p[k], n[k] words) set to one value in one launch.
+constexpr int kFillRanges = 6;
+struct FillRanges {
+    uint32_t *p[kFillRanges];
+    int64_t n[kFillRanges];
+    int count = 0;
+    void add(void *ptr, int64_t words) {
+        if (count < kFillRanges && words > 0) {
+            p[count] = (uint32_t *)ptr;
+            n[count] = words;
+            ++count;
+        }
+    }
+};
+void fill_ranges_u32(const FillRanges &r, uint32_t v, hipStream_t s);
+
 // Exclusive scan of n 32-bit values; *total (device) receives the sum.
 // scratch: scan_scratch_words(n) words.  Sums must stay below 2^30.
 int64_t scan_scratch_words(int64_t n);

@@ -21,6 +21,26 @@ void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
+// Several ranges in one launch: block b of the grid strides over every range.
+__global__ void k_fill_ranges_u32(FillRanges r, uint32_t v) {
+    for (int k = 0; k < r.count; ++k) {
+        uint32_t *p = r.p[k];
+        const int64_t n = r.n[k];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = v;
+    }
+}
+
+void fill_ranges_u32(const FillRanges &r, uint32_t v, hipStream_t s) {
+    int64_t most = 0;
+    for (int k = 0; k < r.count; ++k) most = r.n[k] > most ? r.n[k] : most;
+    if (most <= 0) return;
+    int64_t blocks = (most + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_ranges_u32, dim3((unsigned)blocks), dim3(256), 0, s, r, v);
+}
+
 // ---------------------------------------------------------------- scan
 
 constexpr int kScanThreads = 256;
