@@ -115,6 +115,18 @@ def test_tree_adjoint_fp32c_matches_oracle():
         _close(g, r, 2e-4, name)
 
 
+@pytest.mark.parametrize("form,rtol,dtype", [("fp64", 1e-8, np.float64), ("fp32c", 2e-4, np.float32)])
+def test_tree_adjoint_gas_only_matches_oracle(form, rtol, dtype):
+    # no sinks: the gas-only node adjoints are neither allocated nor walked
+    _say("tree adjoint gas only", form)
+    ps = differentiation_cloud(3000, seed=21, dtype=dtype)
+    ga, gp = cotangents(ps.n, seed=21)
+    got = gpu_backward(ps, ga, gp, form, "tree")
+    ref = oracle_tree_vjp(ps, ga, gp)
+    for g, r, name in zip(got, ref, ("x", "m", "h")):
+        _close(g, r, rtol, name)
+
+
 def test_tree_adjoint_theta_zero_is_direct_adjoint():
     _say("tree adjoint theta 0 == direct oracle")
     ps = clustered_cloud(3000, 10, seed=15, dtype=np.float64)
