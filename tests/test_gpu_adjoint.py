@@ -11,7 +11,7 @@ import torch
 
 from oracle import direct as odirect
 from oracle import tree as otree
-from synth import clustered_cloud, cotangents, differentiation_cloud
+from synth import clustered_cloud, cotangents, differentiation_cloud, uniform_sphere
 
 pytestmark = pytest.mark.gpu
 
@@ -125,6 +125,26 @@ def test_tree_adjoint_gas_only_matches_oracle(form, rtol, dtype):
     ref = oracle_tree_vjp(ps, ga, gp)
     for g, r, name in zip(got, ref, ("x", "m", "h")):
         _close(g, r, rtol, name)
+
+
+@pytest.mark.parametrize("form,rtol", [("fp64", 1e-8), ("fp32", 1e-3), ("fp32c", 2e-4)])
+def test_tree_adjoint_edge_sizes(form, rtol):
+    # tiny trees (one leaf, one split, group and batch boundaries) with mixed
+    # softening radii, against the oracle tree's adjoint on the same lists
+    dt = np.float64 if form == "fp64" else np.float32
+    for n in (1, 2, 3, 17, 33, 65, 200):
+        _say("tree adjoint", form, "n =", n)
+        ps = uniform_sphere(n, seed=300 + n, dtype=dt)   # about 32 neighbours within h
+        rng = np.random.default_rng(400 + n)
+        ps.h = (ps.h * (1.0 + 0.5 * rng.random(n))).astype(dt)
+        ga, gp = cotangents(ps.n, seed=300 + n)
+        got = gpu_backward(ps, ga, gp, form, "tree", leaf_cap=16, group_cap=32)
+        if n == 1:
+            assert all(np.all(g == 0.0) for g in got)
+            continue
+        ref = oracle_tree_vjp(ps, ga, gp, leaf_cap=16, group_cap=32)
+        for g, r, name in zip(got, ref, ("x", "m", "h")):
+            _close(g, r, rtol, (n, name))
 
 
 def test_tree_adjoint_theta_zero_is_direct_adjoint():
