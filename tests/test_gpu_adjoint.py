@@ -65,7 +65,7 @@ def oracle_tree_vjp(ps, ga, gp, theta=0.5, order=2, leaf_cap=16, group_cap=64):
 
 # ---------------------------------------------------------------- direct
 
-@pytest.mark.parametrize("form,rtol", [("fp64", 1e-9), ("fp32c", 2e-4)])
+@pytest.mark.parametrize("form,rtol", [("fp64", 1e-9), ("fp32", 1e-3), ("fp32c", 2e-4)])
 def test_direct_adjoint_matches_oracle(form, rtol):
     _say("direct adjoint", form)
     ps = clustered_cloud(6000, 20, seed=12, dtype=np.float64 if form == "fp64" else np.float32)
@@ -74,6 +74,28 @@ def test_direct_adjoint_matches_oracle(form, rtol):
     ref = odirect.direct_vjp(ps.x.astype(float), ps.m.astype(float), ps.h.astype(float), ga, gp)
     for g, r, name in zip(got, ref, ("x", "m", "h")):
         _close(g, r, rtol, name)
+
+
+@pytest.mark.parametrize("form,rtol", [("fp64", 1e-9), ("fp32c", 2e-4)])
+def test_direct_adjoint_edge_sizes(form, rtol):
+    # single particle, pairs, ragged 64-particle tiles, sinks at the end of
+    # the order (gas-sink and sink-sink pairs)
+    dt = np.float64 if form == "fp64" else np.float32
+    for n, n_sink in ((1, 0), (2, 1), (3, 0), (63, 2), (64, 0), (65, 3), (130, 5)):
+        _say("direct adjoint", form, "n =", n, "sinks", n_sink)
+        ps = uniform_sphere(n, seed=500 + n, dtype=dt)
+        rng = np.random.default_rng(600 + n)
+        ps.h = (ps.h * (1.0 + 0.5 * rng.random(n))).astype(dt)
+        ps.n_gas = n - n_sink
+        ga, gp = cotangents(ps.n, seed=500 + n)
+        got = gpu_backward(ps, ga, gp, form, "direct")
+        if n == 1:
+            assert all(np.all(g == 0.0) for g in got)
+            continue
+        ref = odirect.direct_vjp(ps.x.astype(float), ps.m.astype(float), ps.h.astype(float), ga,
+                                 gp)
+        for g, r, name in zip(got, ref, ("x", "m", "h")):
+            _close(g, r, rtol, (n, name))
 
 
 def test_direct_adjoint_dense_torch_reference_2048():
