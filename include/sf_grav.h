@@ -121,6 +121,9 @@ sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft
  *   handle's (else SF_E_STATE); pos/mass/soft may be NULL (ignored).
  *   theta, order, form, G come from *o; leaf_cap/group_cap from the build.
  * tree == NULL: direct path over pos/mass/soft (all pairs, no tree kept).
+ * The tree path reads back the walk's capacity-guard flag at the end of the
+ * call, and the direct path with validate = 1 reads back the validation
+ * flag: each synchronises `stream` once.
  * Errors: SF_E_INVALID, SF_E_STATE, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */
 sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass,
                         const void *soft, int64_t n, sf_dtype dt,
@@ -133,7 +136,7 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass,
  * (the interaction lists are recomputed, not stored); it flows through node
  * mass, centre of mass and quadrupole.  A pair's softening derivative goes to
  * the particle with the larger radius (half to each on a tie).
- * Same path selection and errors as sf_grav_accel. */
+ * Same path selection, errors and synchronisation as sf_grav_accel. */
 sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  const void *mass, const void *soft, int64_t n,
                                  sf_dtype dt, const sf_grav_opts *o,

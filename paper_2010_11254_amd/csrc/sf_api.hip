@@ -396,6 +396,17 @@ static sf_status eval_opts(const sf_grav_opts *o, sf::EvalOpts &e) {
     return SF_OK;
 }
 
+// Direct paths with validate = 1: read the flag the input pass raised
+// (synchronises the stream once).
+static sf_status validation_result(const sf_grav_tree_s &t) {
+    sf::Frame hf;
+    hipError_t he = hipMemcpyAsync(&hf, t.frame, sizeof(hf), hipMemcpyDeviceToHost, t.stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(t.stream);
+    if (he != hipSuccess) return sf_fail(SF_E_DEVICE, "%s", hipGetErrorString(he));
+    if (hf.bad) return sf_fail(SF_E_INVALID, "inputs contain non-finite values, h <= 0 or m < 0");
+    return SF_OK;
+}
+
 sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, const void *soft,
                         int64_t n, sf_dtype dt, const sf_grav_opts *o, void *acc, void *pot,
                         void *stream) {
@@ -434,13 +445,7 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, co
         DevArena ar(t.stream);
         const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
         st = sf::build_sorted(pos, mass, soft, n, ng, dt, true, o->validate != 0, &t, ar);
-        if (st == SF_OK && o->validate) {
-            sf::Frame hf;
-            hipError_t he = hipMemcpyAsync(&hf, t.frame, sizeof(hf), hipMemcpyDeviceToHost, t.stream);
-            if (he == hipSuccess) he = hipStreamSynchronize(t.stream);
-            if (he != hipSuccess) st = sf_fail(SF_E_DEVICE, "%s", hipGetErrorString(he));
-            else if (hf.bad) st = sf_fail(SF_E_INVALID, "inputs contain non-finite values, h <= 0 or m < 0");
-        }
+        if (st == SF_OK && o->validate) st = validation_result(t);
         if (st == SF_OK) st = sf::direct_accel(&t, e, acc, pot, ar);
         // the handle's own arrays are released once the stream reaches here
         ar.free_keep();
@@ -479,7 +484,8 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void 
     {
         DevArena ar(t.stream);
         const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
-        st = sf::build_sorted(pos, mass, soft, n, ng, dt, true, false, &t, ar);
+        st = sf::build_sorted(pos, mass, soft, n, ng, dt, true, o->validate != 0, &t, ar);
+        if (st == SF_OK && o->validate) st = validation_result(t);
         if (st == SF_OK) st = sf::direct_backward(&t, e, g_acc, g_pot, g_pos, g_mass, g_soft, ar);
         ar.free_keep();
     }

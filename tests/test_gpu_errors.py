@@ -53,6 +53,8 @@ def test_validate_rejects_bad_inputs(what):
     o = L.make_opts(form="fp32c", n_gas=ps.n_gas, validate=True)
     assert _status(lambda: L.sf_grav_build_tree(x, m, h, o)) == SF_E_INVALID
     assert _status(lambda: L.sf_grav_accel(None, x, m, h, o)) == SF_E_INVALID
+    ga = torch.ones((ps.n, 3), dtype=torch.float32, device="cuda")
+    assert _status(lambda: L.sf_grav_accel_backward(None, x, m, h, o, ga)) == SF_E_INVALID
     torch.cuda.synchronize()
 
 
