@@ -464,6 +464,7 @@ struct WalkArgsB {
     double *scat;               // 5 per sorted particle: source side (x y z m h)
     double *nadj;               // 9 per node: M, c(3), dQ(5)
     int64_t scat_stride, nadj_stride;   // elements between copies
+    const uint32_t *gperm;      // task -> group (costly groups first), or null: Morton order
     int32_t *task_ctr, *err;
     uint32_t *gstack;           // kStack entries per block: stack overflow area
 };
@@ -726,7 +727,9 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
     const int xcd = xcd_id();
     ev.scat = a.scat + xcd * a.scat_stride;
     ev.nadj = a.nadj + xcd * a.nadj_stride;
-    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+    for (int tk = next_task(a.task_ctr); tk < ng; tk = next_task(a.task_ctr)) {
+        const int g = a.gperm ? __builtin_amdgcn_readfirstlane((int)a.gperm[tk]) : tk;
+        if (g < 0 || g >= ng) continue;   // a cost order is a permutation of the groups
         const int64_t gf = a.gfirst[g], gc = a.gcount[g];
         double blo[3], bhi[3];
         for (int d = 0; d < 3; ++d) {
@@ -915,6 +918,20 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
     }
 }
 
+// Groups the adjoint walk may take in cost order: at most this many per
+// resident wave (with more, the tail is short and Morton order keeps
+// neighbouring groups, which share nodes, close in time).
+constexpr int64_t kCostOrderGroups = 32;
+
+// Sort keys for the cost order (largest cost first) and group indices.
+__global__ void k_cost_keys(const uint32_t *__restrict__ cost, int64_t n,
+                            uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = 0xffffffffull - cost[i];
+    vals[i] = (uint32_t)i;
+}
+
 // Fold the kXcd per-XCD copies of an atomic array into copy 0.
 __global__ void k_sum_copies(double *__restrict__ base, int64_t len) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
@@ -1094,7 +1111,7 @@ template <typename T, int FORM, int ORDER>
 static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
                            const void *g_pot, double *tgt, double *scat, double *nadj0,
                            double *nadj1, int32_t *ctr, uint32_t *gstack, uint32_t *sstack,
-                           hipStream_t side) {
+                           const uint32_t *gperm, hipStream_t side) {
     const unsigned grid = (unsigned)walk_grid();
     if (t->n_sink > 0) {
         WalkArgsB<T> as = make_args_b<T>(t, o, 1, g_acc, g_pot, tgt, scat, nadj1, ctr + kCtrSinks);
@@ -1107,6 +1124,7 @@ static void launch_walks_b(sf_grav_tree_s *t, const EvalOpts &o, const void *g_a
     }
     WalkArgsB<T> ag = make_args_b<T>(t, o, 0, g_acc, g_pot, tgt, scat, nadj0, ctr);
     ag.gstack = gstack;
+    ag.gperm = gperm;
     phase_begin(t, 8);
     hipLaunchKernelGGL((k_walk_groups_b<T, FORM, ORDER>), dim3(grid), dim3(64), 0, t->stream, ag);
     phase_end(t, 8);
@@ -1136,6 +1154,24 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     zero.add(nadj0, kXcd * 18 * nn);
     if (t->n_sink > 0) zero.add(nadj1, kXcd * 18 * nn);
     fill_ranges_u32(zero, 0u, s);
+    // With few groups per resident wave the last groups to start set the
+    // end of the walk; if a forward walk on this handle recorded each
+    // group's cost, take the groups in order of decreasing cost.
+    const uint32_t *gperm = nullptr;
+    const int64_t gcap = t->groups_cap;
+    if (t->have_cost && t->gcost && gcap >= 2 && gcap <= kCostOrderGroups * walk_grid()) {
+        uint64_t *ckeys, *ctmp;
+        uint32_t *cvals, *cvtmp, *cscr;
+        SF_ALLOC_TMP(ar, ckeys, gcap);
+        SF_ALLOC_TMP(ar, ctmp, gcap);
+        SF_ALLOC_TMP(ar, cvals, gcap);
+        SF_ALLOC_TMP(ar, cvtmp, gcap);
+        SF_ALLOC_TMP(ar, cscr, radix_scratch_words(gcap, 4));
+        hipLaunchKernelGGL(k_cost_keys, dim3((unsigned)((gcap + 255) / 256)), dim3(256), 0, s,
+                           (const uint32_t *)t->gcost, gcap, ckeys, cvals);
+        radix_sort_u64(ckeys, cvals, ctmp, cvtmp, gcap, 4, cscr, s);   // stable: ties by index
+        gperm = cvals;
+    }
     uint32_t *sstack = nullptr;
     hipStream_t side = s;
     if (t->n_sink > 0) {
@@ -1150,7 +1186,8 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
         phase_end(t, 7, side);
     }
 #define SF_WB(F, O)                                                                                \
-    launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr, gstack, sstack, side)
+    launch_walks_b<T, F, O>(t, o, g_acc, g_pot, tgt, scat, nadj0, nadj1, ctr, gstack, sstack, \
+                            gperm, side)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_WB(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_WB(SF_FP32, 0);

@@ -167,6 +167,10 @@ struct sf_grav_tree_s {
     double *gcen = nullptr;                           // 3 per group
     int32_t *gnpc = nullptr, *gnpp = nullptr;         // stats
     bool have_stats = false;
+    // per group, written by every forward walk: (3 nodes + particles) x the
+    // adjoint's lanes per target, so the adjoint can start costly groups first
+    uint32_t *gcost = nullptr;
+    bool have_cost = false;
 
     int64_t groups_cap = 0;
     uint32_t *info_dev = nullptr;                     // [0] max level, [1] leaves

@@ -50,6 +50,7 @@ struct WalkArgs {
     int32_t *err;
     uint32_t *gstack;          // kStack entries per block: stack overflow area
     int32_t *gnpc, *gnpp;      // stats (group mode), may be null
+    uint32_t *gcost;           // per-group cost for the adjoint's task order, may be null
     T *acc, *pot;
     double G;
 };
@@ -286,6 +287,12 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
         if (STATS && lane == 0) {
             a.gnpc[g] = (int32_t)npc;
             a.gnpp[g] = (int32_t)npp;
+        }
+        if (lane == 0 && a.gcost) {
+            uint32_t w = 1;   // the adjoint's lanes per target: gc rounded up to a power of two
+            while (w < gcu) w <<= 1;
+            const uint64_t c = ((uint64_t)3 * npc + npp) * w;
+            a.gcost[g] = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
         }
     }
 }
@@ -525,6 +532,7 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     a.gstack = gstack;
     a.gnpc = t->gnpc;
     a.gnpp = t->gnpp;
+    a.gcost = set == 0 ? t->gcost : nullptr;
     a.acc = (T *)acc;
     a.pot = (T *)pot;
     a.G = o.G;
@@ -591,6 +599,14 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
         t->have_stats = true;
     }
+    if (!t->gcost) {   // zero beyond the groups, so a cost order is a permutation of them
+        DevArena keep(t->stream);
+        SF_ALLOC(keep, t->gcost, t->groups_cap);
+        for (void *p : keep.keep) t->allocs.push_back(p);
+        keep.keep.clear();
+        fill_u32(t->gcost, t->groups_cap, 0u, t->stream);
+    }
+    t->have_cost = false;
     // every allocation precedes the fork: no early return between the fork
     // and the join
     hipStream_t side = t->stream;
@@ -616,6 +632,7 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     SF_HIP(hipStreamSynchronize(t->stream));
     if (herr)
         return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);
+    t->have_cost = true;
     return SF_OK;
 }
 
