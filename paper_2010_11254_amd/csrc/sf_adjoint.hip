@@ -918,17 +918,25 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
     }
 }
 
-// Groups the adjoint walk may take in cost order: at most this many per
-// resident wave (with more, the tail is short and Morton order keeps
-// neighbouring groups, which share nodes, close in time).
-constexpr int64_t kCostOrderGroups = 32;
-
-// Sort keys for the cost order (largest cost first) and group indices.
-__global__ void k_cost_keys(const uint32_t *__restrict__ cost, int64_t n,
+// Sort keys for the adjoint's task order.  With at most kFineOrderGroups
+// groups per resident wave (a few tasks per wave, so the last costly group
+// to start sets the end): decreasing cost (a stable sort keeps Morton order
+// among equal costs; 4 passes).  With more: cost classes (powers of two)
+// from the most costly down and Morton order within a class, so that
+// neighbouring groups, which read the same nodes, stay close in time (key
+// bits 0..39: index below 2^32, class below 32; 5 passes).
+constexpr int64_t kFineOrderGroups = 32;
+__global__ void k_cost_keys(const uint32_t *__restrict__ cost, int64_t n, int fine,
                             uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keys[i] = 0xffffffffull - cost[i];
+    const uint32_t c = cost[i];
+    if (fine) {
+        keys[i] = 0xffffffffull - c;
+    } else {
+        const uint32_t lg = c ? 31u - (uint32_t)__clz(c) : 0u;   // floor(log2 c)
+        keys[i] = ((uint64_t)(31u - lg) << 32) | (uint64_t)i;
+    }
     vals[i] = (uint32_t)i;
 }
 
@@ -1154,22 +1162,24 @@ static sf_status tree_backward_t(sf_grav_tree_s *t, const EvalOpts &o, const voi
     zero.add(nadj0, kXcd * 18 * nn);
     if (t->n_sink > 0) zero.add(nadj1, kXcd * 18 * nn);
     fill_ranges_u32(zero, 0u, s);
-    // With few groups per resident wave the last groups to start set the
-    // end of the walk; if a forward walk on this handle recorded each
-    // group's cost, take the groups in order of decreasing cost.
+    // If a forward walk on this handle recorded each group's cost, start the
+    // costly groups first: with few groups per resident wave the last costly
+    // group to start sets the end of the walk.
     const uint32_t *gperm = nullptr;
     const int64_t gcap = t->groups_cap;
-    if (t->have_cost && t->gcost && gcap >= 2 && gcap <= kCostOrderGroups * walk_grid()) {
+    if (t->have_cost && t->gcost && gcap >= 2 && gcap <= 0xffffffffll) {
         uint64_t *ckeys, *ctmp;
         uint32_t *cvals, *cvtmp, *cscr;
         SF_ALLOC_TMP(ar, ckeys, gcap);
         SF_ALLOC_TMP(ar, ctmp, gcap);
         SF_ALLOC_TMP(ar, cvals, gcap);
         SF_ALLOC_TMP(ar, cvtmp, gcap);
-        SF_ALLOC_TMP(ar, cscr, radix_scratch_words(gcap, 4));
+        const bool fine = gcap <= kFineOrderGroups * walk_grid();
+        const int passes = fine ? 4 : 5;
+        SF_ALLOC_TMP(ar, cscr, radix_scratch_words(gcap, passes));
         hipLaunchKernelGGL(k_cost_keys, dim3((unsigned)((gcap + 255) / 256)), dim3(256), 0, s,
-                           (const uint32_t *)t->gcost, gcap, ckeys, cvals);
-        radix_sort_u64(ckeys, cvals, ctmp, cvtmp, gcap, 4, cscr, s);   // stable: ties by index
+                           (const uint32_t *)t->gcost, gcap, fine ? 1 : 0, ckeys, cvals);
+        radix_sort_u64(ckeys, cvals, ctmp, cvtmp, gcap, passes, cscr, s);   // stable
         gperm = cvals;
     }
     uint32_t *sstack = nullptr;
