@@ -203,6 +203,29 @@ def test_autograd_function_tree_backward():
         _close(g.cpu().numpy(), r, 1e-8, name)
 
 
+@pytest.mark.parametrize("n_gas,form", [(20000, "fp32c"), (1 << 20, "fp32c"), (1 << 20, "fp64")])
+def test_tree_adjoint_independent_of_task_order(n_gas, form):
+    # before any forward on the handle the adjoint takes its groups in Morton
+    # order; after one, in the cost order the forward recorded (exact at
+    # 20000 particles, cost classes at 2^20): the same gradients up to the
+    # summation order of its FP64 accumulations
+    L = _lib()
+    _say("tree adjoint task order", form, "n_gas", n_gas)
+    ps = clustered_cloud(n_gas, 64, seed=51)
+    ga, gp = cotangents(ps.n, seed=51, dtype=np.float32)
+    x, m, h, g_a, g_p = _dev(ps.x, ps.m, ps.h, ga, gp)
+    o = L.make_opts(form=form, n_gas=ps.n_gas)
+    t = L.sf_grav_build_tree(x, m, h, o)
+    first = L.sf_grav_accel_backward(t, None, None, None, o, g_a, g_p)
+    L.sf_grav_accel(t, None, None, None, o)
+    second = L.sf_grav_accel_backward(t, None, None, None, o, g_a, g_p)
+    torch.cuda.synchronize()
+    L.sf_grav_tree_free(t)
+    for a, b, name in zip(first, second, ("x", "m", "h")):
+        scale = b.abs().max().item()
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * scale), name
+
+
 def test_tree_adjoint_theta_zero_deep_stack():
     _say("tree adjoint theta 0, leaf 1, uniform 20000: deep stack")
     from synth import uniform_sphere
