@@ -136,11 +136,12 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass,
  * (the interaction lists are recomputed, not stored); it flows through node
  * mass, centre of mass and quadrupole.  A pair's softening derivative goes to
  * the particle with the larger radius (half to each on a tie).
- * Each forward tree walk records every group's cost in the handle; the tree
- * adjoint of a small tree (at most 32 groups per resident wavefront) walks
- * the groups in decreasing recorded cost when a forward walk has run on the
- * handle, else in Morton order (the order changes only the summation order
- * of its FP64 accumulations).
+ * Each forward tree walk records every group's cost in the handle; once one
+ * has run, the tree adjoint walks the groups from the most costly down (by
+ * exact cost for trees of at most 32 groups per resident wavefront, else by
+ * power-of-two cost class with Morton order inside a class), before that in
+ * Morton order.  The order changes only the summation order of its FP64
+ * accumulations.
  * Same path selection, errors and synchronisation as sf_grav_accel. */
 sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  const void *mass, const void *soft, int64_t n,
