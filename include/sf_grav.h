@@ -3,8 +3,9 @@
  * adjoint) for gas cells with adaptive softening plus sink particles, on one
  * AMD Instinct MI355X (gfx950).  C ABI of libsfgrav.so.
  *
- * The operation (arXiv 2010.11254, Sec. 2.2 "Gravity"): the field g = -grad Phi
- * and the potential Phi at the location of every gas cell and sink particle,
+ * The operation (arXiv 2010.11254, Sec. 2.2 "Gravity"): for each particle i,
+ * gas or sink, the gravitational acceleration g = -grad Phi and the
+ * potential Phi it feels from all other particles,
  *     a_i   =  G sum_{j != i} m_j F(r_ij, h_ij) (x_j - x_i)
  *     phi_i = -G sum_{j != i} m_j P(r_ij, h_ij)
  * with the softened law of Sec. 2.2.1: pairs closer than h_ij = max(h_i, h_j)
@@ -17,7 +18,10 @@
  * Two evaluation paths:
  *   - tree   : Barnes-Hut octree (Sec. 2.2) over Morton-sorted particles,
  *              monopole or quadrupole nodes, opening angle theta = L/r
- *              (fiducial 0.5), walked by groups of up to 64 targets;
+ *              (fiducial 0.5) combined, when opts.alpha >= 0, with the
+ *              paper's acceleration-based criterion (a node is opened when
+ *              G M L^2 / r^4 exceeds alpha times the target's previous
+ *              |g|), walked by groups of up to 64 targets;
  *   - direct : all pairs (the theta -> 0 limit of the tree).
  * Sink targets always receive the sink-sink part of their field as an exact
  * FP64 direct sum; their gas part comes from the same path as gas targets.
@@ -46,8 +50,12 @@
  *     leaked).  sf_grav_last_error() gives a message for the calling thread.
  *   - The library allocates its device scratch with stream-ordered
  *     allocation on `stream` and keeps freed blocks in a per-stream cache
- *     (at most 64 GiB) for later calls on the same stream; the cache is
- *     returned to HIP only when the process ends.
+ *     (at most 64 GiB) for later calls on the same stream;
+ *     sf_grav_release_cache() returns the cache to HIP.
+ *   - Test hook: with SF_GRAV_FAIL_ALLOC=k in the environment, the k-th
+ *     device allocation of every entry-point call fails (SF_E_NOMEM; the
+ *     call releases what it had allocated, and a handle passed to it keeps
+ *     its previous state).
  */
 #ifndef SF_GRAV_H
 #define SF_GRAV_H
@@ -93,8 +101,16 @@ typedef struct {
     int32_t group_cap;    /* max targets per walk group, 1..64, default 32  */
     int32_t validate;     /* 1: check finite inputs, h > 0, m >= 0 (one pass) */
     int64_t n_gas;        /* particles [0,n_gas) are gas; default -1 = all   */
-    int32_t collect_stats;/* 1: record per-group interaction counts          */
+    int32_t collect_stats;/* 1: record per-group interaction counts and list
+                             checksums (sf_grav_get_stats)                  */
     int32_t timing;       /* 1: record hipEvents around each phase (tree)    */
+    double alpha;         /* relative (acceleration-based) opening criterion,
+                             Sec. 2.2: with alpha >= 0 a node is also opened
+                             when G M L^2 > alpha |g|min r^4, |g|min the
+                             smallest |g| of the task's targets in the field
+                             given to sf_grav_tree_set_field and r as for
+                             theta; < 0 (default -1) switches it off;
+                             alpha = 0 opens every node (direct sum)         */
 } sf_grav_opts;
 
 /* Fill *o with the defaults above (struct_size set).  Never fails. */
@@ -110,8 +126,8 @@ void sf_grav_opts_default(sf_grav_opts *o);
  * and group counts synchronises `stream` once.
  * The handle keeps its own sorted copy of pos/mass/soft: later calls on the
  * handle use the values captured here.  Release with sf_grav_tree_free.
- * Errors: SF_E_INVALID (NULL pointers, n < 1, n > 2^30, bad options),
- * SF_E_NOMEM, SF_E_DEVICE. */
+ * Errors: SF_E_INVALID (NULL pointers, n < 1, bad options), SF_E_UNSUPPORTED
+ * (n > 2^25, or more than 2^27 nodes), SF_E_NOMEM, SF_E_DEVICE. */
 sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft,
                              int64_t n, sf_dtype dt, const sf_grav_opts *o,
                              void *stream, sf_grav_tree *out);
@@ -120,7 +136,10 @@ sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft
  * tree != NULL: tree path on the handle's particles; n and dt must equal the
  *   handle's (else SF_E_STATE); pos/mass/soft may be NULL (ignored).
  *   theta, order, form, G come from *o; leaf_cap/group_cap from the build.
- * tree == NULL: direct path over pos/mass/soft (all pairs, no tree kept).
+ * tree == NULL: direct path over pos/mass/soft (all pairs, no tree kept;
+ *   n > 2^25 gives SF_E_UNSUPPORTED).
+ * With opts.alpha >= 0 the tree path needs a field set on the handle by
+ * sf_grav_tree_set_field (else SF_E_STATE).
  * The tree path reads back the walk's capacity-guard flag at the end of the
  * call, and the direct path with validate = 1 reads back the validation
  * flag: each synchronises `stream` once.
@@ -150,8 +169,68 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  void *g_pos, void *g_mass, void *g_soft,
                                  void *stream);
 
-/* Free a handle (synchronises the stream it was built on).  NULL is a no-op. */
+/* Free a handle: synchronises the stream of the last call made on it, then
+ * returns its memory to the library's cache.  NULL is a no-op. */
 sf_status sf_grav_tree_free(sf_grav_tree tree);
+
+/* Previous field for the relative opening criterion (Sec. 2.2: the error
+ * estimate of a node is compared with the target's total field, which a
+ * simulation knows from its previous step).  acc_prev: n x 3, caller order,
+ * the handle's dtype (device pointer, read before the call's work ends).
+ * The handle keeps |g| of every particle (FP64, correctly rounded
+ * sqrt((gx^2 + gy^2) + gz^2)) and the smallest |g| of each target group;
+ * later tree calls with opts.alpha >= 0 use them, until the next call of this
+ * function.  Enqueued on `stream`, no synchronisation.
+ * Errors: SF_E_INVALID (NULL), SF_E_STATE (no tree), SF_E_NOMEM, SF_E_DEVICE. */
+sf_status sf_grav_tree_set_field(sf_grav_tree tree, const void *acc_prev, void *stream);
+
+/* Refit: new positions, masses and softening radii (caller order, the
+ * handle's n and dtype) on a frozen tree.  Keys, order, topology, node cubes
+ * and group ranges stay as built; the handle's sorted copy of the particles,
+ * the node moments and the group boxes are recomputed.  Meant for small
+ * displacements (finite differences of the tree approximation with fixed
+ * topology): the safety tests of the walk use the frozen cubes, so a particle
+ * moved out of its cell may have a softened pair treated as Newtonian.  The
+ * list checksums of sf_grav_get_stats show whether the walk's decisions
+ * changed.  Enqueued on `stream`, no synchronisation.
+ * Errors: SF_E_INVALID (NULL), SF_E_STATE (no tree), SF_E_NOMEM, SF_E_DEVICE. */
+sf_status sf_grav_tree_refit(sf_grav_tree tree, const void *pos, const void *mass,
+                             const void *soft, void *stream);
+
+/* Statistics of the last tree accel on the handle made with
+ * opts.collect_stats = 1 (synchronises the handle's stream).
+ *   n_pc, n_pp: accepted-node and particle-pair interactions summed over the
+ *               gas targets (each group's list times its gas targets);
+ *   hist[b]:    groups whose list holds L = nodes + particles entries with
+ *               2^b <= L < 2^(b+1) (bin 0 also counts L = 0; bin 31 all
+ *               longer lists);
+ *   checksum:   order-independent hash of every group's decisions (which
+ *               nodes were accepted, which leaves opened); equal checksums
+ *               mean, up to hash collisions, identical interaction lists.
+ *               Per-group values: sf_grav_tree_export(SF_EXPORT_GROUP_CKS).
+ *               Sink targets' lists are not included.
+ * Errors: SF_E_INVALID (NULL, struct_size), SF_E_STATE (no tree or no
+ * statistics), SF_E_NOMEM, SF_E_DEVICE. */
+typedef struct {
+    uint32_t struct_size;  /* = sizeof(sf_grav_stats) */
+    int32_t max_level;
+    int64_t n_nodes;
+    int64_t n_leaves;
+    int64_t n_groups;
+    int64_t n_pc;
+    int64_t n_pp;
+    int64_t hist[32];
+    uint64_t checksum;
+} sf_grav_stats;
+
+sf_status sf_grav_get_stats(sf_grav_tree tree, sf_grav_stats *out);
+
+/* Return every device block the library keeps cached for reuse to HIP
+ * (synchronises each device that owns cached blocks, then trims its default
+ * memory pool).  *live_bytes (may be NULL) receives the bytes still handed
+ * out: held by live handles or by calls in progress on other threads.
+ * Errors: SF_E_DEVICE. */
+sf_status sf_grav_release_cache(size_t *live_bytes);
 
 /* Sizes of a built tree. */
 typedef struct {
@@ -184,6 +263,8 @@ sf_status sf_grav_get_tree_info(sf_grav_tree tree, sf_grav_tree_info *info);
  *   SF_EXPORT_GROUP_NPC   int32  [n_groups] accepted nodes of the last
  *   SF_EXPORT_GROUP_NPP   int32  [n_groups]   accel with collect_stats=1, and
  *                                             opened-leaf particles
+ *   SF_EXPORT_GROUP_CKS   uint64 [n_groups] list checksum of each group (same
+ *                                             accel)
  * Errors: SF_E_INVALID (unknown id, NULL, wrong size), SF_E_STATE (stats not
  * collected), SF_E_DEVICE. */
 typedef enum {
@@ -201,7 +282,8 @@ typedef enum {
     SF_EXPORT_NODE_COM = 11,
     SF_EXPORT_NODE_QUAD = 12,
     SF_EXPORT_GROUP_NPC = 13,
-    SF_EXPORT_GROUP_NPP = 14
+    SF_EXPORT_GROUP_NPP = 14,
+    SF_EXPORT_GROUP_CKS = 15
 } sf_export_id;
 
 sf_status sf_grav_tree_export(sf_grav_tree tree, int32_t what, void *host_dst,

@@ -22,12 +22,22 @@ a multipole:
   (a) L^2 > theta^2 r^2, r = distance from the node centre of mass to the
       group's bounding box (0 if inside) -- the per-target test made safe for
       every target of the group;
+  (r) only when a relative tolerance alpha is given: G M L^2 > alpha g r^4,
+      with g the smallest previous field magnitude |g| among the group's
+      members and r as in (a) -- Sec. 2.2's acceleration-based criterion (the
+      node's quadrupole-order error G M L^2 / r^4 must stay below a fraction
+      alpha of the target's total field), which the paper always combines
+      with (a); taking the smallest r and the smallest |g| makes it hold for
+      every member;
   (b) the node's cube meets the group's bounding box, or the node holds one of
       the group's particles -- a target never sits inside an accepted node;
   (c) the gap between cube and bounding box is below the larger of the two
       maximum softening radii -- every softened pair (r < max(S_i,S_j),
-      Sec. 2.2.1) is summed particle by particle, so nodes carry no softening.
-All three decisions are taken in FP64 with separate multiply and add steps.
+      Sec. 2.2.1) is summed particle by particle, so nodes carry no softening;
+  (z) the node's mass is zero: it has no centre of mass to expand about, so
+      its (massless) particles are summed as pairs, which keeps the mass
+      derivative of the frozen-list approximation equal to the direct sum's.
+All decisions are taken in FP64 with separate multiply and add steps.
 
 Sink particles: targets that are sinks see gas through the tree (node moments
 over gas only) and other sinks through an exact FP64 direct sum.
@@ -292,11 +302,19 @@ def make_groups(tree, group_cap=64):
 
 # --------------------------------------------------------------- walk
 
-def walk(tree, mom, clo, chi, cell, blo, bhi, hg, gfirst, gcount, theta):
+def field_norms(acc_prev):
+    """|g| per particle from a previous field (n, 3): sqrt((gx^2 + gy^2) + gz^2)
+    in FP64, each step separately rounded."""
+    g = np.asarray(acc_prev, dtype=np.float64)
+    return np.sqrt((g[:, 0] * g[:, 0] + g[:, 1] * g[:, 1]) + g[:, 2] * g[:, 2])
+
+
+def walk(tree, mom, clo, chi, cell, blo, bhi, hg, gfirst, gcount, theta, ag=None, G=1.0):
     """Interaction lists of one group: (accepted nodes, opened-leaf particles).
 
-    Particles are returned as sorted positions.  Nodes whose (selected) mass
-    is zero are skipped together with their subtree.
+    Particles are returned as sorted positions.  `ag` = alpha * (smallest
+    previous |g| of the group's members) switches on the relative criterion
+    (r); None leaves only the opening angle and the guards.
     """
     th2 = theta * theta
     M, com, hmax = mom["M"], mom["com"], mom["hmax"]
@@ -304,9 +322,6 @@ def walk(tree, mom, clo, chi, cell, blo, bhi, hg, gfirst, gcount, theta):
     pc, pp = [], []
     gl = gfirst + gcount
     while front.size:
-        front = front[M[front] > 0.0]
-        if not front.size:
-            break
         f = tree.first[front]
         c = tree.count[front]
         overlap = (f < gl) & (gfirst < f + c)
@@ -320,8 +335,13 @@ def walk(tree, mom, clo, chi, cell, blo, bhi, hg, gfirst, gcount, theta):
         e = np.maximum(np.maximum(blo[None, :] - cm, cm - bhi[None, :]), 0.0)
         r2 = (e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1]) + e[:, 2] * e[:, 2]
         L = cell[front]
-        angle = (L * L) > (th2 * r2)
-        opened = overlap | meets | soft | angle
+        L2 = L * L
+        angle = L2 > (th2 * r2)
+        Mf = M[front]
+        opened = overlap | meets | soft | angle | ~(Mf > 0.0)
+        if ag is not None:
+            with np.errstate(invalid="ignore"):   # inf * 0 (alpha = inf, r = 0) is not open
+                opened |= ((G * Mf) * L2) > (ag * (r2 * r2))
         pc.append(front[~opened])
         op = front[opened]
         leaf = tree.n_child[op] == 0
@@ -382,9 +402,14 @@ class TreeLists:
 
 
 def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=None,
-               lazy=False):
+               lazy=False, alpha=None, field=None, G=1.0):
     """Build the tree and every interaction list (optionally for some groups;
-    `lazy` computes node moments only where the walks look)."""
+    `lazy` computes node moments only where the walks look).
+
+    alpha (>= 0) with field (previous accelerations, (n, 3), input order)
+    adds the relative criterion: a group uses alpha times the smallest |g| of
+    its members, a sink target alpha times its own |g|.
+    """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     tree = build_tree(x, leaf_cap)
@@ -397,6 +422,11 @@ def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=
     xs = x[tree.order]
     hs = np.asarray(h, dtype=np.float64)[tree.order]
     sink_sorted = is_sink[tree.order]
+    gmag = None
+    if alpha is not None:
+        if field is None:
+            raise ValueError("the relative criterion needs a previous field")
+        gmag = field_norms(field)[tree.order]
     gl, sl = {}, {}
     n_pc = n_pp = 0
     gsel = range(groups.shape[0]) if groups_sel is None else groups_sel
@@ -406,7 +436,8 @@ def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=
             continue
         blo, bhi = xs[f:f + c].min(axis=0), xs[f:f + c].max(axis=0)
         hg = hs[f:f + c].max()
-        pc, pp = walk(tree, tree.mom["all"], clo, chi, cell, blo, bhi, hg, f, c, theta)
+        ag = None if gmag is None else alpha * gmag[f:f + c].min()
+        pc, pp = walk(tree, tree.mom["all"], clo, chi, cell, blo, bhi, hg, f, c, theta, ag, G)
         gl[g] = (pc, pp)
         ng = int((~sink_sorted[f:f + c]).sum())
         n_pc += ng * pc.size
@@ -418,7 +449,9 @@ def tree_lists(x, m, h, n_gas, theta=0.5, leaf_cap=16, group_cap=64, groups_sel=
         for p in np.nonzero(sink_sorted)[0]:
             sl[int(p)] = None
     for p in list(sl):
-        pc, pp = walk(tree, tree.mom["gas"], clo, chi, cell, xs[p], xs[p], hs[p], p, 1, theta)
+        ag = None if gmag is None else alpha * gmag[p]
+        pc, pp = walk(tree, tree.mom["gas"], clo, chi, cell, xs[p], xs[p], hs[p], p, 1, theta,
+                      ag, G)
         pp = pp[~sink_sorted[pp]]
         sl[p] = (pc, pp)
     return TreeLists(tree, groups, gl, sl, sink_sorted, n_pc, n_pp)
@@ -551,9 +584,11 @@ def tree_eval(x, m, h, n_gas, lists, G=1.0, order=0, targets=None):
     return acc, pot
 
 
-def tree_forward(x, m, h, n_gas, G=1.0, theta=0.5, order=0, leaf_cap=16, group_cap=64):
+def tree_forward(x, m, h, n_gas, G=1.0, theta=0.5, order=0, leaf_cap=16, group_cap=64,
+                 alpha=None, field=None):
     """Convenience: lists + FP64 evaluation, numpy in and out."""
-    lists = tree_lists(x, m, h, n_gas, theta, leaf_cap, group_cap)
+    lists = tree_lists(x, m, h, n_gas, theta, leaf_cap, group_cap, alpha=alpha, field=field,
+                       G=G)
     t = lambda v: torch.as_tensor(np.asarray(v, dtype=np.float64))
     with torch.no_grad():
         a, p = tree_eval(t(x), t(m), t(h), n_gas, lists, G, order)

@@ -12,9 +12,13 @@ from ._lib import (  # noqa: F401
     sf_grav_accel,
     sf_grav_accel_backward,
     sf_grav_build_tree,
+    sf_grav_get_stats,
     sf_grav_get_timings,
     sf_grav_get_tree_info,
+    sf_grav_release_cache,
     sf_grav_tree_export,
     sf_grav_tree_free,
+    sf_grav_tree_refit,
+    sf_grav_tree_set_field,
 )
 from .gravity import SFGravity, gravity  # noqa: F401

@@ -29,7 +29,7 @@ EXPORTS = {
     "group_first": (8, torch.int32, 2), "group_count": (9, torch.int32, 2),
     "node_mass": (10, torch.float64, 0), "node_com": (11, torch.float64, 0),
     "node_quad": (12, torch.float64, 0), "group_npc": (13, torch.int32, 2),
-    "group_npp": (14, torch.int32, 2),
+    "group_npp": (14, torch.int32, 2), "group_cks": (15, torch.int64, 2),
 }
 
 
@@ -45,6 +45,7 @@ class sf_grav_opts(ctypes.Structure):
         ("theta", ctypes.c_double), ("order", ctypes.c_int32), ("leaf_cap", ctypes.c_int32),
         ("group_cap", ctypes.c_int32), ("validate", ctypes.c_int32), ("n_gas", ctypes.c_int64),
         ("collect_stats", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
     ]
 
 
@@ -65,11 +66,21 @@ class sf_grav_tree_info(ctypes.Structure):
     ]
 
 
+class sf_grav_stats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("max_level", ctypes.c_int32),
+        ("n_nodes", ctypes.c_int64), ("n_leaves", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+        ("n_pc", ctypes.c_int64), ("n_pp", ctypes.c_int64), ("hist", ctypes.c_int64 * 32),
+        ("checksum", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_accel_backward", "sf_grav_tree_free", "sf_grav_get_tree_info",
             "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
-            "sf_grav_last_error")
+            "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
+            "sf_grav_get_stats", "sf_grav_release_cache")
 
 
 def lib():
@@ -97,9 +108,14 @@ def lib():
     L.sf_grav_strerror.restype = ctypes.c_char_p
     L.sf_grav_last_error.argtypes = []
     L.sf_grav_last_error.restype = ctypes.c_char_p
+    L.sf_grav_tree_set_field.argtypes = [vp, vp, vp]
+    L.sf_grav_tree_refit.argtypes = [vp, vp, vp, vp, vp]
+    L.sf_grav_get_stats.argtypes = [vp, ctypes.POINTER(sf_grav_stats)]
+    L.sf_grav_release_cache.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
                  "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
-                 "sf_grav_get_timings"):
+                 "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
+                 "sf_grav_get_stats", "sf_grav_release_cache"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -113,7 +129,8 @@ def _check(status, where):
 
 
 def make_opts(form="fp32c", G=1.0, theta=0.5, order=2, leaf_cap=32, group_cap=32,
-              validate=False, n_gas=-1, collect_stats=False, timing=False):
+              validate=False, n_gas=-1, collect_stats=False, timing=False, alpha=None):
+    """sf_grav_opts; alpha=None leaves the relative criterion off (-1)."""
     o = sf_grav_opts()
     lib().sf_grav_opts_default(ctypes.byref(o))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -121,6 +138,8 @@ def make_opts(form="fp32c", G=1.0, theta=0.5, order=2, leaf_cap=32, group_cap=32
     o.leaf_cap, o.group_cap = int(leaf_cap), int(group_cap)
     o.validate, o.n_gas, o.collect_stats = int(bool(validate)), int(n_gas), int(bool(collect_stats))
     o.timing = int(bool(timing))
+    if alpha is not None:
+        o.alpha = float(alpha)
     return o
 
 
@@ -259,3 +278,38 @@ def sf_grav_tree_export(tree, what):
     _check(lib().sf_grav_tree_export(tree.handle, wid, ctypes.c_void_p(out.data_ptr()), nbytes),
            "sf_grav_tree_export")
     return out.view(count, width) if width > 1 else out
+
+
+def sf_grav_tree_set_field(tree, acc_prev):
+    """Previous field (n, 3) in caller order for the relative criterion."""
+    if not acc_prev.is_cuda or not acc_prev.is_contiguous():
+        raise ValueError("acc_prev must be a contiguous GPU tensor")
+    if acc_prev.shape != (tree.n, 3) or acc_prev.dtype != tree.dtype:
+        raise ValueError("acc_prev must be (n, 3) in the handle's dtype")
+    _check(lib().sf_grav_tree_set_field(tree.handle, _ptr(acc_prev), _stream()),
+           "sf_grav_tree_set_field")
+
+
+def sf_grav_tree_refit(tree, pos, mass, soft):
+    """New particle values on the handle's frozen tree."""
+    _check_inputs(pos, mass, soft)
+    if pos.shape[0] != tree.n or pos.dtype != tree.dtype:
+        raise ValueError("refit needs the handle's n and dtype")
+    _check(lib().sf_grav_tree_refit(tree.handle, _ptr(pos), _ptr(mass), _ptr(soft), _stream()),
+           "sf_grav_tree_refit")
+
+
+def sf_grav_get_stats(tree):
+    st = sf_grav_stats()
+    st.struct_size = ctypes.sizeof(sf_grav_stats)
+    _check(lib().sf_grav_get_stats(tree.handle, ctypes.byref(st)), "sf_grav_get_stats")
+    out = {k: getattr(st, k) for k, _ in sf_grav_stats._fields_ if k not in ("struct_size", "hist")}
+    out["hist"] = list(st.hist)
+    return out
+
+
+def sf_grav_release_cache():
+    """Return the library's cached device blocks to HIP; bytes still in use."""
+    live = ctypes.c_size_t(0)
+    _check(lib().sf_grav_release_cache(ctypes.byref(live)), "sf_grav_release_cache")
+    return int(live.value)

@@ -770,8 +770,9 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
         ev.oz.zero();
         ev.oh.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf, gf + gc,
-                  a.err, npc, npp);
+        uint64_t cks;
+        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
+                         gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks);
         double v[4] = {ev.ox.value(), ev.oy.value(), ev.oz.value(), ev.oh.value()};
         for (uint32_t off = W; off < 64u; off <<= 1)
             for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
@@ -904,8 +905,9 @@ __global__ __launch_bounds__(64) void k_walk_sinks_b(WalkArgsB<T> a) {
         ev.oz.zero();
         ev.oh.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b, (double)a.hs[p], p,
-                  p + 1, a.err, npc, npp);
+        uint64_t cks;
+        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b,
+                         (double)a.hs[p], p, p + 1, task_ag_point(a.nd, p), a.err, npc, npp, cks);
         const double s0 = wave_sum_d(ev.ox.value()), s1 = wave_sum_d(ev.oy.value());
         const double s2 = wave_sum_d(ev.oz.value()), s4 = wave_sum_d(ev.oh.value());
         if (lane == 0) {
@@ -1084,6 +1086,7 @@ static WalkArgsB<T> make_args_b(sf_grav_tree_s *t, const EvalOpts &o, int set, c
     a.nd.q = t->nq[set];
     a.nd.side = t->hframe.side;
     a.nd.th2 = o.theta * o.theta;
+    set_relative(a.nd, t, o);
     a.xs = (const T *)t->xs;
     a.ys = (const T *)t->ys;
     a.zs = (const T *)t->zs;

@@ -82,8 +82,24 @@ void cache_release(void *p, hipStream_t s) {
     g_cached_bytes += lb.bytes;
 }
 
+// Allocation-failure injection (test hook): with SF_GRAV_FAIL_ALLOC=k in the
+// environment, the k-th device allocation of each entry-point call fails.
+namespace {
+thread_local long t_alloc_count = 0;
+thread_local long t_fail_at = 0;
+}  // namespace
+
+void fail_alloc_arm() {
+    const char *e = getenv("SF_GRAV_FAIL_ALLOC");
+    t_fail_at = e ? atol(e) : 0;
+    t_alloc_count = 0;
+}
+
 sf_status DevArena::alloc(void **p, size_t bytes, bool temp) {
     *p = nullptr;
+    if (t_fail_at > 0 && ++t_alloc_count == t_fail_at)
+        return sf_fail(SF_E_NOMEM, "device allocation %ld of this call failed (SF_GRAV_FAIL_ALLOC)",
+                       t_alloc_count);
     const size_t cls = size_class(bytes);
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -120,6 +136,45 @@ void DevArena::free_tmp() {
 void DevArena::free_keep() {
     for (void *p : keep) cache_release(p, s);
     keep.clear();
+}
+
+// Return every cached block to HIP (after the devices that own them have
+// finished their work) and trim the devices' default memory pools; report
+// the bytes still handed out (held by live handles or running calls).
+sf_status release_cache(size_t *live_bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return sf_fail(SF_E_DEVICE, "hipGetDevice failed");
+    bool used[64] = {};
+    for (auto &kv : g_free)
+        if (kv.first.dev >= 0 && kv.first.dev < 64) used[kv.first.dev] = true;
+    sf_status st = SF_OK;
+    for (int d = 0; d < 64; ++d) {
+        if (!used[d]) continue;
+        if (hipSetDevice(d) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            st = sf_fail(SF_E_DEVICE, "synchronising device %d failed", d);
+            continue;
+        }
+        for (auto it = g_free.begin(); it != g_free.end();) {
+            if (it->first.dev != d) {
+                ++it;
+                continue;
+            }
+            (void)hipFreeAsync(it->second, nullptr);
+            g_cached_bytes -= it->first.bytes;
+            it = g_free.erase(it);
+        }
+        (void)hipDeviceSynchronize();
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, d) == hipSuccess && pool)
+            (void)hipMemPoolTrimTo(pool, 0);
+    }
+    (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+    size_t live = 0;
+    for (auto &kv : g_live) live += kv.second.bytes;
+    if (live_bytes) *live_bytes = live;
+    return st;
 }
 
 // hipEvents for the phase timers, reused across handles.
@@ -252,6 +307,7 @@ static sf_status check_opts(const sf_grav_opts *o, int64_t n, bool need_tree_cap
     }
     if (!(o->G == o->G) || o->G > 1e300 || o->G < -1e300)
         return sf_fail(SF_E_INVALID, "opts.G must be finite");
+    if (o->alpha != o->alpha) return sf_fail(SF_E_INVALID, "opts.alpha is NaN");
     const int64_t ng = o->n_gas < 0 ? n : o->n_gas;
     if (ng > n) return sf_fail(SF_E_INVALID, "opts.n_gas %lld > n %lld", (long long)ng, (long long)n);
     return SF_OK;
@@ -301,6 +357,7 @@ void sf_grav_opts_default(sf_grav_opts *o) {
     o->n_gas = -1;
     o->collect_stats = 0;
     o->timing = 0;
+    o->alpha = -1.0;
 }
 
 const char *sf_grav_strerror(sf_status s) {
@@ -338,7 +395,7 @@ static sf_status build_all(sf_grav_tree_s *t, const void *pos, const void *mass,
     if (t->n_nodes >= (1ll << 27))
         return sf_fail(SF_E_UNSUPPORTED, "tree has %lld nodes (limit 2^27)", (long long)t->n_nodes);
     sf::phase_begin(t, 2);
-    st = sf::build_moments(t, ar);
+    st = sf::build_moments(t, ar, false);
     if (st != SF_OK) return st;
     sf::phase_end(t, 2);
     sf::phase_begin(t, 3);
@@ -356,6 +413,7 @@ sf_status sf_grav_build_tree(const void *pos, const void *mass, const void *soft
     if (st != SF_OK) return st;
     st = check_opts(o, n, true);
     if (st != SF_OK) return st;
+    sf::fail_alloc_arm();
     sf_grav_tree_s *t = new (std::nothrow) sf_grav_tree_s();
     if (!t) return sf_fail(SF_E_NOMEM, "host allocation failed");
     t->stream = (hipStream_t)stream;
@@ -392,7 +450,16 @@ static sf_status eval_opts(const sf_grav_opts *o, sf::EvalOpts &e) {
     e.order = o->order;
     e.G = o->G;
     e.theta = o->theta;
+    e.alpha = o->alpha;
     e.stats = o->collect_stats != 0;
+    return SF_OK;
+}
+
+// The relative criterion needs a previous field on the handle.
+static sf_status check_field(const sf_grav_tree_s *t, const sf_grav_opts *o) {
+    if (o->alpha >= 0.0 && !t->have_field)
+        return sf_fail(SF_E_STATE,
+                       "opts.alpha >= 0 needs a previous field: call sf_grav_tree_set_field first");
     return SF_OK;
 }
 
@@ -420,6 +487,9 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, co
         if (n != tree->n || dt != tree->dt)
             return sf_fail(SF_E_STATE, "n/dtype (%lld, %d) differ from the handle's (%lld, %d)",
                            (long long)n, (int)dt, (long long)tree->n, (int)tree->dt);
+        st = check_field(tree, o);
+        if (st != SF_OK) return st;
+        sf::fail_alloc_arm();
         eval_opts(o, e);
         hipStream_t prev = tree->stream;
         tree->stream = (hipStream_t)stream;
@@ -438,6 +508,7 @@ sf_status sf_grav_accel(sf_grav_tree tree, const void *pos, const void *mass, co
     st = check_opts(o, n, false);
     if (st != SF_OK) return st;
     eval_opts(o, e);
+    sf::fail_alloc_arm();
     sf_grav_tree_s t;
     t.stream = (hipStream_t)stream;
     t.direct_only = true;
@@ -466,6 +537,9 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void 
         if (tree->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
         if (n != tree->n || dt != tree->dt)
             return sf_fail(SF_E_STATE, "n/dtype differ from the handle's");
+        st = check_field(tree, o);
+        if (st != SF_OK) return st;
+        sf::fail_alloc_arm();
         eval_opts(o, e);
         tree->stream = (hipStream_t)stream;
         tree->timing = o->timing != 0;
@@ -478,6 +552,7 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos, const void 
     st = check_opts(o, n, false);
     if (st != SF_OK) return st;
     eval_opts(o, e);
+    sf::fail_alloc_arm();
     sf_grav_tree_s t;
     t.stream = (hipStream_t)stream;
     t.direct_only = true;
@@ -570,6 +645,11 @@ sf_status sf_grav_tree_export(sf_grav_tree t, int32_t what, void *host_dst, size
             src = what == SF_EXPORT_GROUP_NPC ? (const void *)t->gnpc : (const void *)t->gnpp;
             need = g * 4;
             break;
+        case SF_EXPORT_GROUP_CKS:
+            if (!t->have_stats) return sf_fail(SF_E_STATE, "no statistics collected");
+            src = t->gcks;
+            need = g * 8;
+            break;
         default: return sf_fail(SF_E_INVALID, "unknown export id %d", what);
     }
     if (bytes != need)
@@ -578,6 +658,41 @@ sf_status sf_grav_tree_export(sf_grav_tree t, int32_t what, void *host_dst, size
     SF_HIP(hipMemcpyAsync(host_dst, src, need, hipMemcpyDeviceToHost, t->stream));
     SF_HIP(hipStreamSynchronize(t->stream));
     return SF_OK;
+}
+
+sf_status sf_grav_tree_set_field(sf_grav_tree t, const void *acc_prev, void *stream) {
+    g_msg[0] = 0;
+    if (!t || !acc_prev) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (t->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    sf::fail_alloc_arm();
+    t->stream = (hipStream_t)stream;
+    return sf::set_field(t, acc_prev);
+}
+
+sf_status sf_grav_tree_refit(sf_grav_tree t, const void *pos, const void *mass, const void *soft,
+                             void *stream) {
+    g_msg[0] = 0;
+    if (!t || !pos || !mass || !soft) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (t->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    sf::fail_alloc_arm();
+    t->stream = (hipStream_t)stream;
+    DevArena ar(t->stream);
+    return sf::refit(t, pos, mass, soft, ar);
+}
+
+sf_status sf_grav_get_stats(sf_grav_tree t, sf_grav_stats *out) {
+    g_msg[0] = 0;
+    if (!t || !out) return sf_fail(SF_E_INVALID, "NULL argument");
+    if (out->struct_size != sizeof(sf_grav_stats))
+        return sf_fail(SF_E_INVALID, "stats.struct_size mismatch");
+    if (t->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    if (!t->have_stats) return sf_fail(SF_E_STATE, "no statistics collected");
+    return sf::tree_stats(t, out);
+}
+
+sf_status sf_grav_release_cache(size_t *live_bytes) {
+    g_msg[0] = 0;
+    return sf::release_cache(live_bytes);
 }
 
 }  // extern "C"

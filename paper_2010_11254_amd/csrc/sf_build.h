@@ -25,6 +25,23 @@ struct DevArena {
 
 // Return a block from DevArena::alloc to the library's cache (stream ordered).
 void cache_release(void *p, hipStream_t s);
+// Give every cached block back to HIP; *live_bytes = bytes still handed out.
+sf_status release_cache(size_t *live_bytes);
+// Read SF_GRAV_FAIL_ALLOC and restart the per-call allocation count.
+void fail_alloc_arm();
+
+// Allocations that a call adds to an existing handle: released again unless
+// committed to the handle.
+struct HandleAlloc {
+    DevArena ar;
+    sf_grav_tree_s *t;
+    explicit HandleAlloc(sf_grav_tree_s *tt) : ar(tt->stream), t(tt) {}
+    ~HandleAlloc() { ar.free_keep(); }
+    void commit() {
+        t->allocs.insert(t->allocs.end(), ar.keep.begin(), ar.keep.end());
+        ar.keep.clear();
+    }
+};
 
 }  // namespace sf
 
@@ -52,16 +69,29 @@ sf_status build_sorted(const void *pos, const void *mass, const void *soft, int6
                        int64_t n_gas, sf_dtype dt, bool type_major, bool validate,
                        sf_grav_tree_s *t, DevArena &ar);
 sf_status build_topology(sf_grav_tree_s *t, DevArena &ar);   // A5 (one stream sync)
-sf_status build_moments(sf_grav_tree_s *t, DevArena &ar);    // A6
+sf_status build_moments(sf_grav_tree_s *t, DevArena &ar, bool refit);   // A6
 sf_status build_groups(sf_grav_tree_s *t, DevArena &ar);     // A7
+sf_status group_boxes(sf_grav_tree_s *t);                    // A7: boxes of the built groups
+// Frozen-topology refit: new pos/mass/soft, same keys, order, nodes, groups.
+sf_status refit(sf_grav_tree_s *t, const void *pos, const void *mass, const void *soft,
+                DevArena &ar);
 
 struct EvalOpts {
     int form;
     int order;
     double G;
     double theta;
+    double alpha;   // relative criterion tolerance; < 0: off
     bool stats;
 };
+
+// Store |g| of a previous field (caller order, handle dtype) for the
+// relative criterion: per sorted particle and per group minimum.
+sf_status set_field(sf_grav_tree_s *t, const void *acc_prev);
+// Totals, list-length histogram and list checksum of the last walk with stats.
+sf_status tree_stats(sf_grav_tree_s *t, sf_grav_stats *out);
+struct WalkNodes;
+void set_relative(WalkNodes &nd, const sf_grav_tree_s *t, const EvalOpts &o);
 
 // A8-A10, A12: tree walk for gas targets, sink walk + FP64 sink-sink.
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);

@@ -163,7 +163,7 @@ static sf_status sort_stage(const void *pos, const void *mass, const void *soft,
                             DevArena &ar) {
     hipStream_t s = t->stream;
     SF_ALLOC(ar, t->frame, 1);
-    SF_HIP(hipMemsetAsync(t->frame, 0, sizeof(Frame), s));
+    fill_u32((uint32_t *)t->frame, sizeof(Frame) / 4, 0u, s);
     double *part = nullptr;
     SF_ALLOC_TMP(ar, part, kBoxBlocks * 6);
     int bb = (int)std::min<int64_t>(kBoxBlocks, (n + 255) / 256);
@@ -734,20 +734,22 @@ __global__ void k_moments_final(int64_t n_nodes, const double *__restrict__ clo,
     nq[k] = q;
 }
 
-sf_status build_moments(sf_grav_tree_s *t, DevArena &ar) {
+sf_status build_moments(sf_grav_tree_s *t, DevArena &ar, bool refit) {
     hipStream_t s = t->stream;
     const int64_t nn = t->n_nodes;
     double *raw0, *raw1;
     SF_ALLOC_TMP(ar, raw0, 11 * nn);
     SF_ALLOC_TMP(ar, raw1, 11 * nn);
-    SF_ALLOC(ar, t->pleaf, t->n);
-    for (int set = 0; set < 2; ++set) {
-        SF_ALLOC(ar, t->M[set], nn);
-        SF_ALLOC(ar, t->com[set], 3 * nn);
-        SF_ALLOC(ar, t->Q[set], 6 * nn);
-        SF_ALLOC(ar, t->hmax[set], nn);
-        SF_ALLOC(ar, t->nw[set], nn);
-        SF_ALLOC(ar, t->nq[set], nn);
+    if (!refit) {   // a refit overwrites the handle's arrays in place
+        SF_ALLOC(ar, t->pleaf, t->n);
+        for (int set = 0; set < 2; ++set) {
+            SF_ALLOC(ar, t->M[set], nn);
+            SF_ALLOC(ar, t->com[set], 3 * nn);
+            SF_ALLOC(ar, t->Q[set], 6 * nn);
+            SF_ALLOC(ar, t->hmax[set], nn);
+            SF_ALLOC(ar, t->nw[set], nn);
+            SF_ALLOC(ar, t->nq[set], nn);
+        }
     }
     if (t->dt == SF_F32)
         hipLaunchKernelGGL(k_moments_leaf<float>, dim3(nblk(8 * nn)), dim3(256), 0, s, nn,
@@ -898,6 +900,13 @@ sf_status build_groups(sf_grav_tree_s *t, DevArena &ar) {
                        t->nchild, t->nnchild, gcap, mark);
     scan_u32(mark, idx, n, scr, (uint32_t *)t->n_groups_dev, s);
     hipLaunchKernelGGL(k_grp_write, dim3(nblk(n)), dim3(256), 0, s, mark, idx, n, t->gfirst);
+    return group_boxes(t);
+}
+
+// Box, centre and largest softening of every group from the sorted particles.
+sf_status group_boxes(sf_grav_tree_s *t) {
+    hipStream_t s = t->stream;
+    const int64_t n = t->n;
     const int blocks = 16384;   // four waves per block, one group per wave
     if (t->dt == SF_F32)
         hipLaunchKernelGGL(k_grp_info<float>, dim3(blocks), dim3(256), 0, s, t->n_groups_dev, n,
@@ -910,6 +919,28 @@ sf_status build_groups(sf_grav_tree_s *t, DevArena &ar) {
                            t->gcen);
     SF_HIP(hipGetLastError());
     return SF_OK;
+}
+
+// New particle values on a frozen tree: the sorted SoA is re-gathered in the
+// handle's order, moments and group boxes are recomputed; keys, order,
+// topology, cubes and group ranges stay as built.
+sf_status refit(sf_grav_tree_s *t, const void *pos, const void *mass, const void *soft,
+                DevArena &ar) {
+    hipStream_t s = t->stream;
+    const int64_t n = t->n;
+    if (t->dt == SF_F32)
+        hipLaunchKernelGGL(k_permute<float>, dim3(nblk(n)), dim3(256), 0, s, (const float *)pos,
+                           (const float *)mass, (const float *)soft, (const uint32_t *)t->order, n,
+                           (float *)t->xs, (float *)t->ys, (float *)t->zs, (float *)t->ms,
+                           (float *)t->hs);
+    else
+        hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(256), 0, s, (const double *)pos,
+                           (const double *)mass, (const double *)soft, (const uint32_t *)t->order,
+                           n, (double *)t->xs, (double *)t->ys, (double *)t->zs, (double *)t->ms,
+                           (double *)t->hs);
+    sf_status st = build_moments(t, ar, true);
+    if (st != SF_OK) return st;
+    return group_boxes(t);
 }
 
 }  // namespace sf

@@ -24,6 +24,7 @@ struct Frame {
     int32_t bad;      // validation: count of non-finite / h <= 0 / m < 0
     int32_t pad;
 };
+static_assert(sizeof(Frame) % 4 == 0, "Frame is cleared as 32-bit words");
 
 // Status word of a decoupled look-back scan: 2 flag bits + 30-bit value.
 constexpr uint32_t kFlagAgg = 1u << 30;
@@ -166,7 +167,12 @@ struct sf_grav_tree_s {
     double *ghmax = nullptr;
     double *gcen = nullptr;                           // 3 per group
     int32_t *gnpc = nullptr, *gnpp = nullptr;         // stats
+    uint64_t *gcks = nullptr;                         // stats: list checksum per group
     bool have_stats = false;
+    // previous field for the relative criterion: |g| per sorted particle and
+    // smallest |g| per group
+    double *fpt = nullptr, *fgrp = nullptr;
+    bool have_field = false;
     // per group, written by every forward walk: (3 nodes + particles) x the
     // adjoint's lanes per target, so the adjoint can start costly groups first
     uint32_t *gcost = nullptr;

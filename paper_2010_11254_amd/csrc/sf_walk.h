@@ -20,6 +20,12 @@ struct WalkNodes {
     const NodeQ *q;                      // quadrupoles of that set
     double side;                         // root cube side (cell = side 2^-level)
     double th2;                          // theta^2
+    // relative (acceleration-based) criterion, on when rel != 0: a task
+    // opens a node when G M L^2 > ag r^4, ag = alpha |g|min of the task
+    int32_t rel;
+    double G, alpha;
+    const double *fgrp;                  // per group: smallest previous |g| of its members
+    const double *fpt;                   // per sorted particle: previous |g|
 };
 
 // Ring of opened-leaf particle ranges (first, count).
@@ -119,12 +125,15 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
 
 // ---------------------------------------------------------------- walk core
 
-// Test one node against the task box: cls 0 skip, 1 accept, 2 open leaf that
-// may hold softened pairs, 3 open inner, 4 open leaf with only Newtonian
-// pairs (gap to the box at least the larger max softening).  All FP64 steps
-// are separately rounded (no contraction).  The node record is read once,
-// whole, and the fields the walk needs next are returned with the class, so
-// a step costs one memory round trip per node.
+// Test one node against the task box: cls 1 accept, 2 open leaf that may
+// hold softened pairs, 3 open inner, 4 open leaf with only Newtonian pairs
+// (gap to the box at least the larger max softening).  A node is opened when
+// its opening angle is too large, when the relative criterion (if on) asks
+// for it, when it is near the box (overlap, contact, softening) or when it
+// has no mass (no centre of mass to expand about: its particles are summed
+// as pairs).  All FP64 steps are separately rounded (no contraction).  The
+// node record is read once, whole, and the fields the walk needs next are
+// returned with the class, so a step costs one memory round trip per node.
 struct NodeHit {
     int cls;
     int32_t first, count, child, lvl_nch;
@@ -132,7 +141,7 @@ struct NodeHit {
 
 __device__ __forceinline__ NodeHit classify(const WalkNodes &nd, int node, const double blo[3],
                                             const double bhi[3], double hg, int64_t gf,
-                                            int64_t gl) {
+                                            int64_t gl, double ag) {
     const NodeW w = nd.w[node];
     const int64_t f = w.first, c = w.count;
     const bool open = (f < gl) && (gf < f + c);
@@ -149,11 +158,31 @@ __device__ __forceinline__ NodeHit classify(const WalkNodes &nd, int node, const
     const bool soft = dbb2 < dmul(hm, hm);
     const double r2 = dadd(dadd(dmul(e[0], e[0]), dmul(e[1], e[1])), dmul(e[2], e[2]));
     const double L = ldexp(nd.side, -(w.lvl_nch >> 8));
-    const bool angle = dmul(L, L) > dmul(nd.th2, r2);
+    const double L2 = dmul(L, L);
+    bool far_ok = !(L2 > dmul(nd.th2, r2)) && w.M > 0.0;
+    if (nd.rel) far_ok = far_ok && !(dmul(dmul(nd.G, w.M), L2) > dmul(ag, dmul(r2, r2)));
     const bool near = open || meets || soft;
-    int cls = !(near || angle) ? 1 : ((w.lvl_nch & 255) != 0 ? 3 : (near ? 2 : 4));
-    if (!(w.M > 0.0)) cls = 0;
+    const int cls = (!near && far_ok) ? 1 : ((w.lvl_nch & 255) != 0 ? 3 : (near ? 2 : 4));
     return {cls, w.first, w.count, w.child, w.lvl_nch};
+}
+
+// Relative-criterion threshold of a task (alpha times the smallest previous
+// |g| of its targets); unused when the criterion is off.
+__device__ __forceinline__ double task_ag_group(const WalkNodes &nd, int g) {
+    return nd.rel ? dmul(nd.alpha, nd.fgrp[g]) : 0.0;
+}
+__device__ __forceinline__ double task_ag_point(const WalkNodes &nd, int64_t p) {
+    return nd.rel ? dmul(nd.alpha, nd.fpt[p]) : 0.0;
+}
+
+// Order-independent list checksum: each accepted node adds mix(node), each
+// opened leaf mix(node + 2^31); the sum over the list (mod 2^64) identifies
+// the set of decisions a task took.
+__device__ __forceinline__ uint64_t list_mix(uint64_t v) {
+    v += 0x9e3779b97f4a7c15ull;
+    v = (v ^ (v >> 30)) * 0xbf58476d1ce4e5b9ull;
+    v = (v ^ (v >> 27)) * 0x94d049bb133111ebull;
+    return v ^ (v >> 31);
 }
 
 // Next task index for the whole wave, as a scalar (SGPR) value: lane 0 takes
@@ -282,11 +311,12 @@ __device__ __forceinline__ uint32_t stack_in(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class Ev>
+// With CKS, cks receives (on every lane) the task's list checksum.
+template <bool CKS, class Ev>
 __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev &ev,
                           const double blo[3], const double bhi[3], double hg, int64_t gf,
-                          int64_t gl, int32_t *err, uint32_t &n_pc, uint32_t &n_pp,
-                          uint32_t ppb = 64u) {
+                          int64_t gl, double ag, int32_t *err, uint32_t &n_pc, uint32_t &n_pp,
+                          uint64_t &cks, uint32_t ppb = 64u) {
     const int lane = threadIdx.x;
     const uint64_t lt = lane_mask_lt();
     uint32_t sp = 1;     // stack positions [0, sp)
@@ -298,6 +328,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
     uint32_t fh = 0, ft = 0, fpend = 0;   // far ring
     n_pc = 0;
     n_pp = 0;
+    uint64_t lane_cks = 0;
     __syncthreads();
     // Every node is popped at most once per task, so a task takes at most
     // n_nodes steps; the bound makes termination unconditional.
@@ -337,8 +368,10 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
                              ? (int)((ent_e >> 4) + ((uint32_t)lane - (incl_e - (ent_e & 15u))))
                              : -1;
         NodeHit hit{0, 0, 0, 0, 0};
-        if (node >= 0) hit = classify(nd, node, blo, bhi, hg, gf, gl);
+        if (node >= 0) hit = classify(nd, node, blo, bhi, hg, gf, gl, ag);
         const int cls = hit.cls;
+        if (CKS && (cls == 1 || cls == 2 || cls == 4))
+            lane_cks += list_mix((uint64_t)node + (cls == 1 ? 0ull : (1ull << 31)));
         const uint64_t macc = __ballot(cls == 1), mnear = __ballot(cls == 2),
                        mint = __ballot(cls == 3), mfar = __ballot(cls == 4);
         if (cls == 1) L.pc[(pc_t + popc64(macc & lt)) & 127] = node;
@@ -414,6 +447,12 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
             ev.template pp_batch<true>(L, npend);
             n_pp += npend;
         }
+    }
+    if (CKS) {
+        uint64_t v = lane_cks;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+        cks = v;
     }
     __syncthreads();
 }

@@ -12,9 +12,11 @@
 // entries from the top, up to 64 nodes, one node per lane, and tests each
 // against the task's bounding box in FP64 with separately rounded operations.
 // A node is opened when (a) L^2 > theta^2 r^2 with r the distance from its
-// centre of mass to the box, (b) its cube meets the box or it holds one of
-// the task's particles, or (c) the cube-box gap is below the larger maximum
-// softening.  Accepted nodes go to a ring of multipole interactions, opened
+// centre of mass to the box, (r) with the relative criterion on,
+// G M L^2 > alpha |g|min r^4 (|g|min the smallest previous field magnitude
+// of the task's targets), (b) its cube meets the box or it holds one of the
+// task's particles, (c) the cube-box gap is below the larger maximum
+// softening, or (z) it has no mass.  Accepted nodes go to a ring of multipole interactions, opened
 // leaves to a ring of particle ranges, opened inner nodes push their child
 // range.  Children are pushed in reverse lane order, so levels never decrease
 // from bottom to top of the stack; a new level-L entry is only pushed when a
@@ -50,6 +52,7 @@ struct WalkArgs {
     int32_t *err;
     uint32_t *gstack;          // kStack entries per block: stack overflow area
     int32_t *gnpc, *gnpp;      // stats (group mode), may be null
+    uint64_t *gcks;            // stats: per-group list checksum, may be null
     uint32_t *gcost;           // per-group cost for the adjoint's task order, may be null
     T *acc, *pot;
     double G;
@@ -243,6 +246,7 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
         const int64_t i = gf + tl;
         const bool active = a.order[i] < a.n_gas;
         uint32_t npc = 0, npp = 0;
+        uint64_t cks = 0;
         if (__ballot(active) != 0ull) {   // groups of sinks only are left to the sink walk
             ev.tx = to_frame<FORM>(a.xs[i], ev.cen[0]);
             ev.ty = to_frame<FORM>(a.ys[i], ev.cen[1]);
@@ -264,8 +268,9 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.ay.zero();
             ev.az.zero();
             ev.ap.zero();
-            walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
-                      gf + gc, a.err, npc, npp, kPPBatch<R>);
+            walk_task<STATS>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg,
+                             gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks,
+                             kPPBatch<R>);
             double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
             // sum the k copies of each target in a fixed order, through LDS
             // (the stage is free once the task's batches are done)
@@ -287,6 +292,7 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
         if (STATS && lane == 0) {
             a.gnpc[g] = (int32_t)npc;
             a.gnpp[g] = (int32_t)npp;
+            a.gcks[g] = cks;
         }
         if (lane == 0 && a.gcost) {
             uint32_t w = 1;   // the adjoint's lanes per target: gc rounded up to a power of two
@@ -394,8 +400,9 @@ __global__ __launch_bounds__(64) void k_walk_sinks(WalkArgs<T> a) {
         ev.az.zero();
         ev.ap.zero();
         uint32_t npc, npp;
-        walk_task(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b, (double)a.hs[p], p,
-                  p + 1, a.err, npc, npp);
+        uint64_t cks;
+        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, b, b,
+                         (double)a.hs[p], p, p + 1, task_ag_point(a.nd, p), a.err, npc, npp, cks);
         double s[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
         for (int d = 0; d < 4; ++d) s[d] = wave_sum_f64(s[d]);
         if (lane == 0) {
@@ -501,6 +508,119 @@ int device_cu_count() {
     return c;
 }
 
+// ---------------------------------------------------------------- previous field
+
+// |g| of each sorted particle from a previous field given in caller order:
+// sqrt((gx^2 + gy^2) + gz^2) in FP64, every step correctly rounded.
+template <typename T>
+__global__ void k_field_norm(const T *__restrict__ acc, const int32_t *__restrict__ order,
+                             int64_t n, double *__restrict__ fpt) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = order[s];
+    const double x = (double)acc[3 * o], y = (double)acc[3 * o + 1], z = (double)acc[3 * o + 2];
+    fpt[s] = __dsqrt_rn(dadd(dadd(dmul(x, x), dmul(y, y)), dmul(z, z)));
+}
+
+// Smallest |g| over each group's members (all of them, as the group box).
+__global__ void k_field_group(const double *__restrict__ fpt, const int32_t *__restrict__ n_groups,
+                              const int32_t *__restrict__ gfirst, const int32_t *__restrict__ gcount,
+                              int64_t cap, double *__restrict__ fgrp) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= cap) return;
+    double v = 0.0;
+    if (g < *n_groups) {
+        const int64_t f = gfirst[g], c = gcount[g];
+        v = fpt[f];
+        for (int64_t j = 1; j < c; ++j) v = fmin(v, fpt[f + j]);
+    }
+    fgrp[g] = v;
+}
+
+sf_status set_field(sf_grav_tree_s *t, const void *acc_prev) {
+    if (!t->fpt) {
+        HandleAlloc keep(t);
+        double *fpt, *fgrp;
+        SF_ALLOC(keep.ar, fpt, t->n);
+        SF_ALLOC(keep.ar, fgrp, t->groups_cap);
+        keep.commit();
+        t->fpt = fpt;
+        t->fgrp = fgrp;
+    }
+    const unsigned nb = (unsigned)((t->n + 255) / 256);
+    if (t->dt == SF_F32)
+        hipLaunchKernelGGL(k_field_norm<float>, dim3(nb), dim3(256), 0, t->stream,
+                           (const float *)acc_prev, t->order, t->n, t->fpt);
+    else
+        hipLaunchKernelGGL(k_field_norm<double>, dim3(nb), dim3(256), 0, t->stream,
+                           (const double *)acc_prev, t->order, t->n, t->fpt);
+    hipLaunchKernelGGL(k_field_group, dim3((unsigned)((t->groups_cap + 255) / 256)), dim3(256), 0,
+                       t->stream, t->fpt, t->n_groups_dev, t->gfirst, t->gcount, t->groups_cap,
+                       t->fgrp);
+    SF_HIP(hipGetLastError());
+    t->have_field = true;
+    return SF_OK;
+}
+
+// ---------------------------------------------------------------- statistics
+
+// One thread per group: interactions summed over the group's gas targets,
+// list-length histogram (bin b: 2^b <= nodes + particles < 2^(b+1), bin 0
+// also empty lists) and the combined list checksum; integer atomics only,
+// so the result does not depend on their order.
+__global__ void k_stats(const int32_t *__restrict__ n_groups, const int32_t *__restrict__ gfirst,
+                        const int32_t *__restrict__ gcount, const int32_t *__restrict__ order,
+                        int64_t n_gas, const int32_t *__restrict__ npc,
+                        const int32_t *__restrict__ npp, const uint64_t *__restrict__ cks,
+                        unsigned long long *__restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= *n_groups) return;
+    const int64_t f = gfirst[g], c = gcount[g];
+    uint64_t act = 0;
+    for (int64_t j = 0; j < c; ++j) act += order[f + j] < n_gas ? 1u : 0u;
+    atomicAdd(out + 0, (unsigned long long)(act * (uint64_t)npc[g]));
+    atomicAdd(out + 1, (unsigned long long)(act * (uint64_t)npp[g]));
+    atomicAdd(out + 2, (unsigned long long)list_mix(cks[g] + list_mix((uint64_t)g)));
+    const uint64_t len = (uint64_t)npc[g] + (uint64_t)npp[g];
+    const int bin = len <= 1 ? 0 : 63 - __clzll((long long)len);
+    atomicAdd(out + 3 + (bin < 32 ? bin : 31), 1ull);
+}
+
+sf_status tree_stats(sf_grav_tree_s *t, sf_grav_stats *out) {
+    DevArena ar(t->stream);
+    unsigned long long *d = nullptr;
+    SF_ALLOC_TMP(ar, d, 3 + 32);
+    fill_u32((uint32_t *)d, 2 * (3 + 32), 0u, t->stream);
+    hipLaunchKernelGGL(k_stats, dim3((unsigned)((t->groups_cap + 255) / 256)), dim3(256), 0,
+                       t->stream, t->n_groups_dev, t->gfirst, t->gcount, t->order, t->n_gas,
+                       t->gnpc, t->gnpp, t->gcks, d);
+    unsigned long long h[3 + 32];
+    uint32_t info[2] = {0, 0};
+    int32_t ng = 0;
+    SF_HIP(hipGetLastError());
+    SF_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipMemcpyAsync(info, t->info_dev, sizeof(info), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipMemcpyAsync(&ng, t->n_groups_dev, sizeof(ng), hipMemcpyDeviceToHost, t->stream));
+    SF_HIP(hipStreamSynchronize(t->stream));
+    out->max_level = (int32_t)info[0];
+    out->n_nodes = t->n_nodes;
+    out->n_leaves = info[1];
+    out->n_groups = ng;
+    out->n_pc = (int64_t)h[0];
+    out->n_pp = (int64_t)h[1];
+    out->checksum = h[2];
+    for (int b = 0; b < 32; ++b) out->hist[b] = (int64_t)h[3 + b];
+    return SF_OK;
+}
+
+void set_relative(WalkNodes &nd, const sf_grav_tree_s *t, const EvalOpts &o) {
+    nd.rel = o.alpha >= 0.0 ? 1 : 0;
+    nd.G = o.G;
+    nd.alpha = o.alpha;
+    nd.fgrp = t->fgrp;
+    nd.fpt = t->fpt;
+}
+
 template <typename T>
 static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void *acc, void *pot,
                              int32_t *ctr, double *ss, uint32_t *gstack) {
@@ -510,6 +630,7 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     a.nd.q = t->nq[set];
     a.nd.side = t->hframe.side;
     a.nd.th2 = o.theta * o.theta;
+    set_relative(a.nd, t, o);
     a.xs = (const T *)t->xs;
     a.ys = (const T *)t->ys;
     a.zs = (const T *)t->zs;
@@ -532,6 +653,7 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
     a.gstack = gstack;
     a.gnpc = t->gnpc;
     a.gnpp = t->gnpp;
+    a.gcks = t->gcks;
     a.gcost = set == 0 ? t->gcost : nullptr;
     a.acc = (T *)acc;
     a.pot = (T *)pot;
@@ -589,21 +711,30 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
     if (o.stats) {
         if (!t->gnpc) {
-            DevArena keep(t->stream);
-            SF_ALLOC(keep, t->gnpc, t->groups_cap);
-            SF_ALLOC(keep, t->gnpp, t->groups_cap);
-            for (void *p : keep.keep) t->allocs.push_back(p);
-            keep.keep.clear();
+            HandleAlloc keep(t);
+            int32_t *npc, *npp;
+            uint64_t *cks;
+            SF_ALLOC(keep.ar, npc, t->groups_cap);
+            SF_ALLOC(keep.ar, npp, t->groups_cap);
+            SF_ALLOC(keep.ar, cks, t->groups_cap);
+            keep.commit();
+            t->gnpc = npc;
+            t->gnpp = npp;
+            t->gcks = cks;
         }
-        fill_u32((uint32_t *)t->gnpc, t->groups_cap, 0u, t->stream);
-        fill_u32((uint32_t *)t->gnpp, t->groups_cap, 0u, t->stream);
+        FillRanges zero;
+        zero.add(t->gnpc, t->groups_cap);
+        zero.add(t->gnpp, t->groups_cap);
+        zero.add(t->gcks, 2 * t->groups_cap);
+        fill_ranges_u32(zero, 0u, t->stream);
         t->have_stats = true;
     }
     if (!t->gcost) {   // zero beyond the groups, so a cost order is a permutation of them
-        DevArena keep(t->stream);
-        SF_ALLOC(keep, t->gcost, t->groups_cap);
-        for (void *p : keep.keep) t->allocs.push_back(p);
-        keep.keep.clear();
+        HandleAlloc keep(t);
+        uint32_t *cost;
+        SF_ALLOC(keep.ar, cost, t->groups_cap);
+        keep.commit();
+        t->gcost = cost;
         fill_u32(t->gcost, t->groups_cap, 0u, t->stream);
     }
     t->have_cost = false;

@@ -33,8 +33,10 @@ def test_library_exports_every_declared_symbol():
 def test_opts_layout_and_defaults():
     from paper_2010_11254_amd import _lib
     o = _lib.make_opts()
-    assert o.struct_size == ctypes.sizeof(_lib.sf_grav_opts) == 56
+    assert o.struct_size == ctypes.sizeof(_lib.sf_grav_opts) == 64
     assert (o.theta, o.order, o.leaf_cap, o.group_cap, o.form) == (0.5, 2, 32, 32, 0)
+    assert o.alpha == -1.0          # relative criterion off by default
+    assert ctypes.sizeof(_lib.sf_grav_stats) == 8 + 5 * 8 + 32 * 8 + 8
 
 
 def test_strerror_and_invalid_arguments_without_device():
@@ -65,3 +67,10 @@ def test_strerror_and_invalid_arguments_without_device():
     assert L.sf_grav_accel(None, p, p, p, 10, 7, ctypes.byref(o), p, p, None) == 1
     assert L.sf_grav_accel(None, p, p, p, 10, 0, ctypes.byref(o), None, p, None) == 1
     assert L.sf_grav_tree_free(None) == 0
+    bad = _lib.make_opts(alpha=float("nan"))
+    assert L.sf_grav_accel(None, p, p, p, 10, 0, ctypes.byref(bad), p, p, None) == 1
+    assert b"alpha" in L.sf_grav_last_error()
+    # the new handle calls reject NULL before touching anything
+    assert L.sf_grav_tree_set_field(None, p, None) == 1
+    assert L.sf_grav_tree_refit(None, p, p, p, None) == 1
+    assert L.sf_grav_get_stats(None, None) == 1

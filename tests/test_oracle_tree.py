@@ -267,3 +267,23 @@ def test_lazy_moments_equal_eager_and_lists_agree():
     for g in a.gas_lists:
         for u, v in zip(a.gas_lists[g], b.gas_lists[g]):
             assert np.array_equal(u, v)
+
+
+def test_differentiable_moments_equal_plain_sums():
+    # the torch moments that the adjoint differentiates are the same M, centre
+    # of mass and traceless Q as the plain FP64 node sums (with and without a
+    # particle selection)
+    ps = clustered_cloud(3000, 12, seed=8, dtype=np.float64)
+    tree = T.build_tree(ps.x, 8)
+    xs = torch.tensor(ps.x[tree.order])
+    ms = torch.tensor(ps.m[tree.order])
+    nodes = np.arange(tree.n_nodes)
+    for sel in (None, np.arange(ps.n) < ps.n_gas):
+        mom = T.node_moments(tree, ps.x, ps.m, ps.h, sel=sel)
+        ok = mom["M"] > 0
+        M, com, Q = T._moments_torch(tree, xs, ms, nodes[ok], None if sel is None else sel[tree.order])
+        assert np.allclose(M.numpy(), mom["M"][ok], rtol=1e-13, atol=0)
+        scale = np.abs(ps.x).max()
+        assert np.allclose(com.numpy(), mom["com"][ok], rtol=0, atol=1e-13 * scale)
+        qs = (mom["M"][ok] * (tree.side / 2.0 ** tree.level[ok]) ** 2)[:, None, None]
+        assert np.all(np.abs(Q.numpy() - mom["Q"][ok]) <= 1e-13 * qs)
