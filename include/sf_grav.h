@@ -225,6 +225,25 @@ typedef struct {
 
 sf_status sf_grav_get_stats(sf_grav_tree tree, sf_grav_stats *out);
 
+/* Allocation-free variant of the direct path of sf_grav_accel (tree ==
+ * NULL), for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, kernels and results as sf_grav_accel(NULL, ...), but every
+ * scratch buffer is carved out of one fixed device array of 96 MiB inside
+ * the library (each device the library runs on holds its own copy until the
+ * process ends); the call makes no device allocation and no free.
+ * Limit: n <= 2^19 = 524,288 particles (any dtype, form and sink count).
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (the call clears what must start at zero): calls that overlap on
+ * one device, on any streams or threads, race and give undefined results.
+ * No synchronisation unless opts.validate = 1 (one stream sync, as in
+ * sf_grav_accel).
+ * Errors: SF_E_INVALID (as sf_grav_accel), SF_E_UNSUPPORTED (n > 2^19),
+ * SF_E_DEVICE. */
+sf_status sf_grav_accel_direct_noalloc(const void *pos, const void *mass, const void *soft,
+                                       int64_t n, sf_dtype dt, const sf_grav_opts *o,
+                                       void *acc, void *pot, void *stream);
+
 /* Return every device block the library keeps cached for reuse to HIP
  * (synchronises each device that owns cached blocks, then trims its default
  * memory pool).  *live_bytes (may be NULL) receives the bytes still handed

@@ -80,7 +80,7 @@ EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_accel_backward", "sf_grav_tree_free", "sf_grav_get_tree_info",
             "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
             "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
-            "sf_grav_get_stats", "sf_grav_release_cache")
+            "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc")
 
 
 def lib():
@@ -112,10 +112,12 @@ def lib():
     L.sf_grav_tree_refit.argtypes = [vp, vp, vp, vp, vp]
     L.sf_grav_get_stats.argtypes = [vp, ctypes.POINTER(sf_grav_stats)]
     L.sf_grav_release_cache.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+    L.sf_grav_accel_direct_noalloc.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(sf_grav_opts),
+                                               vp, vp, vp]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
                  "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
                  "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
-                 "sf_grav_get_stats", "sf_grav_release_cache"):
+                 "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -313,3 +315,18 @@ def sf_grav_release_cache():
     live = ctypes.c_size_t(0)
     _check(lib().sf_grav_release_cache(ctypes.byref(live)), "sf_grav_release_cache")
     return int(live.value)
+
+
+def sf_grav_accel_direct_noalloc(pos, mass, soft, opts, acc=None, pot=None, want_pot=True):
+    """Direct path without device allocation inside the library (n <= 2^19);
+    acc/pot: caller-allocated outputs (allocated here if not given)."""
+    _check_inputs(pos, mass, soft)
+    n, dtype = pos.shape[0], pos.dtype
+    if acc is None:
+        acc = torch.empty((n, 3), dtype=dtype, device=pos.device)
+    if pot is None and want_pot:
+        pot = torch.empty((n,), dtype=dtype, device=pos.device)
+    st = lib().sf_grav_accel_direct_noalloc(_ptr(pos), _ptr(mass), _ptr(soft), n, _dt(pos),
+                                            ctypes.byref(opts), _ptr(acc), _ptr(pot), _stream())
+    _check(st, "sf_grav_accel_direct_noalloc")
+    return acc, pot

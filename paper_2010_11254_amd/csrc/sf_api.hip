@@ -97,6 +97,15 @@ void fail_alloc_arm() {
 
 sf_status DevArena::alloc(void **p, size_t bytes, bool temp) {
     *p = nullptr;
+    if (fixed) {   // bump mode: no HIP allocation, nothing to release
+        const size_t off = (fixed_used + 255) & ~(size_t)255;
+        if (off > fixed_cap || bytes > fixed_cap - off)
+            return sf_fail(SF_E_INTERNAL, "fixed scratch of %zu bytes exhausted (%zu more needed)",
+                           fixed_cap, off + bytes - fixed_cap);
+        *p = fixed + off;
+        fixed_used = off + bytes;
+        return SF_OK;
+    }
     if (t_fail_at > 0 && ++t_alloc_count == t_fail_at)
         return sf_fail(SF_E_NOMEM, "device allocation %ld of this call failed (SF_GRAV_FAIL_ALLOC)",
                        t_alloc_count);

@@ -13,11 +13,21 @@ namespace sf {
 // Stream-ordered device allocations.  `keep` allocations belong to a tree
 // handle; `tmp` ones are released when the arena is destroyed (at the end of
 // a call).  On failure every allocation made so far can be released.
+// Bump mode (set_fixed): every allocation is carved, 256-byte aligned, out
+// of one caller-supplied device region and nothing is ever released or
+// allocated from HIP; running past the region's end is SF_E_INTERNAL.
 struct DevArena {
     hipStream_t s = nullptr;
     std::vector<void *> keep, tmp;
+    char *fixed = nullptr;
+    size_t fixed_cap = 0, fixed_used = 0;
     explicit DevArena(hipStream_t st) : s(st) {}
     ~DevArena() { free_tmp(); }
+    void set_fixed(void *base, size_t cap) {
+        fixed = (char *)base;
+        fixed_cap = cap;
+        fixed_used = 0;
+    }
     sf_status alloc(void **p, size_t bytes, bool temp);   // cached, stream ordered
     void free_tmp();
     void free_keep();
@@ -97,6 +107,8 @@ void set_relative(WalkNodes &nd, const sf_grav_tree_s *t, const EvalOpts &o);
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
 // A11: direct path on a handle built with type-major keys (no topology).
 sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
+// Bytes of one packed source record of the direct path in form `form`.
+size_t direct_rec_bytes(int form);
 // A13: adjoints.
 sf_status tree_backward(sf_grav_tree_s *t, const EvalOpts &o, const void *g_acc,
                         const void *g_pot, void *g_pos, void *g_mass, void *g_soft,

@@ -222,6 +222,10 @@ static sf_status direct_run(sf_grav_tree_s *t, const EvalOpts &o, void *acc, voi
     return SF_OK;
 }
 
+size_t direct_rec_bytes(int form) {
+    return form == SF_FP64 ? sizeof(SrcRec<double>) : sizeof(SrcRec<float>);
+}
+
 sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
     if (t->dt == SF_F32) {
         if (o.form == SF_FP32C) return direct_run<float, SF_FP32C>(t, o, acc, pot, ar);
