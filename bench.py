@@ -1,32 +1,42 @@
 #!/usr/bin/env python3
-"""Benchmark: softened-gravity accelerations/s at 4M particles, FP32C vs FP64.
+"""Benchmark: softened-gravity accelerations/s at 4M particles, FP32C vs FP64,
+with the p99 relative force error against the FP64 CPU oracle.
 
-Workload (precision study): 4,194,304 gas cells drawn as 512 Plummer clumps
-(scale radii log-uniform in [1e-4, 0.05], 70% of the mass) on a uniform
-background, softening = radius enclosing the 32 nearest neighbours, plus 2048
-close sink binaries (separations 1e-5..1e-3, sink softening 1e-4), FP32 inputs,
-seed 2.  One step = one full force evaluation on the GPU through the C ABI:
-tree build (box, keys, radix sort, gather, topology, moments, groups), group
-walk with quadrupole nodes at theta = 0.5, FP64 sink-sink sum, sink walk and
-output scatter.  value = particles / step time (accelerations per second).
+Headline workload (precision study, precision4m): 4,194,304 gas cells drawn
+as 512 Plummer clumps (scale radii log-uniform in [1e-4, 0.05], 70% of the
+mass) on a uniform background, softening = radius enclosing the 32 nearest
+neighbours, plus 2048 close sink binaries (separations 1e-5..1e-3, sink
+softening 1e-4), FP32 inputs, seed 2.  One step = one full force evaluation
+through the C ABI: tree build (box, keys, radix sort, gather, topology,
+moments, groups), the previous step's field handed to the tree (for the
+acceleration-based opening criterion), group walk with quadrupole nodes at
+theta = 0.5 combined with the relative criterion (alpha = 0.003), FP64
+sink-sink sum, sink walk and output scatter.  value = particles / step time.
 
-Reported beside it, on the same inputs:
-  * the tree step in the plain FP32 and the FP64 forms;
-  * the adjoint (accel_backward) against the force evaluation on one handle;
-  * the direct (all-pairs) path in FP32C and FP64, one evaluation each;
-  * the median and p99 relative force error of every form and path against
-    the FP64 CPU oracle (direct sum) on a random target subsample;
-  * the walk kernel's roofline (algorithmic FLOP per launch / launch time from
-    HIP events on the library's stream), the direct kernel's likewise, the
-    build's algorithmic HBM bytes per phase time, and the oracle itself timed
-    on the host cores over the subsample.
+Reported beside it:
+  * the same step without the relative criterion (theta only), and in the
+    FP64 and plain FP32 forms (FP32C/FP64 ratio at equal accuracy);
+  * the adjoint against the force evaluation on one handle (precision4m,
+    diff256k, fractal16m);
+  * the direct path in FP32C, plain FP32 and FP64, one evaluation each;
+  * uniform4k (4096 particles, FP64, monopole) and clustered1m (2^20 gas +
+    256 sinks) tree errors and times; fractal16m (2^24 gas + 10^4 sinks)
+    forward and backward at theta 0.5 and 0.7;
+  * median and p99 relative force error of every leg against the oracle on
+    random target samples (65,536 at precision4m), computed by a background
+    process running the oracle on the host cores while the GPU legs run;
+  * the walk kernel's roofline (algorithmic FLOP per launch / launch time
+    from HIP events on the library's stream), the direct kernel's and the
+    build's, and the oracle's own throughput (cpu_baseline).
 """
 import argparse
 import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +57,12 @@ PEAK_HBM_GBS = 8000.0
 # 8 x 24) + gather (read index 4 and x, m, h 20, write 20) + sink positions
 # (flags 8, scan 8, compaction 8).
 SORT_BYTES_PER_PARTICLE = 12 + 24 + 8 + 8 * 24 + 44 + 24
+# Relative (acceleration-based) opening criterion tolerances: quadrupole
+# workloads, and the monopole uniform sphere.
+ALPHA = 0.003
+ALPHA_MONO = 0.0005
+# Oracle target samples per workload (R18: 65,536 at precision4m).
+SAMPLES = {"precision4m": 65536, "clustered1m": 8192, "fractal16m": 2048, "uniform4k": 4096}
 # Files whose change invalidates the stored walk-kernel byte counters.
 WALK_SOURCES = ("sf_internal.h", "sf_math.h", "sf_walk.h", "sf_walk.hip")
 WALK_PMC_FILE = os.path.join(ROOT, "profiles", "walk_precision4m_pmc.md")
@@ -80,188 +96,70 @@ def stored_walk_traffic():
     return rec
 
 
-def fractal_leg(np, torch, L, cpu_targets, cotangents, subsample):
-    """Large run: fractal16m (16,777,216 gas in a 3-level Plummer-in-Plummer
-    hierarchy + 10,000 sinks, seed 4), forward and backward at theta 0.5 and
-    0.7, FP32C against FP64, with the force error on a random target sample."""
-    from synth import fractal_cloud
-    t0 = time.time()
-    ps = fractal_cloud(1 << 24, 5000, 2500, seed=4)
-    log(f"fractal16m: {ps.n} particles generated in {time.time() - t0:.1f}s")
-    dev = torch.device("cuda", 0)
-    x, m, h = (torch.as_tensor(v).to(dev) for v in (ps.x, ps.m, ps.h))
-    ga, gp = cotangents(ps.n, seed=4, dtype=np.float32)
-    ga, gp = torch.as_tensor(ga).to(dev), torch.as_tensor(gp).to(dev)
-    acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
-    pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
-    sample = subsample(ps.n, cpu_targets, seed=4) if cpu_targets else None
-    ref = None
-    if sample is not None:
-        from oracle import direct as odirect
-        t0 = time.perf_counter()
-        ref, _ = odirect.direct(ps.x.astype(np.float64), ps.m.astype(np.float64),
-                                ps.h.astype(np.float64), targets=sample)
-        log(f"fractal16m oracle: {sample.size} targets in {time.perf_counter() - t0:.1f}s")
-
-    def ev_ms(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
-
-    out = {"n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "seed": 4}
-    for theta in (0.5, 0.7):
-        for form in ("fp32c", "fp64"):
-            o = L.make_opts(form=form, theta=theta, n_gas=ps.n_gas, collect_stats=True)
-
-            def full():
-                t = L.sf_grav_build_tree(x, m, h, o)
-                L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
-                L.sf_grav_tree_free(t)
-            o.collect_stats = 0
-            step_ms = ev_ms(full, 3)
-            o.collect_stats = 1
-            t = L.sf_grav_build_tree(x, m, h, o)
-            L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
-            torch.cuda.synchronize()
-            r = {"step_ms": step_ms, "accels_per_s": ps.n / (step_ms * 1e-3)}
-            if form == "fp32c":
-                gf = L.sf_grav_tree_export(t, "group_first").numpy().astype(np.int64)
-                gc = L.sf_grav_tree_export(t, "group_count").numpy().astype(np.int64)
-                npc = L.sf_grav_tree_export(t, "group_npc").numpy().astype(np.int64)
-                npp = L.sf_grav_tree_export(t, "group_npp").numpy().astype(np.int64)
-                order = L.sf_grav_tree_export(t, "order").numpy()
-                csum = np.concatenate([[0], np.cumsum(order < ps.n_gas)])
-                active = csum[gf + gc] - csum[gf]
-                r["n_pc"], r["n_pp"] = int((active * npc).sum()), int((active * npp).sum())
-            o.collect_stats = 0
-            r["accel_ms"] = ev_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=acc,
-                                                            pot=pot), 2)
-            if ref is not None:
-                got = acc[torch.as_tensor(sample, device=dev)].double().cpu().numpy()
-                e = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
-                r["rel_err"] = {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99))}
-            r["backward_ms"] = ev_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga,
-                                                                      gp), 1)
-            r["backward_over_accel"] = r["backward_ms"] / r["accel_ms"]
-            L.sf_grav_tree_free(t)
-            key = f"theta{theta}_{form}"
-            out[key] = r
-            log(f"fractal16m {key}: step {step_ms:.1f} ms, accel {r['accel_ms']:.1f} ms, "
-                f"backward {r['backward_ms']:.1f} ms" +
-                (f", p99 {r['rel_err']['p99']:.2e}" if "rel_err" in r else ""))
-        fl = FLOP_PP * out[f"theta{theta}_fp32c"]["n_pp"] + FLOP_PC[2] * out[f"theta{theta}_fp32c"]["n_pc"]
-        out[f"theta{theta}_fp32c"]["accel_tflops"] = fl / (out[f"theta{theta}_fp32c"]["accel_ms"] * 1e-3) / 1e12
-        out[f"theta{theta}_fp32c_over_fp64"] = (out[f"theta{theta}_fp64"]["step_ms"] /
-                                                out[f"theta{theta}_fp32c"]["step_ms"])
-    return out
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="target CPU time of the oracle baseline sample")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 and plain-FP32 forms")
-    ap.add_argument("--no-direct", action="store_true", help="skip the direct-path evaluations")
-    ap.add_argument("--no-backward", action="store_true", help="skip the adjoint timing")
-    ap.add_argument("--scale", type=float, default=1.0, help="particle-count scale (tests only)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
-    ap.add_argument("--fractal", action="store_true",
-                    help="also run the 16M fractal workload (forward + backward, theta 0.5 and 0.7)")
-    ap.add_argument("--leaf-cap", type=int, default=32)
-    ap.add_argument("--group-cap", type=int, default=32)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
-              "(how the walk would shard over GPUs is a design, not code)", file=sys.stderr)
-        sys.exit(2)
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
 
+
+# ---------------------------------------------------------------- oracle worker
+
+def make_workload(name):
+    from synth import make_config
+    return make_config(name)
+
+
+def oracle_worker(outdir, names):
+    """Runs in its own process: regenerate each workload from its seed, draw
+    its target sample and evaluate the FP64 oracle direct sum on it."""
     import numpy as np
-    import torch
-
-    from paper_2010_11254_amd import _lib as L
-    from synth import cotangents, precision_cloud, subsample
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    n_gas = max(4096, int(round((1 << 22) * args.scale)))
-    n_bin = max(16, int(round(2048 * args.scale)))
-    t0 = time.time()
-    ps = precision_cloud(n_gas, n_bin, seed=2)
-    log(f"workload: {ps.n} particles ({ps.n_gas} gas, {ps.n_sink} sinks), "
-        f"generated in {time.time() - t0:.1f}s")
-    dev = torch.device("cuda", 0)
-    x, m, h = (torch.as_tensor(v).to(dev) for v in (ps.x, ps.m, ps.h))
-    if args.copy_probe:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.add(src, 1.0, out=dst)   # reads 256 MiB, writes 256 MiB
-        torch.cuda.synchronize()
-        del src, dst
-    acc = torch.empty((ps.n, 3), dtype=torch.float32, device=dev)
-    pot = torch.empty((ps.n,), dtype=torch.float32, device=dev)
-
-    # oracle target sample: size it to the requested CPU time first
-    sample = None
-    xd = md = hd = None
-    if not args.no_cpu:
-        from oracle import direct as odirect
-        xd, md, hd = (np.asarray(v, dtype=np.float64) for v in (ps.x, ps.m, ps.h))
-        probe = subsample(ps.n, 256, seed=2)
+    from oracle import direct as odirect
+    from synth import subsample
+    for name in names:
+        t0 = time.time()
+        ps = make_workload(name)
+        tg = time.time() - t0
+        sample = subsample(ps.n, SAMPLES[name], seed=_seed(name))
+        x, m, h = (np.asarray(v, dtype=np.float64) for v in (ps.x, ps.m, ps.h))
         t0 = time.perf_counter()
-        odirect.direct(xd, md, hd, targets=probe)
-        rate = probe.size / (time.perf_counter() - t0)
-        sample = subsample(ps.n, int(min(65536, max(512, rate * args.cpu_seconds))), seed=2)
-    outs = {}
+        ref, _ = odirect.direct(x, m, h, targets=sample)
+        tc = time.perf_counter() - t0
+        np.save(os.path.join(outdir, f"{name}_ref.npy"), ref)
+        np.save(os.path.join(outdir, f"{name}_sample.npy"), sample)
+        with open(os.path.join(outdir, f"{name}.json"), "w") as fh:
+            json.dump({"targets": int(sample.size), "sources": int(ps.n), "seconds": tc,
+                       "gen_seconds": tg, "threads": host_threads()}, fh)
+        print(f"[oracle] {name}: {sample.size} targets x {ps.n} sources in {tc:.1f}s", flush=True,
+              file=sys.stderr)
 
-    def keep(name):
-        if sample is not None:
-            outs[name] = acc[torch.as_tensor(sample, device=dev)].double().cpu().numpy()
 
-    def opts(form, timing=False, stats=False):
-        return L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=args.leaf_cap,
-                           group_cap=args.group_cap, n_gas=ps.n_gas, timing=timing,
-                           collect_stats=stats)
+def _seed(name):
+    return {"uniform4k": 0, "clustered1m": 1, "precision4m": 2, "diff256k": 7, "fractal16m": 4}[name]
 
-    def step(o):
-        t = L.sf_grav_build_tree(x, m, h, o)
-        L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot)
-        return t
 
-    def timed(form, steps, warmup):
-        o = opts(form, timing=True)
-        for _ in range(warmup):
-            L.sf_grav_tree_free(step(o))
-        torch.cuda.synchronize()
-        walk_ms, phase = [], {}
-        t_start = time.perf_counter()
-        for _ in range(steps):
-            t = step(o)
-            tm = L.sf_grav_get_timings(t)
-            walk_ms.append(tm["walk"])
-            for k, v in tm.items():
-                if v is not None:
-                    phase.setdefault(k, []).append(v)
-            L.sf_grav_tree_free(t)
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t_start) / steps
-        return wall, float(np.mean(walk_ms)), {k: float(np.mean(v)) for k, v in phase.items()}
+# ---------------------------------------------------------------- GPU helpers
 
-    def event_ms(fn, reps):
+class Gpu:
+    def __init__(self, np, torch, L):
+        self.np, self.torch, self.L = np, torch, L
+        self.dev = torch.device("cuda", 0)
+
+    def upload(self, ps):
+        return [self.torch.as_tensor(v).to(self.dev) for v in (ps.x, ps.m, ps.h)]
+
+    def event_ms(self, fn, reps):
         """Mean time of fn() over reps calls, HIP events on the current stream
         (the one the library enqueues on)."""
+        torch = self.torch
         fn()
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -273,96 +171,212 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    # interaction counts of one evaluation (untimed), for the FLOP count
-    t = step(opts("fp32c", stats=True))
-    torch.cuda.synchronize()
-    gf = L.sf_grav_tree_export(t, "group_first").numpy().astype(np.int64)
-    gc = L.sf_grav_tree_export(t, "group_count").numpy().astype(np.int64)
-    npc = L.sf_grav_tree_export(t, "group_npc").numpy().astype(np.int64)
-    npp = L.sf_grav_tree_export(t, "group_npp").numpy().astype(np.int64)
-    order = L.sf_grav_tree_export(t, "order").numpy()
-    info = L.sf_grav_get_tree_info(t)
-    L.sf_grav_tree_free(t)
-    is_gas_sorted = (order < ps.n_gas).astype(np.int64)
-    csum = np.concatenate([[0], np.cumsum(is_gas_sorted)])
-    active = csum[gf + gc] - csum[gf]
-    n_pc = int((active * npc).sum())
-    n_pp = int((active * npp).sum())
+
+class TreeLeg:
+    """Repeated tree steps on one workload: build, previous field (when the
+    relative criterion is on), walk.  The field of step k is the output of
+    step k - 1 (the first from a theta-only evaluation)."""
+
+    def __init__(self, g, ps, x, m, h, form, theta, alpha, order=2, leaf_cap=32, group_cap=32):
+        self.g, self.ps, self.x, self.m, self.h = g, ps, x, m, h
+        L, torch = g.L, g.torch
+        self.opts = dict(form=form, theta=theta, order=order, leaf_cap=leaf_cap,
+                         group_cap=group_cap, n_gas=ps.n_gas, alpha=alpha)
+        self.alpha = alpha
+        n = ps.n
+        self.acc = [torch.empty((n, 3), dtype=x.dtype, device=g.dev) for _ in range(2)]
+        self.pot = torch.empty((n,), dtype=x.dtype, device=g.dev)
+        self.cur = 0
+        if alpha is not None:   # field of a theta-only evaluation to start from
+            # (with statistics on: another kernel instance than the timed walks)
+            o = L.make_opts(**{**self.opts, "alpha": None, "collect_stats": True})
+            t = L.sf_grav_build_tree(x, m, h, o)
+            L.sf_grav_accel(t, None, None, None, o, acc=self.acc[1], pot=self.pot)
+            L.sf_grav_tree_free(t)
+
+    def o(self, **kw):
+        return self.g.L.make_opts(**{**self.opts, **kw})
+
+    def step(self, o):
+        L = self.g.L
+        t = L.sf_grav_build_tree(self.x, self.m, self.h, o)
+        if self.alpha is not None:
+            L.sf_grav_tree_set_field(t, self.acc[1 - self.cur])
+        L.sf_grav_accel(t, None, None, None, o, acc=self.acc[self.cur], pot=self.pot)
+        self.cur = 1 - self.cur
+        return t
+
+    @property
+    def last(self):
+        return self.acc[1 - self.cur]
+
+    def timed(self, steps, warmup):
+        """Wall time per step (host clock around synchronised steps) and the
+        mean per-phase HIP event times."""
+        np, torch, L = self.g.np, self.g.torch, self.g.L
+        o = self.o(timing=True)
+        for _ in range(warmup):
+            L.sf_grav_tree_free(self.step(o))
+        torch.cuda.synchronize()
+        phase = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t = self.step(o)
+            for k, v in L.sf_grav_get_timings(t).items():
+                if v is not None:
+                    phase.setdefault(k, []).append(v)
+            L.sf_grav_tree_free(t)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        return wall, {k: float(np.mean(v)) for k, v in phase.items()}
+
+    def stats(self):
+        """Interaction totals of one (untimed) evaluation."""
+        L = self.g.L
+        t = self.step(self.o(collect_stats=True))
+        st = L.sf_grav_get_stats(t)
+        info = L.sf_grav_get_tree_info(t)
+        L.sf_grav_tree_free(t)
+        return st, info
+
+    def handle(self):
+        """A built tree with the field set, for accel/backward timings."""
+        L = self.g.L
+        o = self.o()
+        t = L.sf_grav_build_tree(self.x, self.m, self.h, o)
+        if self.alpha is not None:
+            L.sf_grav_tree_set_field(t, self.last)
+        return t, o
+
+
+def errors(np, got, ref):
+    nref = np.linalg.norm(ref, axis=1)
+    ok = nref > 0
+    e = np.linalg.norm(got - ref, axis=1)[ok] / nref[ok]
+    return {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)),
+            "max": float(e.max()), "targets": int(ok.sum())}
+
+
+# ---------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--alpha", type=float, default=ALPHA,
+                    help="relative opening criterion of the headline (negative: off)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline FP32C steps (profiling runs)")
+    ap.add_argument("--no-fractal", action="store_true", help="skip the 16M fractal workload")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
+    ap.add_argument("--leaf-cap", type=int, default=32)
+    ap.add_argument("--group-cap", type=int, default=32)
+    ap.add_argument("--oracle-worker", metavar="DIR", help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-names", default="", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.oracle_worker:
+        oracle_worker(args.oracle_worker, [s for s in args.oracle_names.split(",") if s])
+        return
+    if args.gpus != 1:
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how the walk would shard over GPUs is a design, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_11254_amd import _lib as L
+    from synth import cotangents, differentiation_cloud, subsample
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    alpha = args.alpha if args.alpha >= 0 else None
+    g = Gpu(np, torch, L)
+
+    # the oracle runs beside the GPU legs, on all host threads but two
+    worker, outdir = None, None
+    names = ["precision4m", "uniform4k", "clustered1m"] + ([] if args.no_fractal else ["fractal16m"])
+    if not (args.no_cpu or args.headline_only):
+        outdir = tempfile.mkdtemp(prefix="sfgrav_oracle_")
+        threads = max(1, host_threads() - 2)
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        worker = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                                   outdir, "--oracle-names", ",".join(names)], env=env)
+    samples = {n: subsample(make_workload_size(n), SAMPLES[n], seed=_seed(n)) for n in names}
+    kept = {}   # (workload, leg) -> outputs at the workload's sample
+
+    def keep(name, leg, acc):
+        kept[(name, leg)] = acc[torch.as_tensor(samples[name], device=g.dev)].double().cpu().numpy()
+
+    t0 = time.time()
+    ps = make_workload("precision4m")
+    log(f"precision4m: {ps.n} particles ({ps.n_gas} gas, {ps.n_sink} sinks), "
+        f"generated in {time.time() - t0:.1f}s")
+    x, m, h = g.upload(ps)
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=g.dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.add(src, 1.0, out=dst)   # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
+    caps = dict(leaf_cap=args.leaf_cap, group_cap=args.group_cap)
+
+    # headline: FP32C tree steps, theta + relative criterion
+    head = TreeLeg(g, ps, x, m, h, "fp32c", args.theta, alpha, **caps)
+    st, info = head.stats()
+    n_pc, n_pp = st["n_pc"], st["n_pp"]
     walk_flop = FLOP_PP * n_pp + FLOP_PC[2] * n_pc
     log(f"tree: {info['n_nodes']} nodes, {info['n_groups']} groups, max level {info['max_level']}; "
         f"interactions/target: {n_pc / ps.n_gas:.0f} node + {n_pp / ps.n_gas:.0f} particle")
-
-    # headline: FP32C tree steps
-    wall32, walk32, ph32 = timed("fp32c", args.steps, args.warmup)
-    keep("tree_fp32c")
+    wall32, ph32 = head.timed(args.steps, args.warmup)
+    keep("precision4m", "tree_fp32c", head.last)
+    walk32 = ph32["walk"]
     log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
         + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
-    res = {}
-    if not args.no_fp64:
-        k64 = max(2, args.steps // 3)
-        for form in ("fp64", "fp32"):
-            wall, walk, ph = timed(form, k64, 1)
-            keep("tree_" + form)
-            res[form] = {"ms_per_step": wall * 1e3, "value": ps.n / wall, "walk_ms": walk,
-                         "phases_ms": ph}
-            log(f"{form}: {wall * 1e3:.2f} ms/step, walk kernel {walk:.2f} ms")
 
-    # adjoint against the force evaluation on one handle (build excluded)
-    adj = {}
-    if not args.no_backward:
-        ga, gp = cotangents(ps.n, seed=2, dtype=np.float32)
-        ga, gp = torch.as_tensor(ga).to(dev), torch.as_tensor(gp).to(dev)
-        for form in ("fp32c",) + (() if args.no_fp64 else ("fp64",)):
-            o = opts(form)
-            t = L.sf_grav_build_tree(x, m, h, o)
-            fwd = event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=acc, pot=pot), 3)
-            bwd = event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga, gp), 2)
+    res, adj, direct = {}, {}, {}
+    if not args.headline_only:
+        # theta only (no relative criterion), and the FP64 / plain FP32 forms
+        k2 = max(2, args.steps // 3)
+        legs = [("fp32c_theta_only", "fp32c", None)] + [(f, f, alpha) for f in ("fp64", "fp32")]
+        for key, form, al in legs:
+            leg = TreeLeg(g, ps, x, m, h, form, args.theta, al, **caps)
+            wall, ph = leg.timed(k2, 1)
+            keep("precision4m", "tree_" + key, leg.last)
+            res[key] = {"ms_per_step": wall * 1e3, "value": ps.n / wall, "walk_ms": ph.get("walk"),
+                        "phases_ms": ph, "alpha": al}
+            if al is None and form == "fp32c":
+                s2, _ = leg.stats()
+                res[key].update(n_pc=s2["n_pc"], n_pp=s2["n_pp"])
+            log(f"{key}: {wall * 1e3:.2f} ms/step, walk kernel {ph.get('walk', 0):.2f} ms")
+            del leg
+
+        # adjoint against the force evaluation on one handle (build excluded)
+        ga, gp = (torch.as_tensor(v).to(g.dev) for v in cotangents(ps.n, seed=2, dtype=np.float32))
+        for form in ("fp32c", "fp64"):
+            leg = head if form == "fp32c" else TreeLeg(g, ps, x, m, h, form, args.theta, alpha, **caps)
+            t, o = leg.handle()
+            fwd = g.event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=leg.acc[0],
+                                                     pot=leg.pot), 3)
+            bwd = g.event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga, gp), 2)
             L.sf_grav_tree_free(t)
-            build = res.get(form, {}).get("phases_ms") if form != "fp32c" else ph32
-            b_ms = sum(build[k] for k in ("sort", "topology", "moments", "groups")) if build else None
             adj[form] = {"accel_ms": fwd, "backward_ms": bwd, "backward_over_accel": bwd / fwd}
-            if b_ms is not None:
-                adj[form]["with_build"] = (bwd + b_ms) / (fwd + b_ms)
             log(f"adjoint {form}: accel {fwd:.2f} ms, backward {bwd:.2f} ms, ratio {bwd / fwd:.2f}")
         del ga, gp
 
-    # the same ratio on the differentiation workload (2^18 clustered gas,
-    # per-particle h, seed 7; cotangents N(0, 1)); the build is timed with
-    # events too, for the ratio that includes it
-    adj_diff = {}
-    if not args.no_backward:
-        from synth import differentiation_cloud
-        dcl = differentiation_cloud(1 << 18, seed=7)
-        dx, dm, dh = (torch.as_tensor(v).to(dev) for v in (dcl.x, dcl.m, dcl.h))
-        dga, dgp = cotangents(dcl.n, seed=7, dtype=np.float32)
-        dga, dgp = torch.as_tensor(dga).to(dev), torch.as_tensor(dgp).to(dev)
-        dacc = torch.empty((dcl.n, 3), dtype=torch.float32, device=dev)
-        dpot = torch.empty(dcl.n, dtype=torch.float32, device=dev)
-        for form in ("fp32c",) + (() if args.no_fp64 else ("fp64",)):
-            o = L.make_opts(form=form, theta=args.theta, order=2, leaf_cap=args.leaf_cap,
-                            group_cap=args.group_cap, n_gas=dcl.n_gas)
-            bld = event_ms(lambda: L.sf_grav_tree_free(L.sf_grav_build_tree(dx, dm, dh, o)), 5)
-            t = L.sf_grav_build_tree(dx, dm, dh, o)
-            fwd = event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=dacc, pot=dpot), 10)
-            bwd = event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, dga, dgp), 5)
-            L.sf_grav_tree_free(t)
-            adj_diff[form] = {"build_ms": bld, "accel_ms": fwd, "backward_ms": bwd,
-                              "backward_over_accel": bwd / fwd,
-                              "with_build": (bwd + bld) / (fwd + bld)}
-            log(f"diff256k adjoint {form}: build {bld:.2f} ms, accel {fwd:.2f} ms, backward "
-                f"{bwd:.2f} ms, ratio {bwd / fwd:.2f} ({(bwd + bld) / (fwd + bld):.2f} with the build)")
-        del dx, dm, dh, dga, dgp, dacc, dpot
-
-    # direct path: one evaluation per form over all pairs
-    direct = {}
-    if not args.no_direct:
+        # direct path: one evaluation per form over all pairs
         pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
-        for form in ("fp32c", "fp64"):
-            o = opts(form)
-            k = min(ps.n, 65536)
-            wx, wm, wh = x[:k].contiguous(), m[:k].contiguous(), h[:k].contiguous()
-            L.sf_grav_accel(None, wx, wm, wh, L.make_opts(form=form, n_gas=min(k, ps.n_gas)),
-                            acc=acc[:k], pot=pot[:k])   # loads the kernels
+        acc, pot = head.acc[0], head.pot
+        for form in ("fp32c", "fp32", "fp64"):
+            o = L.make_opts(form=form, n_gas=ps.n_gas)
+            k = 65536
+            L.sf_grav_accel(None, x[:k].contiguous(), m[:k].contiguous(), h[:k].contiguous(),
+                            L.make_opts(form=form, n_gas=k), acc=acc[:k], pot=pot[:k])  # warm
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -371,40 +385,97 @@ def main():
             b.record()
             torch.cuda.synchronize()
             ms = a.elapsed_time(b)
-            keep("direct_" + form)
+            keep("precision4m", "direct_" + form, acc)
             tf = FLOP_PP * pairs / (ms * 1e-3) / 1e12
-            peak = PEAK_FP32_TFLOPS if form == "fp32c" else PEAK_FP64_TFLOPS
+            peak = PEAK_FP64_TFLOPS if form == "fp64" else PEAK_FP32_TFLOPS
             direct[form] = {"ms": ms, "value": ps.n / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
                             "achieved_tflops": tf, "peak": peak, "frac": tf / peak}
-            if form == "fp32c":
+            if form != "fp64":
                 direct[form]["frac_nonpacked"] = tf / PEAK_FP32_NONPACKED_TFLOPS
             log(f"direct {form}: {ms:.1f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, {tf:.1f} TFLOP/s")
+        direct["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+    del x, m, h, head
+    torch.cuda.empty_cache()
 
-    cpu = None
-    errs = {}
-    if sample is not None:
-        from oracle import direct as odirect
-        t0 = time.perf_counter()
-        ar, _ = odirect.direct(xd, md, hd, targets=sample)
-        tcpu = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": sample.size / tcpu, "unit": "accels/s", "cores": cores, "kind": "oracle",
-               "sample": f"{sample.size} random targets x all {ps.n} sources, FP64 direct sum, "
-                         f"{tcpu:.1f}s"}
-        log(f"oracle: {sample.size} targets in {tcpu:.1f}s on {cores} threads")
-        nref = np.linalg.norm(ar, axis=1)
-        ok = nref > 0
-        for name, out in outs.items():
-            e = np.linalg.norm(out - ar, axis=1)[ok] / nref[ok]
-            errs[name] = {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99))}
-            log(f"error {name}: median {errs[name]['median']:.3e}, p99 {errs[name]['p99']:.3e}")
+    others = {}
+    if not args.headline_only:
+        # uniform4k: FP64, monopole, theta 0.5 with and without the criterion
+        u = make_workload("uniform4k")
+        ux, um, uh = g.upload(u)
+        others["uniform4k"] = {"n": u.n, "order": "monopole", "dtype": "fp64"}
+        for key, al in (("theta_only", None), ("relative", ALPHA_MONO)):
+            leg = TreeLeg(g, u, ux, um, uh, "fp64", args.theta, al, order=0, leaf_cap=16,
+                          group_cap=64)
+            wall, _ = leg.timed(5, 2)
+            keep("uniform4k", key, leg.last)
+            others["uniform4k"][key] = {"ms_per_step": wall * 1e3, "alpha": al}
+        # clustered1m: FP32C, quadrupole
+        c1 = make_workload("clustered1m")
+        cx, cm, ch = g.upload(c1)
+        others["clustered1m"] = {"n": c1.n, "n_sink": c1.n_sink, "order": "quadrupole",
+                                 "form": "fp32c"}
+        for key, al in (("theta_only", None), ("relative", alpha)):
+            leg = TreeLeg(g, c1, cx, cm, ch, "fp32c", args.theta, al, **caps)
+            wall, ph = leg.timed(args.steps, 2)
+            s1, _ = leg.stats()
+            keep("clustered1m", key, leg.last)
+            others["clustered1m"][key] = {"ms_per_step": wall * 1e3, "value": c1.n / wall,
+                                          "walk_ms": ph.get("walk"), "alpha": al,
+                                          "n_pc": s1["n_pc"], "n_pp": s1["n_pp"]}
+            log(f"clustered1m {key}: {wall * 1e3:.2f} ms/step")
+        del cx, cm, ch, leg
+        # diff256k: adjoint ratio (theta only, as the workload specifies)
+        d = differentiation_cloud(1 << 18, seed=7)
+        dx, dm, dh = g.upload(d)
+        dga, dgp = (torch.as_tensor(v).to(g.dev) for v in cotangents(d.n, seed=7, dtype=np.float32))
+        others["diff256k"] = {}
+        for form in ("fp32c", "fp64"):
+            o = L.make_opts(form=form, theta=args.theta, n_gas=d.n_gas, **caps)
+            bld = g.event_ms(lambda: L.sf_grav_tree_free(L.sf_grav_build_tree(dx, dm, dh, o)), 5)
+            t = L.sf_grav_build_tree(dx, dm, dh, o)
+            fwd = g.event_ms(lambda: L.sf_grav_accel(t, None, None, None, o), 10)
+            bwd = g.event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, dga, dgp), 5)
+            L.sf_grav_tree_free(t)
+            others["diff256k"][form] = {"build_ms": bld, "accel_ms": fwd, "backward_ms": bwd,
+                                        "backward_over_accel": bwd / fwd,
+                                        "with_build": (bwd + bld) / (fwd + bld)}
+            log(f"diff256k adjoint {form}: build {bld:.2f} ms, accel {fwd:.2f} ms, backward "
+                f"{bwd:.2f} ms, ratio {bwd / fwd:.2f}")
+        del dx, dm, dh, dga, dgp
+        torch.cuda.empty_cache()
+        if not args.no_fractal:
+            others["fractal16m"] = fractal_leg(g, caps, alpha, keep)
+
+    # oracle results
+    cpu, errs = None, {}
+    if worker is not None:
+        rc = worker.wait(timeout=900)
+        if rc != 0:
+            log(f"oracle worker failed with status {rc}")
+        for name in names:
+            try:
+                ref = np.load(os.path.join(outdir, f"{name}_ref.npy"))
+                smp = np.load(os.path.join(outdir, f"{name}_sample.npy"))
+                meta = json.load(open(os.path.join(outdir, f"{name}.json")))
+            except OSError:
+                continue
+            assert np.array_equal(smp, samples[name])
+            for (wname, leg), got in kept.items():
+                if wname == name:
+                    errs.setdefault(name, {})[leg] = errors(np, got, ref)
+                    e = errs[name][leg]
+                    log(f"error {name} {leg}: median {e['median']:.3e}, p99 {e['p99']:.3e}")
+            if name == "precision4m":
+                cpu = {"value": meta["targets"] / meta["seconds"], "unit": "accels/s",
+                       "cores": meta["threads"], "kind": "oracle",
+                       "cpu": cpu_model(),
+                       "sample": f"{meta['targets']} random targets x all {meta['sources']} "
+                                 f"sources, FP64 direct sum, {meta['seconds']:.1f}s on "
+                                 f"{meta['threads']} threads (run beside the GPU legs)"}
 
     achieved = walk_flop / (walk32 * 1e-3) / 1e12
-    traffic = None
     pmc = stored_walk_traffic()
-    if pmc is not None:
-        traffic = pmc["bytes_per_launch"]
-    sort_ms = ph32.get("sort")
+    traffic = pmc["bytes_per_launch"] if pmc else None
     line = {
         "metric": "softened-gravity accels/sec at 4M particles (FP32c vs FP64); p99 force err",
         "value": ps.n / wall32,
@@ -420,7 +491,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "precision4m: 4,194,304 clustered gas + 2048 sink binaries",
                    "n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "inputs": "fp32",
-                   "path": "tree", "theta": args.theta, "order": "quadrupole",
+                   "path": "tree", "theta": args.theta, "alpha": alpha, "order": "quadrupole",
                    "form": "fp32c", "leaf_cap": args.leaf_cap, "group_cap": args.group_cap,
                    "seed": 2},
         "roofline": {"bound": "alu", "kernel": "k_walk_groups", "achieved": achieved,
@@ -434,33 +505,79 @@ def main():
         "cpu_baseline": cpu,
         "phases_ms": ph32,
     }
+    sort_ms = ph32.get("sort")
     if sort_ms:
         gbs = SORT_BYTES_PER_PARTICLE * ps.n / (sort_ms * 1e-3) / 1e9
         line["build_sort_hbm"] = {"bytes_per_particle": SORT_BYTES_PER_PARTICLE,
                                   "achieved_gbs": gbs, "frac": gbs / PEAK_HBM_GBS}
-    for form in ("fp64", "fp32"):
-        if form in res:
-            line[form] = res[form]
+    for key, v in res.items():
+        line[key] = v
     if "fp64" in res:
         line["fp32c_over_fp64"] = res["fp64"]["ms_per_step"] / (wall32 * 1e3)
     if adj:
         line["adjoint"] = adj
-    if adj_diff:
-        line["adjoint_diff256k"] = adj_diff
     if direct:
         line["direct"] = direct
-        if "fp64" in direct:
-            line["direct"]["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+    line.update(others)
     if errs:
         line["rel_err"] = errs
-        if "tree_fp32c" in errs:
-            line["rel_err_fp32c"] = errs["tree_fp32c"]
-    if args.fractal:
-        del x, m, h, acc, pot
-        torch.cuda.empty_cache()
-        line["fractal16m"] = fractal_leg(np, torch, L, 0 if args.no_cpu else 2048, cotangents,
-                                         subsample)
+        e = errs.get("precision4m", {}).get("tree_fp32c")
+        if e:
+            line["rel_err_fp32c"] = e
+            line["p99_bar_1e-3_met"] = e["p99"] <= 1e-3
     print(json.dumps(line), flush=True)
+
+
+def make_workload_size(name):
+    return {"uniform4k": 4096, "clustered1m": (1 << 20) + 256, "precision4m": (1 << 22) + 4096,
+            "fractal16m": (1 << 24) + 10000}[name]
+
+
+def fractal_leg(g, caps, alpha, keep):
+    """fractal16m (16,777,216 gas in a 3-level Plummer-in-Plummer hierarchy +
+    10,000 sinks, seed 4): forward and backward at theta 0.5 and 0.7,
+    FP32C against FP64 (theta only, as the workload specifies), and the
+    FP32C step with the relative criterion at theta 0.5."""
+    np, torch, L = g.np, g.torch, g.L
+    from synth import cotangents
+    t0 = time.time()
+    ps = make_workload("fractal16m")
+    log(f"fractal16m: {ps.n} particles generated in {time.time() - t0:.1f}s")
+    x, m, h = g.upload(ps)
+    ga, gp = (torch.as_tensor(v).to(g.dev) for v in cotangents(ps.n, seed=4, dtype=np.float32))
+    out = {"n": ps.n, "n_gas": ps.n_gas, "n_sink": ps.n_sink, "seed": 4}
+    for theta, al in ((0.5, None), (0.7, None), (0.5, alpha)):
+        for form in ("fp32c", "fp64"):
+            if al is not None and form == "fp64":
+                continue
+            leg = TreeLeg(g, ps, x, m, h, form, theta, al, **caps)
+            wall, ph = leg.timed(3, 1)
+            key = f"theta{theta}_{form}" + ("_relative" if al is not None else "")
+            keep("fractal16m", key, leg.last)
+            r = {"ms_per_step": wall * 1e3, "value": ps.n / wall, "walk_ms": ph.get("walk"),
+                 "alpha": al}
+            if form == "fp32c":
+                st, _ = leg.stats()
+                r["n_pc"], r["n_pp"] = st["n_pc"], st["n_pp"]
+                r["walk_tflops"] = (FLOP_PP * st["n_pp"] + FLOP_PC[2] * st["n_pc"]) / (
+                    ph["walk"] * 1e-3) / 1e12
+            t, o = leg.handle()
+            r["accel_ms"] = g.event_ms(lambda: L.sf_grav_accel(t, None, None, None, o,
+                                                               acc=leg.acc[0], pot=leg.pot), 2)
+            r["backward_ms"] = g.event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o,
+                                                                           ga, gp), 1)
+            r["backward_over_accel"] = r["backward_ms"] / r["accel_ms"]
+            L.sf_grav_tree_free(t)
+            out[key] = r
+            log(f"fractal16m {key}: step {wall * 1e3:.1f} ms, accel {r['accel_ms']:.1f} ms, "
+                f"backward {r['backward_ms']:.1f} ms")
+            del leg
+        if al is None:
+            out[f"theta{theta}_fp32c_over_fp64"] = (out[f"theta{theta}_fp64"]["ms_per_step"] /
+                                                    out[f"theta{theta}_fp32c"]["ms_per_step"])
+    del x, m, h, ga, gp
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
