@@ -118,6 +118,59 @@ void or_direct(int64_t n, const double *x, const double *m, const double *h,
     }
 }
 
+/* Tidal tensor T = -grad grad Phi = d a / d x (at the target) and jerk
+ * j = d a / dt at targets tidx[0..nt) (or all if tidx NULL), from the same
+ * softened kernel (Sec. 2.2: T and j are summed with spatial derivatives of
+ * the kernel used for g).  With d = x_j - x_i, w = v_j - v_i:
+ *     T_i = -G sum_j m_j [F I + (F'/r) d d^T]
+ *     j_i =  G sum_j m_j [F w + (F'/r) (d . w) d]
+ * T is written as xx yy zz xy xz yz (6 per target); v may be NULL (then j
+ * is not computed). */
+void or_direct_tidal(int64_t n, const double *x, const double *m, const double *h,
+                     const double *v, double G, int64_t nt, const int64_t *tidx,
+                     double *T, double *J)
+{
+    int64_t count = tidx ? nt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = tidx ? tidx[t] : t;
+        double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2], hi = h[i];
+        double txx = 0.0, tyy = 0.0, tzz = 0.0, txy = 0.0, txz = 0.0, tyz = 0.0;
+        double jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double hij = hi > h[j] ? hi : h[j];
+            double F, P, FrR, b, c;
+            kern(r, hij, &F, &P, &FrR, &b, &c);
+            double mF = m[j] * F, mR = m[j] * FrR;
+            txx -= mF + mR * dx * dx;
+            tyy -= mF + mR * dy * dy;
+            tzz -= mF + mR * dz * dz;
+            txy -= mR * dx * dy;
+            txz -= mR * dx * dz;
+            tyz -= mR * dy * dz;
+            if (v) {
+                double wx = v[3 * j] - v[3 * i], wy = v[3 * j + 1] - v[3 * i + 1];
+                double wz = v[3 * j + 2] - v[3 * i + 2];
+                double dw = dx * wx + dy * wy + dz * wz;
+                jx += mF * wx + mR * dw * dx;
+                jy += mF * wy + mR * dw * dy;
+                jz += mF * wz + mR * dw * dz;
+            }
+        }
+        double *Tt = T + 6 * t;
+        Tt[0] = G * txx; Tt[1] = G * tyy; Tt[2] = G * tzz;
+        Tt[3] = G * txy; Tt[4] = G * txz; Tt[5] = G * tyz;
+        if (v) {
+            J[3 * t] = G * jx;
+            J[3 * t + 1] = G * jy;
+            J[3 * t + 2] = G * jz;
+        }
+    }
+}
+
 /* Exact gradient of L = sum_i (ga_i . a_i + gp_i phi_i) with respect to every
  * position, mass and softening radius (gather form over k).  The softening
  * derivative of a pair goes to the particle whose radius is the larger one;

@@ -26,6 +26,8 @@ def lib():
                                    _D, _D, ctypes.c_int64, _D, ctypes.c_double,
                                    ctypes.c_double]
         L.or_pair_loss.restype = ctypes.c_double
+        L.or_direct_tidal.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double,
+                                      ctypes.c_int64, _L, _D, _D]
         _lib = L
     return _lib
 
@@ -60,6 +62,27 @@ def direct(x, m, h, G=1.0, targets=None):
     pot = np.empty(nt)
     lib().or_direct(n, _p(x), _p(m), _p(h), float(G), nt, tp, _p(acc), _p(pot))
     return acc, pot
+
+
+def direct_tidal(x, m, h, v=None, G=1.0, targets=None):
+    """FP64 tidal tensor (n_t, 6: xx yy zz xy xz yz) and, with velocities v,
+    jerk (n_t, 3) by direct summation (None without v)."""
+    x, m, h = _d(x), _d(m), _d(h)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        nt, tp = t.size, t.ctypes.data_as(_L)
+    T = np.empty((nt, 6))
+    J = np.empty((nt, 3)) if v is not None else None
+    vp = _p(_d(v)) if v is not None else None
+    if v is not None:
+        v = _d(v)
+        vp = _p(v)
+    lib().or_direct_tidal(n, _p(x), _p(m), _p(h), vp, float(G), nt, tp, _p(T),
+                          _p(J) if J is not None else None)
+    return T, J
 
 
 def direct_vjp(x, m, h, ga, gp, G=1.0):

@@ -593,3 +593,104 @@ def tree_forward(x, m, h, n_gas, G=1.0, theta=0.5, order=0, leaf_cap=16, group_c
     with torch.no_grad():
         a, p = tree_eval(t(x), t(m), t(h), n_gas, lists, G, order)
     return a.numpy(), p.numpy(), lists
+
+
+# --------------------------------------------------------------- tidal tensor and jerk
+
+def _kernel_F_FrR(r, h):
+    """F and (dF/dr)/r of the softened kernel (numpy, FP64), r >= 0."""
+    u = r / h
+    h3, h5 = h ** 3, h ** 5
+    safe_u = np.where(u > 0.25, u, 0.25)
+    safe_r = np.where(r > 0, r, 1.0)
+    Fa = (32.0 / 3.0 - 192.0 / 5.0 * u ** 2 + 32.0 * u ** 3) / h3
+    Fb = (64.0 / 3.0 - 48.0 * u + 192.0 / 5.0 * u ** 2 - 32.0 / 3.0 * u ** 3
+          - 1.0 / (15.0 * safe_u ** 3)) / h3
+    Ra = (-384.0 / 5.0 + 96.0 * u) / h5
+    Rb = (-48.0 / safe_u + 384.0 / 5.0 - 32.0 * u + 1.0 / (5.0 * safe_u ** 5)) / h5
+    F = np.where(u < 0.5, Fa, np.where(u < 1.0, Fb, 1.0 / safe_r ** 3))
+    R = np.where(u < 0.5, Ra, np.where(u < 1.0, Rb, -3.0 / safe_r ** 5))
+    return F, R
+
+
+def _tidal_terms(d, w, mF, mR):
+    """Sums over the last-but-one axis of -(mF I + mR d d^T) and
+    mF w + mR (d.w) d, as (.., 6) and (.., 3)."""
+    T = np.stack([-(mF + mR * d[..., 0] * d[..., 0]), -(mF + mR * d[..., 1] * d[..., 1]),
+                  -(mF + mR * d[..., 2] * d[..., 2]), -mR * d[..., 0] * d[..., 1],
+                  -mR * d[..., 0] * d[..., 2], -mR * d[..., 1] * d[..., 2]], axis=-1).sum(-2)
+    J = None
+    if w is not None:
+        dw = (d * w).sum(-1)
+        J = (mF[..., None] * w + (mR * dw)[..., None] * d).sum(-2)
+    return T, J
+
+
+def tree_tidal(x, m, h, v, n_gas, lists, G=1.0):
+    """Tidal tensor (n, 6: xx yy zz xy xz yz) and jerk (n, 3; None without v)
+    of the frozen lists (Sec. 2.2: both summed in the same pass as g, from the
+    monopole contributions of accepted nodes and the softened pair kernel of
+    opened particles).  Node monopole: mass M, centre of mass c and
+    mass-weighted velocity V of the node's particles (gas only for sink
+    targets); sinks add the exact sum over the other sinks."""
+    tree = lists.tree
+    x = np.asarray(x, np.float64)
+    n = x.shape[0]
+    xs = x[tree.order]
+    ms = np.asarray(m, np.float64)[tree.order]
+    hs = np.asarray(h, np.float64)[tree.order]
+    vs = None if v is None else np.asarray(v, np.float64)[tree.order]
+    sink = lists.is_sink_sorted
+    T = np.zeros((n, 6))
+    J = np.zeros((n, 3)) if v is not None else None
+
+    def node(k, gas_only):
+        f, c = tree.first[k], tree.count[k]
+        mk = ms[f:f + c] * (~sink[f:f + c] if gas_only else 1.0)
+        M = mk.sum()
+        com = (mk[:, None] * xs[f:f + c]).sum(0) / M
+        V = None if vs is None else (mk[:, None] * vs[f:f + c]).sum(0) / M
+        return M, com, V
+
+    def one(p, pc, pp, gas_only):
+        Tp = np.zeros(6)
+        Jp = np.zeros(3) if vs is not None else None
+        if pc.size:
+            nodes = [node(k, gas_only) for k in pc]
+            Mn = np.array([a[0] for a in nodes])
+            d = np.array([a[1] for a in nodes]) - xs[p]
+            r = np.sqrt((d * d).sum(-1))
+            w = None if vs is None else np.array([a[2] for a in nodes]) - vs[p]
+            t, j = _tidal_terms(d, w, Mn / r ** 3, -3.0 * Mn / r ** 5)
+            Tp += t
+            if Jp is not None:
+                Jp += j
+        src = pp[pp != p]
+        if src.size:
+            d = xs[src] - xs[p]
+            r = np.sqrt((d * d).sum(-1))
+            F, R = _kernel_F_FrR(r, np.maximum(hs[src], hs[p]))
+            w = None if vs is None else vs[src] - vs[p]
+            t, j = _tidal_terms(d, w, ms[src] * F, ms[src] * R)
+            Tp += t
+            if Jp is not None:
+                Jp += j
+        return Tp, Jp
+
+    for g, (pc, pp) in lists.gas_lists.items():
+        f, c = lists.groups[g]
+        for p in range(f, f + c):
+            if sink[p]:
+                continue
+            Tp, Jp = one(p, pc, pp, False)
+            T[tree.order[p]] = G * Tp
+            if J is not None:
+                J[tree.order[p]] = G * Jp
+    sink_pos = np.nonzero(sink)[0]
+    for p, (pc, pp) in lists.sink_lists.items():
+        others = sink_pos[sink_pos != p]
+        Tp, Jp = one(p, pc, np.concatenate([pp, others]).astype(np.int64), True)
+        T[tree.order[p]] = G * Tp
+        if J is not None:
+            J[tree.order[p]] = G * Jp
+    return T, J
