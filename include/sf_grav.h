@@ -169,6 +169,30 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  void *g_pos, void *g_mass, void *g_soft,
                                  void *stream);
 
+/* Tidal tensor T = -grad grad Phi and jerk j = da/dt of every particle,
+ * computed in the same tree walk as its acceleration and potential (Sec.
+ * 2.2: T and j are summed in the same pass as g, with the same opening
+ * decisions, from the monopole contributions of accepted nodes and the
+ * spatial derivatives of the softened pair kernel; with d = x_j - x_i,
+ * w = v_j - v_i and F' = dF/dr:
+ *     T_i = -G sum_j m_j [F I + (F'/r) d d^T],
+ *     j_i =  G sum_j m_j [F w + (F'/r) (d . w) d]).
+ * The acceleration and potential keep the node expansion of opts.order, so
+ * they equal sf_grav_accel's on the same handle to rounding.  Sink targets
+ * add the exact FP64 sum over the other sinks for all four quantities.
+ * tree: a built handle (NULL gives SF_E_UNSUPPORTED: theta = 0 on a tree
+ *   gives the all-pairs sum); n, dtype and particles are the handle's.
+ * vel:  n x 3 velocities, caller order, handle dtype; needed only for jerk.
+ * acc:  n x 3 (required); pot: n; tidal: n x 6 as xx yy zz xy xz yz;
+ *   jerk: n x 3 -- each optional except acc, caller order and dtype.
+ * One lane per target (this evaluation does not split targets over lanes),
+ * arithmetic in opts.form, node velocities as FP64 mass-weighted means.
+ * Synchronises `stream` once (capacity-guard flag).
+ * Errors: SF_E_INVALID (NULL acc, jerk without vel, bad options),
+ * SF_E_STATE, SF_E_UNSUPPORTED, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */
+sf_status sf_grav_accel_tidal(sf_grav_tree tree, const void *vel, const sf_grav_opts *o,
+                              void *acc, void *pot, void *tidal, void *jerk, void *stream);
+
 /* Free a handle: synchronises the stream of the last call made on it, then
  * returns its memory to the library's cache.  NULL is a no-op. */
 sf_status sf_grav_tree_free(sf_grav_tree tree);

@@ -644,53 +644,54 @@ def tree_tidal(x, m, h, v, n_gas, lists, G=1.0):
     T = np.zeros((n, 6))
     J = np.zeros((n, 3)) if v is not None else None
 
-    def node(k, gas_only):
-        f, c = tree.first[k], tree.count[k]
-        mk = ms[f:f + c] * (~sink[f:f + c] if gas_only else 1.0)
-        M = mk.sum()
-        com = (mk[:, None] * xs[f:f + c]).sum(0) / M
-        V = None if vs is None else (mk[:, None] * vs[f:f + c]).sum(0) / M
+    def nodes(pc, gas_only):
+        """M, centre of mass and mean velocity of the nodes pc."""
+        idx = np.concatenate([np.arange(tree.first[k], tree.first[k] + tree.count[k]) for k in pc])
+        starts = np.concatenate([[0], np.cumsum(tree.count[pc])[:-1]])
+        mk = ms[idx] * (~sink[idx] if gas_only else 1.0)
+        M = np.add.reduceat(mk, starts)
+        com = np.add.reduceat(mk[:, None] * xs[idx], starts) / M[:, None]
+        V = None if vs is None else np.add.reduceat(mk[:, None] * vs[idx], starts) / M[:, None]
         return M, com, V
 
-    def one(p, pc, pp, gas_only):
-        Tp = np.zeros(6)
-        Jp = np.zeros(3) if vs is not None else None
+    def targets(tg, pc, pp, gas_only):
+        """T and j of the sorted targets tg from one list."""
+        Tt = np.zeros((tg.size, 6))
+        Jt = np.zeros((tg.size, 3)) if vs is not None else None
         if pc.size:
-            nodes = [node(k, gas_only) for k in pc]
-            Mn = np.array([a[0] for a in nodes])
-            d = np.array([a[1] for a in nodes]) - xs[p]
+            M, com, V = nodes(pc, gas_only)
+            d = com[None, :, :] - xs[tg][:, None, :]
             r = np.sqrt((d * d).sum(-1))
-            w = None if vs is None else np.array([a[2] for a in nodes]) - vs[p]
-            t, j = _tidal_terms(d, w, Mn / r ** 3, -3.0 * Mn / r ** 5)
-            Tp += t
-            if Jp is not None:
-                Jp += j
-        src = pp[pp != p]
-        if src.size:
-            d = xs[src] - xs[p]
+            w = None if vs is None else V[None, :, :] - vs[tg][:, None, :]
+            t, j = _tidal_terms(d, w, M / r ** 3, -3.0 * M / r ** 5)
+            Tt += t
+            if Jt is not None:
+                Jt += j
+        if pp.size:
+            d = xs[pp][None, :, :] - xs[tg][:, None, :]
             r = np.sqrt((d * d).sum(-1))
-            F, R = _kernel_F_FrR(r, np.maximum(hs[src], hs[p]))
-            w = None if vs is None else vs[src] - vs[p]
-            t, j = _tidal_terms(d, w, ms[src] * F, ms[src] * R)
-            Tp += t
-            if Jp is not None:
-                Jp += j
-        return Tp, Jp
+            F, R = _kernel_F_FrR(r, np.maximum(hs[pp][None, :], hs[tg][:, None]))
+            keep = tg[:, None] != pp[None, :]
+            w = None if vs is None else vs[pp][None, :, :] - vs[tg][:, None, :]
+            t, j = _tidal_terms(d, w, keep * ms[pp][None, :] * F, keep * ms[pp][None, :] * R)
+            Tt += t
+            if Jt is not None:
+                Jt += j
+        return Tt, Jt
 
     for g, (pc, pp) in lists.gas_lists.items():
         f, c = lists.groups[g]
-        for p in range(f, f + c):
-            if sink[p]:
-                continue
-            Tp, Jp = one(p, pc, pp, False)
-            T[tree.order[p]] = G * Tp
-            if J is not None:
-                J[tree.order[p]] = G * Jp
+        tg = np.arange(f, f + c)
+        tg = tg[~sink[tg]]
+        Tt, Jt = targets(tg, pc, pp, False)
+        T[tree.order[tg]] = G * Tt
+        if J is not None:
+            J[tree.order[tg]] = G * Jt
     sink_pos = np.nonzero(sink)[0]
     for p, (pc, pp) in lists.sink_lists.items():
         others = sink_pos[sink_pos != p]
-        Tp, Jp = one(p, pc, np.concatenate([pp, others]).astype(np.int64), True)
-        T[tree.order[p]] = G * Tp
+        Tt, Jt = targets(np.array([p]), pc, np.concatenate([pp, others]).astype(np.int64), True)
+        T[tree.order[p]] = G * Tt[0]
         if J is not None:
-            J[tree.order[p]] = G * Jp
+            J[tree.order[p]] = G * Jt[0]
     return T, J

@@ -80,7 +80,8 @@ EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_accel_backward", "sf_grav_tree_free", "sf_grav_get_tree_info",
             "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
             "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
-            "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc")
+            "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
+            "sf_grav_accel_tidal")
 
 
 def lib():
@@ -112,12 +113,14 @@ def lib():
     L.sf_grav_tree_refit.argtypes = [vp, vp, vp, vp, vp]
     L.sf_grav_get_stats.argtypes = [vp, ctypes.POINTER(sf_grav_stats)]
     L.sf_grav_release_cache.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+    L.sf_grav_accel_tidal.argtypes = [vp, vp, ctypes.POINTER(sf_grav_opts), vp, vp, vp, vp, vp]
     L.sf_grav_accel_direct_noalloc.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(sf_grav_opts),
                                                vp, vp, vp]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
                  "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
                  "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
-                 "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc"):
+                 "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
+                 "sf_grav_accel_tidal"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -330,3 +333,21 @@ def sf_grav_accel_direct_noalloc(pos, mass, soft, opts, acc=None, pot=None, want
                                             ctypes.byref(opts), _ptr(acc), _ptr(pot), _stream())
     _check(st, "sf_grav_accel_direct_noalloc")
     return acc, pot
+
+
+def sf_grav_accel_tidal(tree, opts, vel=None, want_pot=True, want_tidal=True):
+    """(acc, pot, tidal (n, 6: xx yy zz xy xz yz), jerk) of every particle from
+    one tree walk; jerk only with velocities vel (n, 3)."""
+    n, dtype = tree.n, tree.dtype
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if vel is not None and (vel.shape != (n, 3) or vel.dtype != dtype or not vel.is_cuda
+                            or not vel.is_contiguous()):
+        raise ValueError("vel must be a contiguous (n, 3) GPU tensor in the handle's dtype")
+    acc = torch.empty((n, 3), dtype=dtype, device=dev)
+    pot = torch.empty((n,), dtype=dtype, device=dev) if want_pot else None
+    tid = torch.empty((n, 6), dtype=dtype, device=dev) if want_tidal else None
+    jerk = torch.empty((n, 3), dtype=dtype, device=dev) if vel is not None else None
+    st = lib().sf_grav_accel_tidal(tree.handle, _ptr(vel), ctypes.byref(opts), _ptr(acc),
+                                   _ptr(pot), _ptr(tid), _ptr(jerk), _stream())
+    _check(st, "sf_grav_accel_tidal")
+    return acc, pot, tid, jerk

@@ -105,6 +105,10 @@ void set_relative(WalkNodes &nd, const sf_grav_tree_s *t, const EvalOpts &o);
 
 // A8-A10, A12: tree walk for gas targets, sink walk + FP64 sink-sink.
 sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
+// Tidal tensor and jerk (and g, phi) in one tree walk; vel may be NULL when
+// jerk is NULL; pot/tid may be NULL.
+sf_status tidal_accel(sf_grav_tree_s *t, const EvalOpts &o, const void *vel, void *acc, void *pot,
+                      void *tid, void *jerk, DevArena &ar);
 // A11: direct path on a handle built with type-major keys (no topology).
 sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
 // Bytes of one packed source record of the direct path in form `form`.
