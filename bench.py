@@ -61,8 +61,10 @@ SORT_BYTES_PER_PARTICLE = 12 + 24 + 8 + 8 * 24 + 44 + 24
 # workloads, and the monopole uniform sphere.
 ALPHA = 0.003
 ALPHA_MONO = 0.0005
-# Oracle target samples per workload (R18: 65,536 at precision4m).
+# Oracle target samples per workload (R18: 65,536 at precision4m), and the
+# sample of the tidal tensor and jerk check at precision4m (its own seed).
 SAMPLES = {"precision4m": 65536, "clustered1m": 8192, "fractal16m": 2048, "uniform4k": 4096}
+TIDAL_SAMPLE, TIDAL_SEED = 2048, 22
 # Files whose change invalidates the stored walk-kernel byte counters.
 WALK_SOURCES = ("sf_internal.h", "sf_math.h", "sf_walk.h", "sf_walk.hip")
 WALK_PMC_FILE = os.path.join(ROOT, "profiles", "walk_precision4m_pmc.md")
@@ -135,6 +137,13 @@ def oracle_worker(outdir, names):
         tc = time.perf_counter() - t0
         np.save(os.path.join(outdir, f"{name}_ref.npy"), ref)
         np.save(os.path.join(outdir, f"{name}_sample.npy"), sample)
+        if name == "precision4m":   # tidal tensor and jerk on their own sample
+            from synth import velocities
+            ts = subsample(ps.n, TIDAL_SAMPLE, seed=TIDAL_SEED)
+            v = velocities(ps.n, seed=_seed(name)).astype(np.float64)
+            Tr, Jr = odirect.direct_tidal(x, m, h, v, targets=ts)
+            np.save(os.path.join(outdir, "precision4m_tidal_T.npy"), Tr)
+            np.save(os.path.join(outdir, "precision4m_tidal_J.npy"), Jr)
         with open(os.path.join(outdir, f"{name}.json"), "w") as fh:
             json.dump({"targets": int(sample.size), "sources": int(ps.n), "seconds": tc,
                        "gen_seconds": tg, "threads": host_threads()}, fh)
@@ -290,7 +299,7 @@ def main():
     import torch
 
     from paper_2010_11254_amd import _lib as L
-    from synth import cotangents, differentiation_cloud, subsample
+    from synth import cotangents, differentiation_cloud, subsample, velocities
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -308,6 +317,8 @@ def main():
         worker = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
                                    outdir, "--oracle-names", ",".join(names)], env=env)
     samples = {n: subsample(make_workload_size(n), SAMPLES[n], seed=_seed(n)) for n in names}
+    samples["precision4m_tidal"] = subsample(make_workload_size("precision4m"), TIDAL_SAMPLE,
+                                             seed=TIDAL_SEED)
     kept = {}   # (workload, leg) -> outputs at the workload's sample
 
     def keep(name, leg, acc):
@@ -339,7 +350,7 @@ def main():
     log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
         + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
 
-    res, adj, direct = {}, {}, {}
+    res, adj, direct, tidal = {}, {}, {}, {}
     if not args.headline_only:
         # theta only (no relative criterion), and the FP64 / plain FP32 forms
         k2 = max(2, args.steps // 3)
@@ -368,6 +379,22 @@ def main():
             adj[form] = {"accel_ms": fwd, "backward_ms": bwd, "backward_over_accel": bwd / fwd}
             log(f"adjoint {form}: accel {fwd:.2f} ms, backward {bwd:.2f} ms, ratio {bwd / fwd:.2f}")
         del ga, gp
+
+        # tidal tensor and jerk in the same walk (Sec. 2.2), FP32C, same
+        # criterion and field as the headline, against the force evaluation
+        vel = torch.as_tensor(velocities(ps.n, seed=2)).to(g.dev)
+        t, o = head.handle()
+        fwd = g.event_ms(lambda: L.sf_grav_accel(t, None, None, None, o, acc=head.acc[0],
+                                                 pot=head.pot), 3)
+        tms = g.event_ms(lambda: L.sf_grav_accel_tidal(t, o, vel=vel), 3)
+        _, _, tid, jerk = L.sf_grav_accel_tidal(t, o, vel=vel)
+        L.sf_grav_tree_free(t)
+        keep("precision4m_tidal", "T", tid)
+        keep("precision4m_tidal", "j", jerk)
+        tidal = {"accel_ms": fwd, "tidal_jerk_ms": tms, "ratio": tms / fwd, "form": "fp32c",
+                 "alpha": alpha}
+        log(f"tidal+jerk fp32c: {tms:.2f} ms against accel {fwd:.2f} ms ({tms / fwd:.2f}x)")
+        del vel, tid, jerk
 
         # direct path: one evaluation per form over all pairs
         pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
@@ -466,6 +493,17 @@ def main():
                     e = errs[name][leg]
                     log(f"error {name} {leg}: median {e['median']:.3e}, p99 {e['p99']:.3e}")
             if name == "precision4m":
+                for leg, fname in (("T", "precision4m_tidal_T.npy"), ("j", "precision4m_tidal_J.npy")):
+                    try:
+                        ref_t = np.load(os.path.join(outdir, fname))
+                    except OSError:
+                        continue
+                    got = kept.get(("precision4m_tidal", leg))
+                    if got is not None:
+                        tidal["rel_err_" + leg] = errors(np, got, ref_t)
+                        log(f"error precision4m tidal {leg}: median "
+                            f"{tidal['rel_err_' + leg]['median']:.3e}, p99 "
+                            f"{tidal['rel_err_' + leg]['p99']:.3e}")
                 cpu = {"value": meta["targets"] / meta["seconds"], "unit": "accels/s",
                        "cores": meta["threads"], "kind": "oracle",
                        "cpu": cpu_model(),
@@ -518,6 +556,8 @@ def main():
         line["adjoint"] = adj
     if direct:
         line["direct"] = direct
+    if tidal:
+        line["tidal_jerk"] = tidal
     line.update(others)
     if errs:
         line["rel_err"] = errs

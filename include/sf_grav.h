@@ -193,6 +193,38 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
 sf_status sf_grav_accel_tidal(sf_grav_tree tree, const void *vel, const sf_grav_opts *o,
                               void *acc, void *pot, void *tidal, void *jerk, void *stream);
 
+/* Sinks-only pass (Sec. 2.3.2: the accelerations and jerks of all sinks in a
+ * special sinks-only gravity pass), FP64, exact direct sum over the sinks
+ * with the softened kernel (h_ss' = max(h_s, h_s')).  Arrays are FP64
+ * device pointers over the n sinks only: pos, vel n x 3; mass, soft n.
+ * Outputs (each optional except acc): acc n x 3, pot n, jerk n x 3,
+ * tidal n x 6 (xx yy zz xy xz yz), times n x 4 with the two-body time
+ * scales of Sec. 2.3.1 -- t_c,min = min sqrt(r^2 + eps^2) / |v_ss'| and
+ * t_dyn,min = min sqrt((r^2 + eps^2)^(3/2) / (G (m_s + m_s'))) over the other
+ * sinks, eps = h_s / 2.8 -- then, for eta > 0, the 2-body timestep
+ * sqrt(eta) / (1/t_c,min + 1/t_dyn,min) and the tidal timestep
+ * sqrt(eta) (|T|_F^2 / 6)^(-1/4) (0 for eta <= 0; a lone sink gets infinite
+ * time scales).  jerk and times need vel.  Enqueued on `stream`, no
+ * allocation, no synchronisation.
+ * Errors: SF_E_INVALID (NULL pos/mass/soft/acc, n < 1, jerk or times
+ * without vel, NaN G or eta), SF_E_DEVICE. */
+sf_status sf_grav_sinks(const double *pos, const double *vel, const double *mass,
+                        const double *soft, int64_t n, double G, double eta, double *acc,
+                        double *pot, double *jerk, double *tidal, double *times, void *stream);
+
+/* One step dt of the modified 4th-order Hermite scheme for all n sinks
+ * (Sec. 2.3.2, Eqs. predictor and corrector): a sinks-only pass at the
+ * start (a0, j0), the prediction x + v dt + a0 dt^2/2 + j0 dt^3/6,
+ * v + a0 dt + j0 dt^2/2, a second pass at the predicted state (a, j), then
+ * v <- v0 + (a + a0) dt/2 + (j0 - j) dt^2/12 and, with that v,
+ * x <- x0 + (v + v0) dt/2 + (a0 - a) dt^2/12.  pos and vel (FP64, n x 3,
+ * device) are updated in place; mass and soft as in sf_grav_sinks.
+ * Enqueued on `stream` (scratch from the library's cache), no
+ * synchronisation.
+ * Errors: SF_E_INVALID (NULL, n < 1, NaN dt or G), SF_E_NOMEM, SF_E_DEVICE. */
+sf_status sf_grav_sink_hermite(double *pos, double *vel, const double *mass, const double *soft,
+                               int64_t n, double G, double dt, void *stream);
+
 /* Free a handle: synchronises the stream of the last call made on it, then
  * returns its memory to the library's cache.  NULL is a no-op. */
 sf_status sf_grav_tree_free(sf_grav_tree tree);

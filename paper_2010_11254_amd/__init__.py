@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     sf_grav_get_timings,
     sf_grav_get_tree_info,
     sf_grav_release_cache,
+    sf_grav_sink_hermite,
+    sf_grav_sinks,
     sf_grav_tree_export,
     sf_grav_tree_free,
     sf_grav_tree_refit,

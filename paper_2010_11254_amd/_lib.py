@@ -81,7 +81,7 @@ EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
             "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
             "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
-            "sf_grav_accel_tidal")
+            "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite")
 
 
 def lib():
@@ -114,13 +114,16 @@ def lib():
     L.sf_grav_get_stats.argtypes = [vp, ctypes.POINTER(sf_grav_stats)]
     L.sf_grav_release_cache.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
     L.sf_grav_accel_tidal.argtypes = [vp, vp, ctypes.POINTER(sf_grav_opts), vp, vp, vp, vp, vp]
+    f64 = ctypes.c_double
+    L.sf_grav_sinks.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp, vp]
+    L.sf_grav_sink_hermite.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp]
     L.sf_grav_accel_direct_noalloc.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(sf_grav_opts),
                                                vp, vp, vp]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
                  "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
                  "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
                  "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
-                 "sf_grav_accel_tidal"):
+                 "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -351,3 +354,32 @@ def sf_grav_accel_tidal(tree, opts, vel=None, want_pot=True, want_tidal=True):
                                    _ptr(pot), _ptr(tid), _ptr(jerk), _stream())
     _check(st, "sf_grav_accel_tidal")
     return acc, pot, tid, jerk
+
+
+def _sink_arrays(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError("sink arrays must be contiguous FP64 GPU tensors")
+
+
+def sf_grav_sinks(pos, vel, mass, soft, G=1.0, eta=0.0, want=("acc", "pot", "jerk", "tidal", "times")):
+    """Sinks-only FP64 pass: dict of the requested outputs (acc n x 3, pot n,
+    jerk n x 3, tidal n x 6, times n x 4: t_c, t_dyn, dt_2body, dt_tidal)."""
+    _sink_arrays(pos, vel, mass, soft)
+    n = pos.shape[0]
+    shapes = {"acc": (n, 3), "pot": (n,), "jerk": (n, 3), "tidal": (n, 6), "times": (n, 4)}
+    out = {k: torch.empty(shapes[k], dtype=torch.float64, device=pos.device) for k in want}
+    out.setdefault("acc", torch.empty((n, 3), dtype=torch.float64, device=pos.device))
+    st = lib().sf_grav_sinks(_ptr(pos), _ptr(vel), _ptr(mass), _ptr(soft), n, float(G), float(eta),
+                             _ptr(out["acc"]), _ptr(out.get("pot")), _ptr(out.get("jerk")),
+                             _ptr(out.get("tidal")), _ptr(out.get("times")), _stream())
+    _check(st, "sf_grav_sinks")
+    return out
+
+
+def sf_grav_sink_hermite(pos, vel, mass, soft, dt, G=1.0):
+    """One modified Hermite step; pos and vel (FP64, n x 3) updated in place."""
+    _sink_arrays(pos, vel, mass, soft)
+    st = lib().sf_grav_sink_hermite(_ptr(pos), _ptr(vel), _ptr(mass), _ptr(soft), pos.shape[0],
+                                    float(G), float(dt), _stream())
+    _check(st, "sf_grav_sink_hermite")

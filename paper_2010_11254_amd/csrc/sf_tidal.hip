@@ -18,6 +18,7 @@
 // the group (lanes past the group's size idle), batch entries staged in LDS
 // and read by every lane.
 #include "sf_build.h"
+#include "sf_ext.h"
 #include "sf_math.h"
 #include "sf_prims.h"
 #include "sf_walk.h"
@@ -25,49 +26,6 @@
 namespace sf {
 
 namespace {
-
-constexpr int kX = 13;   // ax ay az phi  Txx Tyy Tzz Txy Txz Tyz  jx jy jz
-
-// One source term (pair or node monopole); mF = m F, mR = m F'/r, mP = m P.
-template <typename R, bool JERK>
-__device__ __forceinline__ void ext_term(R dx, R dy, R dz, R wx, R wy, R wz, R mF, R mR, R mP,
-                                         R (&b)[kX], bool force) {
-    if (force) {
-        b[0] += mF * dx;
-        b[1] += mF * dy;
-        b[2] += mF * dz;
-        b[3] -= mP;
-    }
-    const R rx = mR * dx, ry = mR * dy;
-    b[4] -= mF + rx * dx;
-    b[5] -= mF + ry * dy;
-    b[6] -= mF + mR * dz * dz;
-    b[7] -= rx * dy;
-    b[8] -= rx * dz;
-    b[9] -= ry * dz;
-    if (JERK) {
-        const R dw = dx * wx + dy * wy + dz * wz;
-        b[10] += mF * wx + mR * dw * dx;
-        b[11] += mF * wy + mR * dw * dy;
-        b[12] += mF * wz + mR * dw * dz;
-    }
-}
-
-// Particle pair with softening test and self exclusion.
-template <typename R, bool JERK>
-__device__ __forceinline__ void ext_pair(R dx, R dy, R dz, R wx, R wy, R wz, R m, R hj, R ti,
-                                         bool self, R (&b)[kX]) {
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    const R ri = rsq(r2);
-    R F = ri * ri * ri, P = ri, FrR = R(-3) * F * ri * ri;
-    const R hh = hj > ti ? hj : ti;
-    if (r2 < hh * hh) {
-        R dFh, dPh;
-        dsoft<R>(r2, hh, F, P, FrR, dFh, dPh);
-    }
-    if (self) F = P = FrR = R(0);
-    ext_term<R, JERK>(dx, dy, dz, wx, wy, wz, m * F, m * FrR, m * P, b, true);
-}
 
 template <typename T>
 struct WalkArgsX {

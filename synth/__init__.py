@@ -13,6 +13,7 @@ from .clouds import (  # noqa: F401
     fractal_cloud,
     knn_radius,
     cotangents,
+    velocities,
     subsample,
     make_config,
     CONFIG_NAMES,

@@ -250,6 +250,12 @@ def cotangents(n, seed, dtype=np.float64):
     return ga.astype(dtype), gp.astype(dtype)
 
 
+def velocities(n, seed, dtype=np.float32):
+    """Particle velocities for the jerk: i.i.d. standard normal components."""
+    rng = np.random.default_rng([seed, 5])
+    return rng.standard_normal((n, 3)).astype(dtype)
+
+
 def subsample(n, k, seed):
     """k distinct target indices drawn uniformly from [0, n), sorted."""
     rng = np.random.default_rng([seed, 3])
