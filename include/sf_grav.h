@@ -169,6 +169,31 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  void *g_pos, void *g_mass, void *g_soft,
                                  void *stream);
 
+/* Accelerations and potentials with the symmetrised adaptive gas-gas
+ * softening of Sec. 2.2.1 (gas softening follows each cell's kernel radius
+ * H_i, with the symmetrisation and extra terms that keep momentum and energy
+ * conserved), on the handle's tree with the same opening decisions as
+ * sf_grav_accel.  Gas-gas pairs use the average of the two cells' softened
+ * kernels, F_ij = (F(r, h_i) + F(r, h_j))/2 (P likewise), and the
+ * acceleration of gas cell i gains
+ *     -(G/2) sum_j [z_i W_r(r, h_i) + (m_j/m_i) z_j W_r(r, h_j)] d / r,
+ * z = zeta/Omega, W the M4 cubic spline of support h normalised to 1, with
+ * n_i = sum_j W(r_ij, h_i) over gas cells (self included),
+ * zeta_i = (dh_i/dn_i) sum_{j != i} m_j dP(r_ij, h_i)/dh,
+ * Omega_i = 1 - (dh_i/dn_i) sum_j dW(r_ij, h_i)/dh and dh/dn = -h/(3 n):
+ * the force is then the exact gradient of the total potential energy when
+ * every kernel radius satisfies the neighbour-number constraint
+ * (4 pi/3) h_i^3 n_i = N_NGB (32 in Table 1).  The library does not solve
+ * for h: the handle's soft values of gas cells are taken as those radii.
+ * Gas-sink and sink-sink pairs keep the larger-radius rule (sink fields are
+ * those of sf_grav_accel).
+ * acc: n x 3 (required); pot: n; aux: n x 2 (Omega, zeta); caller order and
+ * dtype.  Three walks (the ordinary one, the neighbour sums, the forces),
+ * one lane per target in the last two.  Synchronises `stream`.
+ * Errors: as sf_grav_accel on a tree. */
+sf_status sf_grav_accel_adaptive(sf_grav_tree tree, const sf_grav_opts *o, void *acc, void *pot,
+                                 void *aux, void *stream);
+
 /* Tidal tensor T = -grad grad Phi and jerk j = da/dt of every particle,
  * computed in the same tree walk as its acceleration and potential (Sec.
  * 2.2: T and j are summed in the same pass as g, with the same opening

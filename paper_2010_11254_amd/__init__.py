@@ -10,6 +10,7 @@ from ._lib import (  # noqa: F401
     Tree,
     make_opts,
     sf_grav_accel,
+    sf_grav_accel_adaptive,
     sf_grav_accel_tidal,
     sf_grav_accel_backward,
     sf_grav_build_tree,

@@ -81,7 +81,8 @@ EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_tree_export", "sf_grav_get_timings", "sf_grav_strerror",
             "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
             "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
-            "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite")
+            "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite",
+            "sf_grav_accel_adaptive")
 
 
 def lib():
@@ -117,13 +118,15 @@ def lib():
     f64 = ctypes.c_double
     L.sf_grav_sinks.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp, vp]
     L.sf_grav_sink_hermite.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp]
+    L.sf_grav_accel_adaptive.argtypes = [vp, ctypes.POINTER(sf_grav_opts), vp, vp, vp, vp]
     L.sf_grav_accel_direct_noalloc.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(sf_grav_opts),
                                                vp, vp, vp]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
                  "sf_grav_tree_free", "sf_grav_get_tree_info", "sf_grav_tree_export",
                  "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
                  "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
-                 "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite"):
+                 "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite",
+                 "sf_grav_accel_adaptive"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -383,3 +386,17 @@ def sf_grav_sink_hermite(pos, vel, mass, soft, dt, G=1.0):
     st = lib().sf_grav_sink_hermite(_ptr(pos), _ptr(vel), _ptr(mass), _ptr(soft), pos.shape[0],
                                     float(G), float(dt), _stream())
     _check(st, "sf_grav_sink_hermite")
+
+
+def sf_grav_accel_adaptive(tree, opts, want_pot=True, want_aux=False):
+    """(acc, pot, aux) with the symmetrised adaptive gas-gas softening; aux =
+    (Omega, zeta) per particle (n, 2) when asked for."""
+    n, dtype = tree.n, tree.dtype
+    dev = torch.device("cuda", torch.cuda.current_device())
+    acc = torch.empty((n, 3), dtype=dtype, device=dev)
+    pot = torch.empty((n,), dtype=dtype, device=dev) if want_pot else None
+    aux = torch.zeros((n, 2), dtype=dtype, device=dev) if want_aux else None
+    st = lib().sf_grav_accel_adaptive(tree.handle, ctypes.byref(opts), _ptr(acc), _ptr(pot),
+                                      _ptr(aux), _stream())
+    _check(st, "sf_grav_accel_adaptive")
+    return acc, pot, aux

@@ -1,0 +1,427 @@
+// sf_adaptive.hip -- gas-gas pairs with the symmetrised adaptive softening of
+// Sec. 2.2.1 (gas softening follows each cell's kernel radius, with the
+// symmetrisation and extra terms that keep momentum and energy conserved),
+// on the tree of a handle.
+//
+// Gas-gas pairs use the average of the two cells' softened kernels,
+// F_ij = (F(r, h_i) + F(r, h_j)) / 2 and P_ij likewise, and the acceleration
+// of gas cell i gains
+//     -(G/2) sum_j [z_i W_r(r, h_i) + (m_j/m_i) z_j W_r(r, h_j)] d / r,
+// z = zeta / Omega, W the M4 cubic spline of support h normalised to 1,
+// W_r = dW/dr, with, for the number density n_i = sum_j W(r_ij, h_i) (self
+// included) of the constraint (4 pi/3) h_i^3 n_i = N_NGB:
+//     zeta_i  = (dh_i/dn_i) sum_{j != i} m_j dP(r_ij, h_i)/dh,
+//     Omega_i = 1 - (dh_i/dn_i) sum_j dW(r_ij, h_i)/dh,   dh/dn = -h/(3 n).
+// These terms make the force the exact gradient of the total potential
+// energy when every h_i follows the constraint (the caller's kernel radii
+// are taken to satisfy it).  Gas-sink and sink-sink pairs keep the
+// larger-radius rule.
+//
+// Two walks over the handle's groups with the same decisions as
+// sf_grav_accel: the first sums n, dW/dh and m dP/dh over each gas cell's
+// neighbours (only leaves that may hold softened pairs can hold them); the
+// second evaluates the forces with every source's z from the first.  One
+// lane per target; sinks get their fields from the ordinary walk.
+#include "sf_build.h"
+#include "sf_math.h"
+#include "sf_prims.h"
+#include "sf_walk.h"
+
+namespace sf {
+
+namespace {
+
+// M4 cubic spline normalised to 1 on a ball of radius h, for r < h: W, dW/dr
+// and dW/dh.
+template <typename R>
+__device__ __forceinline__ void m4(R r, R hinv, R &W, R &Wr, R &Wh) {
+    const R u = r * hinv;
+    const R om = R(1) - u;
+    const bool in = u < R(0.5);
+    const R k = in ? R(1) + u * u * (R(-6) + R(6) * u) : R(2) * om * om * om;
+    const R dk = in ? u * (R(-12) + R(18) * u) : R(-6) * om * om;
+    const R c = R(8.0 / 3.14159265358979323846) * hinv * hinv * hinv;
+    W = c * k;
+    Wr = c * hinv * dk;
+    Wh = -c * hinv * (R(3) * k + u * dk);
+}
+
+// F, P and dP/dh of the softened kernel with support h (Newtonian beyond).
+template <typename R>
+__device__ __forceinline__ void kern(R r2, R ri, R h, R &F, R &P, R &Ph) {
+    if (r2 < h * h) {
+        R FrR, dFh;
+        dsoft<R>(r2, h, F, P, FrR, dFh, Ph);
+    } else {
+        F = ri * ri * ri;
+        P = ri;
+        Ph = R(0);
+    }
+}
+
+template <typename T>
+struct AdArgs {
+    WalkNodes nd;
+    const T *xs, *ys, *zs, *ms, *hs;
+    const int32_t *order;
+    int64_t n, n_gas;
+    const int32_t *n_groups_dev, *gfirst, *gcount;
+    const double *gbox, *ghmax, *gcen;
+    int32_t *task_ctr, *err;
+    uint32_t *gstack;
+    double *z;                 // per sorted particle: zeta / Omega (0 for sinks)
+    T *acc, *pot, *aux;        // caller order; pot and aux (Omega, zeta) may be null
+    double G;
+};
+
+template <typename R> struct alignas(16) AdPart { R x, y, z, m, h, zz; int32_t idx, gas; };
+template <typename R> struct alignas(16) AdNode { R x, y, z, M, q[5]; };
+template <typename R> union AdStage {
+    AdPart<R> pp[64];
+    AdNode<R> nd[64];
+};
+
+// Pass 1: neighbour sums of every gas target.
+template <typename T, int FORM>
+struct SumsEval {
+    using R = typename FormT<FORM>::R;
+    const AdArgs<T> *a;
+    AdStage<R> *st;
+    double cen[3];
+    R tx, ty, tz, th, thinv;
+    int32_t tidx;
+    bool on;
+    R sW, sWh, sPh;
+
+    __device__ void pc_batch(WalkLds &, uint32_t, uint32_t) {}
+
+    template <bool SOFT>
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        if (!SOFT) return;   // leaves with Newtonian pairs only hold no neighbours
+        const uint32_t e = threadIdx.x;
+        if (e < nb) {
+            const int p = L.slot[e];
+            AdPart<R> s;
+            s.x = to_frame<FORM>(a->xs[p], cen[0]);
+            s.y = to_frame<FORM>(a->ys[p], cen[1]);
+            s.z = to_frame<FORM>(a->zs[p], cen[2]);
+            s.m = (R)a->ms[p];
+            s.h = s.zz = R(0);
+            s.idx = p;
+            s.gas = a->order[p] < a->n_gas ? 1 : 0;
+            st->pp[e] = s;
+        }
+        __syncthreads();
+        if (on)
+            for (uint32_t j = 0; j < nb; ++j) {
+                const AdPart<R> s = st->pp[j];
+                const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                if (!s.gas || !(r2 < th * th)) continue;
+                const R ri = rsq(r2);
+                const R r = r2 > R(0) ? r2 * ri : R(0);
+                R W, Wr, Wh;
+                m4<R>(r, thinv, W, Wr, Wh);
+                sW += W;
+                sWh += Wh;
+                if (s.idx != tidx) {
+                    R F, P, Ph;
+                    kern<R>(r2, ri, th, F, P, Ph);
+                    sPh += s.m * Ph;
+                }
+            }
+        __syncthreads();
+    }
+};
+
+// Pass 2: forces with the symmetrised gas-gas law.
+template <typename T, int FORM, int ORDER>
+struct ForceEval {
+    using R = typename FormT<FORM>::R;
+    const AdArgs<T> *a;
+    AdStage<R> *st;
+    double cen[3];
+    R tx, ty, tz, th, tm, tz_;   // tz_: the target's zeta / Omega
+    int32_t tidx;
+    bool on;
+    Acc<FORM> ax, ay, az, ap;
+
+    __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
+        const uint32_t e = threadIdx.x;
+        if (e < nb) {
+            const int node = L.pc[(head + e) & 127];
+            const WalkNodes &nd = a->nd;
+            AdNode<R> s;
+            s.x = dto_frame<FORM>(nd.w[node].com[0], cen[0]);
+            s.y = dto_frame<FORM>(nd.w[node].com[1], cen[1]);
+            s.z = dto_frame<FORM>(nd.w[node].com[2], cen[2]);
+            s.M = (R)nd.w[node].M;
+            for (int d = 0; d < 5; ++d) s.q[d] = ORDER == 2 ? (R)nd.q[node].q[d] : R(0);
+            st->nd[e] = s;
+        }
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        if (on)
+            for (uint32_t j = 0; j < nb; ++j) {
+                const AdNode<R> s = st->nd[j];
+                multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.q[0], s.q[1], s.q[2],
+                                    s.q[3], s.q[4], bx, by, bz, bp);
+            }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+
+    template <bool SOFT>
+    __device__ void pp_batch(WalkLds &L, uint32_t nb) {
+        const uint32_t e = threadIdx.x;
+        if (e < nb) {
+            const int p = L.slot[e];
+            AdPart<R> s;
+            s.x = to_frame<FORM>(a->xs[p], cen[0]);
+            s.y = to_frame<FORM>(a->ys[p], cen[1]);
+            s.z = to_frame<FORM>(a->zs[p], cen[2]);
+            s.m = (R)a->ms[p];
+            s.h = (R)a->hs[p];
+            s.zz = (R)a->z[p];
+            s.idx = p;
+            s.gas = a->order[p] < a->n_gas ? 1 : 0;
+            st->pp[e] = s;
+        }
+        __syncthreads();
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        if (on)
+            for (uint32_t j = 0; j < nb; ++j) {
+                const AdPart<R> s = st->pp[j];
+                const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsq(r2);
+                if (!SOFT) {   // both radii below r: Newtonian, no extra terms
+                    const R mri = s.m * ri, mri3 = mri * ri * ri;
+                    bp -= mri;
+                    bx += mri3 * dx;
+                    by += mri3 * dy;
+                    bz += mri3 * dz;
+                    continue;
+                }
+                if (s.idx == tidx) continue;
+                R F, P;
+                R c = R(0);   // extra term over r
+                if (s.gas) {
+                    R Fi, Pi, Phi, Fj, Pj, Phj;
+                    kern<R>(r2, ri, th, Fi, Pi, Phi);
+                    kern<R>(r2, ri, s.h, Fj, Pj, Phj);
+                    F = R(0.5) * (Fi + Fj);
+                    P = R(0.5) * (Pi + Pj);
+                    const R r = r2 > R(0) ? r2 * ri : R(0);
+                    if (r > R(0)) {
+                        R W, Wri, Wh, Wrj;
+                        Wri = Wrj = R(0);
+                        if (r < th) m4<R>(r, rcp(th), W, Wri, Wh);
+                        if (r < s.h) m4<R>(r, rcp(s.h), W, Wrj, Wh);
+                        c = R(0.5) * (tz_ * Wri + (s.m / tm) * s.zz * Wrj) * ri;
+                    }
+                } else {
+                    R Ph;
+                    kern<R>(r2, ri, th > s.h ? th : s.h, F, P, Ph);
+                }
+                const R k = s.m * F - c;
+                bx += k * dx;
+                by += k * dy;
+                bz += k * dz;
+                bp -= s.m * P;
+            }
+        ax.fold(bx);
+        ay.fold(by);
+        az.fold(bz);
+        ap.fold(bp);
+        __syncthreads();
+    }
+};
+
+template <typename T, class Ev>
+__device__ __forceinline__ bool group_target(const AdArgs<T> &a, Ev &ev, int g, int64_t &i,
+                                             double blo[3], double bhi[3]) {
+    using R = typename Ev::R;
+    const int lane = threadIdx.x;
+    const int64_t gf = a.gfirst[g], gc = a.gcount[g];
+    for (int d = 0; d < 3; ++d) {
+        blo[d] = a.gbox[6 * g + d];
+        bhi[d] = a.gbox[6 * g + 3 + d];
+        ev.cen[d] = a.gcen[3 * g + d];
+    }
+    i = gf + (lane < gc ? lane : 0);
+    ev.on = lane < gc && a.order[i] < a.n_gas;
+    if (__ballot(ev.on) == 0ull) return false;
+    ev.tx = (R)((double)a.xs[i] - (FormT<Ev::kForm>::rel ? ev.cen[0] : 0.0));
+    ev.ty = (R)((double)a.ys[i] - (FormT<Ev::kForm>::rel ? ev.cen[1] : 0.0));
+    ev.tz = (R)((double)a.zs[i] - (FormT<Ev::kForm>::rel ? ev.cen[2] : 0.0));
+    ev.th = (R)a.hs[i];
+    ev.tidx = (int32_t)i;
+    return true;
+}
+
+template <typename T, int FORM>
+struct SumsEvalF : SumsEval<T, FORM> {
+    static constexpr int kForm = FORM;
+};
+template <typename T, int FORM, int ORDER>
+struct ForceEvalF : ForceEval<T, FORM, ORDER> {
+    static constexpr int kForm = FORM;
+};
+
+template <typename T, int FORM>
+__global__ __launch_bounds__(64) void k_adaptive_sums(AdArgs<T> a) {
+    using R = typename FormT<FORM>::R;
+    __shared__ WalkLds L;
+    __shared__ AdStage<R> stage;
+    const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
+    SumsEvalF<T, FORM> ev;
+    ev.a = &a;
+    ev.st = &stage;
+    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+        int64_t i;
+        double blo[3], bhi[3];
+        if (!group_target(a, ev, g, i, blo, bhi)) continue;
+        ev.thinv = rcp(ev.th);
+        ev.sW = ev.sWh = ev.sPh = R(0);
+        uint32_t npc, npp;
+        uint64_t cks;
+        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
+                         a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
+                         task_ag_group(a.nd, g), a.err, npc, npp, cks);
+        if (ev.on) {
+            const double h = (double)a.hs[i];
+            const double n = (double)ev.sW;
+            const double dhdn = -h / (3.0 * n);
+            const double omega = 1.0 - dhdn * (double)ev.sWh;
+            const double zeta = dhdn * (double)ev.sPh;
+            a.z[i] = zeta / omega;
+            if (a.aux) {
+                const int64_t o = a.order[i];
+                a.aux[2 * o] = (T)omega;
+                a.aux[2 * o + 1] = (T)zeta;
+            }
+        }
+    }
+}
+
+template <typename T, int FORM, int ORDER>
+__global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
+    using R = typename FormT<FORM>::R;
+    __shared__ WalkLds L;
+    __shared__ AdStage<R> stage;
+    const int ng = __builtin_amdgcn_readfirstlane(*a.n_groups_dev);
+    ForceEvalF<T, FORM, ORDER> ev;
+    ev.a = &a;
+    ev.st = &stage;
+    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+        int64_t i;
+        double blo[3], bhi[3];
+        if (!group_target(a, ev, g, i, blo, bhi)) continue;
+        ev.tm = (R)a.ms[i];
+        ev.tz_ = (R)a.z[i];
+        ev.ax.zero();
+        ev.ay.zero();
+        ev.az.zero();
+        ev.ap.zero();
+        uint32_t npc, npp;
+        uint64_t cks;
+        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
+                         a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
+                         task_ag_group(a.nd, g), a.err, npc, npp, cks);
+        if (ev.on) {
+            const int64_t o = a.order[i];
+            a.acc[3 * o] = (T)(a.G * ev.ax.value());
+            a.acc[3 * o + 1] = (T)(a.G * ev.ay.value());
+            a.acc[3 * o + 2] = (T)(a.G * ev.az.value());
+            if (a.pot) a.pot[o] = (T)(a.G * ev.ap.value());
+        }
+    }
+}
+
+template <typename T, int FORM, int ORDER>
+void launch_ad(const AdArgs<T> &a1, const AdArgs<T> &a2, hipStream_t s) {
+    const unsigned grid = (unsigned)walk_grid();
+    hipLaunchKernelGGL((k_adaptive_sums<T, FORM>), dim3(grid), dim3(64), 0, s, a1);
+    hipLaunchKernelGGL((k_adaptive_force<T, FORM, ORDER>), dim3(grid), dim3(64), 0, s, a2);
+}
+
+template <typename T>
+sf_status adaptive_run(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, void *aux,
+                       DevArena &ar) {
+    hipStream_t s = t->stream;
+    // the ordinary walk first: sinks keep its fields, gas cells are rewritten
+    sf_status st = tree_accel(t, o, acc, pot, ar);
+    if (st != SF_OK) return st;
+    int32_t *ctr;
+    uint32_t *gstack;
+    double *z;
+    SF_ALLOC_TMP(ar, ctr, 2 * kCtrWords);
+    SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
+    SF_ALLOC_TMP(ar, z, t->n);
+    FillRanges zero;
+    zero.add(ctr, 2 * kCtrWords);
+    zero.add(z, 2 * t->n);
+    fill_ranges_u32(zero, 0u, s);
+    AdArgs<T> a{};
+    a.nd.n_nodes = t->n_nodes;
+    a.nd.w = t->nw[0];
+    a.nd.q = t->nq[0];
+    a.nd.side = t->hframe.side;
+    a.nd.th2 = o.theta * o.theta;
+    set_relative(a.nd, t, o);
+    a.xs = (const T *)t->xs;
+    a.ys = (const T *)t->ys;
+    a.zs = (const T *)t->zs;
+    a.ms = (const T *)t->ms;
+    a.hs = (const T *)t->hs;
+    a.order = t->order;
+    a.n = t->n;
+    a.n_gas = t->n_gas;
+    a.n_groups_dev = t->n_groups_dev;
+    a.gfirst = t->gfirst;
+    a.gcount = t->gcount;
+    a.gbox = t->gbox;
+    a.ghmax = t->ghmax;
+    a.gcen = t->gcen;
+    a.gstack = gstack;
+    a.z = z;
+    a.acc = (T *)acc;
+    a.pot = (T *)pot;
+    a.aux = (T *)aux;
+    a.G = o.G;
+    AdArgs<T> a1 = a, a2 = a;
+    a1.task_ctr = ctr;
+    a1.err = ctr + kCtrErr;
+    a2.task_ctr = ctr + kCtrWords;
+    a2.err = ctr + kCtrErr;
+    if (o.order == 0) {
+        if (o.form == SF_FP32C) launch_ad<T, SF_FP32C, 0>(a1, a2, s);
+        else if (o.form == SF_FP32) launch_ad<T, SF_FP32, 0>(a1, a2, s);
+        else launch_ad<T, SF_FP64, 0>(a1, a2, s);
+    } else {
+        if (o.form == SF_FP32C) launch_ad<T, SF_FP32C, 2>(a1, a2, s);
+        else if (o.form == SF_FP32) launch_ad<T, SF_FP32, 2>(a1, a2, s);
+        else launch_ad<T, SF_FP64, 2>(a1, a2, s);
+    }
+    SF_HIP(hipGetLastError());
+    int32_t herr = 0;
+    SF_HIP(hipMemcpyAsync(&herr, ctr + kCtrErr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipStreamSynchronize(s));
+    if (herr)
+        return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);
+    return SF_OK;
+}
+
+}  // namespace
+
+sf_status adaptive_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, void *aux,
+                         DevArena &ar) {
+    if (t->dt == SF_F32) return adaptive_run<float>(t, o, acc, pot, aux, ar);
+    return adaptive_run<double>(t, o, acc, pot, aux, ar);
+}
+
+}  // namespace sf

@@ -689,6 +689,24 @@ sf_status sf_grav_accel_tidal(sf_grav_tree tree, const void *vel, const sf_grav_
     return sf::tidal_accel(tree, e, jerk ? vel : nullptr, acc, pot, tidal, jerk, ar);
 }
 
+sf_status sf_grav_accel_adaptive(sf_grav_tree tree, const sf_grav_opts *o, void *acc, void *pot,
+                                 void *aux, void *stream) {
+    g_msg[0] = 0;
+    if (!tree) return sf_fail(SF_E_INVALID, "tree is NULL");
+    if (!acc) return sf_fail(SF_E_INVALID, "acc is NULL");
+    sf_status st = check_opts(o, tree->n, false);
+    if (st != SF_OK) return st;
+    if (tree->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    st = check_field(tree, o);
+    if (st != SF_OK) return st;
+    sf::fail_alloc_arm();
+    sf::EvalOpts e;
+    eval_opts(o, e);
+    tree->stream = (hipStream_t)stream;
+    DevArena ar(tree->stream);
+    return sf::adaptive_accel(tree, e, acc, pot, aux, ar);
+}
+
 sf_status sf_grav_tree_set_field(sf_grav_tree t, const void *acc_prev, void *stream) {
     g_msg[0] = 0;
     if (!t || !acc_prev) return sf_fail(SF_E_INVALID, "NULL argument");

@@ -109,6 +109,10 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
 // jerk is NULL; pot/tid may be NULL.
 sf_status tidal_accel(sf_grav_tree_s *t, const EvalOpts &o, const void *vel, void *acc, void *pot,
                       void *tid, void *jerk, DevArena &ar);
+// Symmetrised adaptive gas-gas softening (two walks after the ordinary one);
+// aux (Omega, zeta per particle, caller order) may be NULL.
+sf_status adaptive_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, void *aux,
+                         DevArena &ar);
 // A11: direct path on a handle built with type-major keys (no topology).
 sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
 // Bytes of one packed source record of the direct path in form `form`.
