@@ -169,6 +169,30 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
                                  void *g_pos, void *g_mass, void *g_soft,
                                  void *stream);
 
+/* Radiation sums that ride on the gravity walk, for gas cells (sinks get
+ * zeros), with the opening decisions of sf_grav_accel:
+ *   column: n x 6, the gas column density averaged over each of six
+ *     angular bins around the cell (Sec. 3.1: FUV optical depths summed into
+ *     angular bins during the gravity pass, 6 bins by default; the optical
+ *     depth of a bin is kappa_FUV times its column).  The bins are the faces
+ *     of a cube: a direction d = x_source - x_cell belongs to the face of its
+ *     largest |d_k| (ties to the lower axis), in the order +x -x +y -y +z -z,
+ *     each spanning 4 pi/6 sr; a bin holds sum m / (Omega_bin r^2), the
+ *     column density averaged over its solid angle, a gas particle with r^2
+ *     softened to r^2 + (h/2.8)^2, an accepted node as its gas mass at its gas
+ *     centre of mass;
+ *   e_ir: n, the IR energy density from stars (Sec. 3.3),
+ *     sum_s L_s / (4 pi c r^2) over sinks, r^2 softened to r^2 + (h_s/2.8)^2,
+ *     an accepted node as its total sink luminosity at the luminosity centre.
+ * lum: n luminosities in caller order (only sink entries are read; NULL:
+ * no stars); c_light: the speed of light in the caller's units (> 0, used
+ * for e_ir).  Either output may be NULL (not both).  One lane per gas
+ * target.  Synchronises `stream`.
+ * Errors: SF_E_INVALID (NULL tree, both outputs NULL, c_light <= 0 with
+ * e_ir, bad options), SF_E_STATE, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */
+sf_status sf_grav_rad_sums(sf_grav_tree tree, const void *lum, double c_light,
+                           const sf_grav_opts *o, void *column, void *e_ir, void *stream);
+
 /* Accelerations and potentials with the symmetrised adaptive gas-gas
  * softening of Sec. 2.2.1 (gas softening follows each cell's kernel radius
  * H_i, with the symmetrisation and extra terms that keep momentum and energy

@@ -49,7 +49,8 @@ def timesteps(x, v, m, h, eta, G=1.0):
     """(dt_2body, dt_tidal) of every sink: sqrt(eta) / (1/t_c + 1/t_dyn) and
     sqrt(eta) (|T|_F^2 / 6)^(-1/4), T from the sinks-only pass."""
     tc, td = two_body_times(x, v, m, h, G)
-    dt2 = np.sqrt(eta) / (1.0 / tc + 1.0 / td)
+    with np.errstate(divide="ignore"):   # a lone sink: infinite time scales
+        dt2 = np.sqrt(eta) / (1.0 / tc + 1.0 / td)
     _, _, T = sinks_pass(x, v, m, h, G)
     fro2 = (T[:, :3] ** 2).sum(1) + 2.0 * (T[:, 3:] ** 2).sum(1)
     with np.errstate(divide="ignore"):

@@ -17,6 +17,7 @@ from ._lib import (  # noqa: F401
     sf_grav_get_stats,
     sf_grav_get_timings,
     sf_grav_get_tree_info,
+    sf_grav_rad_sums,
     sf_grav_release_cache,
     sf_grav_sink_hermite,
     sf_grav_sinks,

@@ -82,7 +82,7 @@ EXPORTED = ("sf_grav_opts_default", "sf_grav_build_tree", "sf_grav_accel",
             "sf_grav_last_error", "sf_grav_tree_set_field", "sf_grav_tree_refit",
             "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
             "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite",
-            "sf_grav_accel_adaptive")
+            "sf_grav_accel_adaptive", "sf_grav_rad_sums")
 
 
 def lib():
@@ -119,6 +119,7 @@ def lib():
     L.sf_grav_sinks.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp, vp]
     L.sf_grav_sink_hermite.argtypes = [vp, vp, vp, vp, i64, f64, f64, vp]
     L.sf_grav_accel_adaptive.argtypes = [vp, ctypes.POINTER(sf_grav_opts), vp, vp, vp, vp]
+    L.sf_grav_rad_sums.argtypes = [vp, vp, f64, ctypes.POINTER(sf_grav_opts), vp, vp, vp]
     L.sf_grav_accel_direct_noalloc.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(sf_grav_opts),
                                                vp, vp, vp]
     for name in ("sf_grav_build_tree", "sf_grav_accel", "sf_grav_accel_backward",
@@ -126,7 +127,7 @@ def lib():
                  "sf_grav_get_timings", "sf_grav_tree_set_field", "sf_grav_tree_refit",
                  "sf_grav_get_stats", "sf_grav_release_cache", "sf_grav_accel_direct_noalloc",
                  "sf_grav_accel_tidal", "sf_grav_sinks", "sf_grav_sink_hermite",
-                 "sf_grav_accel_adaptive"):
+                 "sf_grav_accel_adaptive", "sf_grav_rad_sums"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -400,3 +401,17 @@ def sf_grav_accel_adaptive(tree, opts, want_pot=True, want_aux=False):
                                       _ptr(aux), _stream())
     _check(st, "sf_grav_accel_adaptive")
     return acc, pot, aux
+
+
+def sf_grav_rad_sums(tree, opts, lum=None, c_light=1.0, want_column=True, want_e_ir=True):
+    """(column (n, 6), e_ir (n,)) of the gas cells from one tree walk."""
+    n, dtype = tree.n, tree.dtype
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if lum is not None and (lum.shape != (n,) or lum.dtype != dtype or not lum.is_cuda):
+        raise ValueError("lum must be an (n,) GPU tensor in the handle's dtype")
+    col = torch.zeros((n, 6), dtype=dtype, device=dev) if want_column else None
+    eir = torch.zeros((n,), dtype=dtype, device=dev) if want_e_ir else None
+    st = lib().sf_grav_rad_sums(tree.handle, _ptr(lum), float(c_light), ctypes.byref(opts),
+                                _ptr(col), _ptr(eir), _stream())
+    _check(st, "sf_grav_rad_sums")
+    return col, eir

@@ -707,6 +707,25 @@ sf_status sf_grav_accel_adaptive(sf_grav_tree tree, const sf_grav_opts *o, void 
     return sf::adaptive_accel(tree, e, acc, pot, aux, ar);
 }
 
+sf_status sf_grav_rad_sums(sf_grav_tree tree, const void *lum, double c_light,
+                           const sf_grav_opts *o, void *column, void *e_ir, void *stream) {
+    g_msg[0] = 0;
+    if (!tree) return sf_fail(SF_E_INVALID, "tree is NULL");
+    if (!column && !e_ir) return sf_fail(SF_E_INVALID, "column and e_ir are both NULL");
+    if (e_ir && !(c_light > 0.0)) return sf_fail(SF_E_INVALID, "c_light must be > 0");
+    sf_status st = check_opts(o, tree->n, false);
+    if (st != SF_OK) return st;
+    if (tree->direct_only) return sf_fail(SF_E_STATE, "handle has no tree");
+    st = check_field(tree, o);
+    if (st != SF_OK) return st;
+    sf::fail_alloc_arm();
+    sf::EvalOpts e;
+    eval_opts(o, e);
+    tree->stream = (hipStream_t)stream;
+    DevArena ar(tree->stream);
+    return sf::rad_sums(tree, e, lum, c_light > 0.0 ? c_light : 1.0, column, e_ir, ar);
+}
+
 sf_status sf_grav_tree_set_field(sf_grav_tree t, const void *acc_prev, void *stream) {
     g_msg[0] = 0;
     if (!t || !acc_prev) return sf_fail(SF_E_INVALID, "NULL argument");

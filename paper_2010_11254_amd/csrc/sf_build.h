@@ -113,6 +113,10 @@ sf_status tidal_accel(sf_grav_tree_s *t, const EvalOpts &o, const void *vel, voi
 // aux (Omega, zeta per particle, caller order) may be NULL.
 sf_status adaptive_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, void *aux,
                          DevArena &ar);
+// Tree-pass radiation sums for gas cells: 6-bin column densities and the IR
+// energy density of the sinks' luminosities (lum may be NULL: no stars).
+sf_status rad_sums(sf_grav_tree_s *t, const EvalOpts &o, const void *lum, double c_light,
+                   void *col, void *eir, DevArena &ar);
 // A11: direct path on a handle built with type-major keys (no topology).
 sf_status direct_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
 // Bytes of one packed source record of the direct path in form `form`.
