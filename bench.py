@@ -19,6 +19,10 @@ Reported beside it:
   * the adjoint against the force evaluation on one handle (precision4m,
     diff256k, fractal16m);
   * the direct path in FP32C, plain FP32 and FP64, one evaluation each;
+  * the other evaluations on a precision4m handle: tidal tensor and jerk
+    (with their error on an oracle sample), the symmetrised adaptive gas
+    softening, the 6-bin columns and IR energy density, and the sinks-only
+    pass and Hermite step on the 4096 sinks;
   * uniform4k (4096 particles, FP64, monopole) and clustered1m (2^20 gas +
     256 sinks) tree errors and times; fractal16m (2^24 gas + 10^4 sinks)
     forward and backward at theta 0.5 and 0.7;
@@ -280,6 +284,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline FP32C steps (profiling runs)")
     ap.add_argument("--no-fractal", action="store_true", help="skip the 16M fractal workload")
+    ap.add_argument("--with-adjoint", action="store_true",
+                    help="with --headline-only: one FP32C adjoint on a headline handle (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
     ap.add_argument("--leaf-cap", type=int, default=32)
@@ -350,7 +356,7 @@ def main():
     log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
         + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
 
-    res, adj, direct, tidal = {}, {}, {}, {}
+    res, adj, direct, tidal, extra = {}, {}, {}, {}, {}
     if not args.headline_only:
         # theta only (no relative criterion), and the FP64 / plain FP32 forms
         k2 = max(2, args.steps // 3)
@@ -394,7 +400,34 @@ def main():
         tidal = {"accel_ms": fwd, "tidal_jerk_ms": tms, "ratio": tms / fwd, "form": "fp32c",
                  "alpha": alpha}
         log(f"tidal+jerk fp32c: {tms:.2f} ms against accel {fwd:.2f} ms ({tms / fwd:.2f}x)")
-        del vel, tid, jerk
+        del tid, jerk
+
+        # the other tree-pass evaluations on the same handle (times only:
+        # their parity is in the tests): symmetrised adaptive gas softening
+        # (softening here is the 32-NN radius, not re-solved) and the
+        # radiation sums (6-bin columns, IR energy density of the sinks)
+        t, o = head.handle()
+        lum = torch.zeros(ps.n, dtype=torch.float32, device=g.dev)
+        lum[ps.n_gas:] = torch.exp(torch.randn(ps.n_sink, generator=torch.Generator().manual_seed(2))).to(g.dev)
+        extra["adaptive_softening_ms"] = g.event_ms(lambda: L.sf_grav_accel_adaptive(t, o), 2)
+        extra["rad_sums_ms"] = g.event_ms(lambda: L.sf_grav_rad_sums(t, o, lum=lum, c_light=1.0), 3)
+        extra["accel_ms"] = fwd
+        L.sf_grav_tree_free(t)
+        log(f"adaptive softening {extra['adaptive_softening_ms']:.2f} ms, radiation sums "
+            f"{extra['rad_sums_ms']:.2f} ms (accel {fwd:.2f} ms)")
+        # sink dynamics on the workload's 4096 sinks (FP64): sinks-only pass
+        # with time scales, and one modified Hermite step
+        sl = slice(ps.n_gas, ps.n)
+        sx, sm_, sh = (torch.as_tensor(np.ascontiguousarray(v[sl], dtype=np.float64)).to(g.dev)
+                       for v in (ps.x, ps.m, ps.h))
+        sv = vel[ps.n_gas:].double().contiguous()
+        extra["sinks_pass_ms"] = g.event_ms(lambda: L.sf_grav_sinks(sx, sv, sm_, sh, eta=0.01), 5)
+        extra["sink_hermite_step_ms"] = g.event_ms(
+            lambda: L.sf_grav_sink_hermite(sx, sv, sm_, sh, 1e-9), 5)
+        extra["n_sink"] = ps.n_sink
+        log(f"sinks pass {extra['sinks_pass_ms']:.3f} ms, Hermite step "
+            f"{extra['sink_hermite_step_ms']:.3f} ms ({ps.n_sink} sinks)")
+        del vel, lum, sx, sm_, sh, sv
 
         # direct path: one evaluation per form over all pairs
         pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
@@ -421,6 +454,13 @@ def main():
                 direct[form]["frac_nonpacked"] = tf / PEAK_FP32_NONPACKED_TFLOPS
             log(f"direct {form}: {ms:.1f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, {tf:.1f} TFLOP/s")
         direct["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+    if args.headline_only and args.with_adjoint:
+        ga, gp = (torch.as_tensor(v).to(g.dev) for v in cotangents(ps.n, seed=2, dtype=np.float32))
+        t, o = head.handle()
+        bwd = g.event_ms(lambda: L.sf_grav_accel_backward(t, None, None, None, o, ga, gp), 1)
+        L.sf_grav_tree_free(t)
+        adj["fp32c"] = {"backward_ms": bwd}
+        log(f"adjoint fp32c: backward {bwd:.2f} ms")
     del x, m, h, head
     torch.cuda.empty_cache()
 
@@ -558,6 +598,8 @@ def main():
         line["direct"] = direct
     if tidal:
         line["tidal_jerk"] = tidal
+    if extra:
+        line["tree_pass_extras"] = extra
     line.update(others)
     if errs:
         line["rel_err"] = errs
