@@ -57,18 +57,35 @@ def _pick_groups(groups, sink_sorted, k_rand, k_sink, seed):
     return sorted(sel)
 
 
-def _tree_sampled(ps, k_rand, k_sink, seed):
+def _sampled_field(ps, x64, m64, h64, tgt, seed):
+    """Previous field for the relative criterion: the oracle's exact direct
+    field on the sampled targets (so their groups' g_min has its true size),
+    seeded Gaussian vectors of the same median magnitude elsewhere.  Rounded
+    to FP32 so that both handles and the oracle see the same values."""
+    f_t, _ = odirect.direct(x64, m64, h64, targets=tgt)
+    rng = np.random.default_rng([seed, 77])
+    field = rng.standard_normal((ps.n, 3))
+    field *= np.median(np.linalg.norm(f_t, axis=1)) / np.sqrt(3.0)
+    field[tgt] = f_t
+    return field.astype(np.float32).astype(np.float64)
+
+
+def _tree_sampled(ps, k_rand, k_sink, seed, alpha=None):
     """GPU tree (FP64 form on FP64 copies of the inputs, FP32C on the FP32
-    inputs) against the oracle's frozen-list evaluation of sampled groups."""
+    inputs) against the oracle's frozen-list evaluation of sampled groups;
+    with `alpha` the relative opening criterion is on, driven by the field of
+    `_sampled_field` on both sides."""
     L = _lib()
     x64, m64, h64 = (v.astype(np.float64) for v in (ps.x, ps.m, ps.h))
-    _say("oracle tree lists", ps.n)
+    _say("oracle tree lists", ps.n, "alpha", alpha)
     tree = otree.build_tree(x64, LEAF)
     groups = otree.make_groups(tree, GROUP)
     sink_sorted = (tree.order >= ps.n_gas)
     sel = _pick_groups(groups, sink_sorted, k_rand, k_sink, seed)
-    lists = otree.tree_lists(x64, m64, h64, ps.n_gas, 0.5, LEAF, GROUP, groups_sel=sel, lazy=True)
     tgt = np.concatenate([tree.order[groups[g, 0]:groups[g, 0] + groups[g, 1]] for g in sel])
+    field = None if alpha is None else _sampled_field(ps, x64, m64, h64, tgt, seed)
+    lists = otree.tree_lists(x64, m64, h64, ps.n_gas, 0.5, LEAF, GROUP, groups_sel=sel, lazy=True,
+                             alpha=alpha, field=field)
     t64 = lambda v: torch.as_tensor(v)
     with torch.no_grad():
         ar, pr = otree.tree_eval(t64(x64), t64(m64), t64(h64), ps.n_gas, lists, 1.0, 2, targets=tgt)
@@ -78,8 +95,10 @@ def _tree_sampled(ps, k_rand, k_sink, seed):
         _say("gpu tree", form, ps.n)
         x, m, h = _dev(*arrs)
         o = L.make_opts(form=form, n_gas=ps.n_gas, collect_stats=True, leaf_cap=LEAF,
-                        group_cap=GROUP)
+                        group_cap=GROUP, alpha=alpha)
         t = L.sf_grav_build_tree(x, m, h, o)
+        if alpha is not None:
+            L.sf_grav_tree_set_field(t, _dev(field.astype(arrs[0].dtype))[0])
         a, p = L.sf_grav_accel(t, None, None, None, o)
         torch.cuda.synchronize()
         npc = L.sf_grav_tree_export(t, "group_npc").numpy()
@@ -93,7 +112,7 @@ def _tree_sampled(ps, k_rand, k_sink, seed):
     assert np.max(np.abs(out["fp64"][1] - pr) / np.abs(pr)) < 1e-10
     e32 = _relerr(out["fp32c"][0], ar)
     assert np.median(e32) < 2e-6 and np.quantile(e32, 0.99) < 2e-5, (np.median(e32), e32.max())
-    return tgt.size
+    return tgt.size, lists, sel
 
 
 def _direct_sampled(ps, k, seed):
@@ -142,7 +161,19 @@ def test_precision4m_build_bit_exact(c2):
 
 def test_precision4m_tree_sampled_groups(c2):
     _say("precision4m tree, sampled groups")
-    assert _tree_sampled(c2, k_rand=6, k_sink=4, seed=2) > 100
+    assert _tree_sampled(c2, k_rand=16, k_sink=8, seed=2)[0] > 400
+
+
+def test_precision4m_tree_sampled_groups_relative(c2):
+    """The benchmark's opening rule: theta 0.5 with the relative criterion at
+    alpha = 0.003; the criterion must actually open nodes here."""
+    _say("precision4m tree relative, sampled groups")
+    n_t, rel, sel = _tree_sampled(c2, k_rand=16, k_sink=8, seed=12, alpha=0.003)
+    assert n_t > 400
+    x64, m64, h64 = (v.astype(np.float64) for v in (c2.x, c2.m, c2.h))
+    ang = otree.tree_lists(x64, m64, h64, c2.n_gas, 0.5, LEAF, GROUP, groups_sel=sel, lazy=True)
+    work = lambda ls: sum(pc.size + pp.size for pc, pp in ls.gas_lists.values())
+    assert work(rel) > work(ang), (work(rel), work(ang))
 
 
 def test_precision4m_direct_sampled(c2):
@@ -154,7 +185,12 @@ def test_precision4m_direct_sampled(c2):
 
 def test_clustered1m_tree_sampled_groups(c1):
     _say("clustered1m tree, sampled groups")
-    assert _tree_sampled(c1, k_rand=6, k_sink=3, seed=1) > 100
+    assert _tree_sampled(c1, k_rand=16, k_sink=6, seed=1)[0] > 400
+
+
+def test_clustered1m_tree_sampled_groups_relative(c1):
+    _say("clustered1m tree relative, sampled groups")
+    assert _tree_sampled(c1, k_rand=16, k_sink=6, seed=11, alpha=0.003)[0] > 400
 
 
 def test_clustered1m_direct_sampled(c1):
