@@ -186,8 +186,9 @@ sf_status sf_grav_accel_backward(sf_grav_tree tree, const void *pos,
  *     an accepted node as its total sink luminosity at the luminosity centre.
  * lum: n luminosities in caller order (only sink entries are read; NULL:
  * no stars); c_light: the speed of light in the caller's units (> 0, used
- * for e_ir).  Either output may be NULL (not both).  One lane per gas
- * target.  Synchronises `stream`.
+ * for e_ir).  Either output may be NULL (not both).  A group's targets
+ * share the wave's lanes, floor(64 / group size) lanes each.  Synchronises
+ * `stream`.
  * Errors: SF_E_INVALID (NULL tree, both outputs NULL, c_light <= 0 with
  * e_ir, bad options), SF_E_STATE, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */
 sf_status sf_grav_rad_sums(sf_grav_tree tree, const void *lum, double c_light,
@@ -212,8 +213,9 @@ sf_status sf_grav_rad_sums(sf_grav_tree tree, const void *lum, double c_light,
  * Gas-sink and sink-sink pairs keep the larger-radius rule (sink fields are
  * those of sf_grav_accel).
  * acc: n x 3 (required); pot: n; aux: n x 2 (Omega, zeta); caller order and
- * dtype.  Three walks (the ordinary one, the neighbour sums, the forces),
- * one lane per target in the last two.  Synchronises `stream`.
+ * dtype.  The sink walk of sf_grav_accel, then two group walks (the
+ * neighbour sums, the forces).  opts.collect_stats records nothing here.
+ * Synchronises `stream`.
  * Errors: as sf_grav_accel on a tree. */
 sf_status sf_grav_accel_adaptive(sf_grav_tree tree, const sf_grav_opts *o, void *acc, void *pot,
                                  void *aux, void *stream);
@@ -234,8 +236,8 @@ sf_status sf_grav_accel_adaptive(sf_grav_tree tree, const sf_grav_opts *o, void 
  * vel:  n x 3 velocities, caller order, handle dtype; needed only for jerk.
  * acc:  n x 3 (required); pot: n; tidal: n x 6 as xx yy zz xy xz yz;
  *   jerk: n x 3 -- each optional except acc, caller order and dtype.
- * One lane per target (this evaluation does not split targets over lanes),
- * arithmetic in opts.form, node velocities as FP64 mass-weighted means.
+ * A group's targets share the wave's lanes, floor(64 / group size) lanes
+ * each; arithmetic in opts.form, node velocities as FP64 mass-weighted means.
  * Synchronises `stream` once (capacity-guard flag).
  * Errors: SF_E_INVALID (NULL acc, jerk without vel, bad options),
  * SF_E_STATE, SF_E_UNSUPPORTED, SF_E_NOMEM, SF_E_DEVICE, SF_E_INTERNAL. */

@@ -20,11 +20,13 @@
 // Two walks over the handle's groups with the same decisions as
 // sf_grav_accel: the first sums n, dW/dh and m dP/dh over each gas cell's
 // neighbours (only leaves that may hold softened pairs can hold them); the
-// second evaluates the forces with every source's z from the first.  One
-// lane per target; sinks get their fields from the ordinary walk.
+// second evaluates the forces with every source's z from the first.  Each
+// target holds floor(64 / gc) lanes that share its batch entries (lane
+// splitting); sinks get their fields from the sink walk of sf_grav_accel.
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_split.h"
 #include "sf_walk.h"
 
 namespace sf {
@@ -80,6 +82,8 @@ template <typename R> union AdStage {
     AdPart<R> pp[64];
     AdNode<R> nd[64];
 };
+// the copies' partial sums (up to 4 per lane) go through the stage
+static_assert(sizeof(AdStage<float>) >= 4 * 64 * sizeof(double), "stage too small for the sums");
 
 // Pass 1: neighbour sums of every gas target.
 template <typename T, int FORM>
@@ -91,6 +95,7 @@ struct SumsEval {
     R tx, ty, tz, th, thinv;
     int32_t tidx;
     bool on;
+    Split sp;
     R sW, sWh, sPh;
 
     __device__ void pc_batch(WalkLds &, uint32_t, uint32_t) {}
@@ -113,11 +118,11 @@ struct SumsEval {
         }
         __syncthreads();
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const AdPart<R> s = st->pp[j];
                 const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                if (!s.gas || !(r2 < th * th)) continue;
+                if (!s.gas || !(r2 < th * th)) return;
                 const R ri = rsq(r2);
                 const R r = r2 > R(0) ? r2 * ri : R(0);
                 R W, Wr, Wh;
@@ -129,7 +134,7 @@ struct SumsEval {
                     kern<R>(r2, ri, th, F, P, Ph);
                     sPh += s.m * Ph;
                 }
-            }
+            });
         __syncthreads();
     }
 };
@@ -144,6 +149,7 @@ struct ForceEval {
     R tx, ty, tz, th, tm, tz_;   // tz_: the target's zeta / Omega
     int32_t tidx;
     bool on;
+    Split sp;
     Acc<FORM> ax, ay, az, ap;
 
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
@@ -162,11 +168,11 @@ struct ForceEval {
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const AdNode<R> s = st->nd[j];
                 multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.q[0], s.q[1], s.q[2],
                                     s.q[3], s.q[4], bx, by, bz, bp);
-            }
+            });
         ax.fold(bx);
         ay.fold(by);
         az.fold(bz);
@@ -193,7 +199,7 @@ struct ForceEval {
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const AdPart<R> s = st->pp[j];
                 const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
                 const R r2 = dx * dx + dy * dy + dz * dz;
@@ -204,9 +210,9 @@ struct ForceEval {
                     bx += mri3 * dx;
                     by += mri3 * dy;
                     bz += mri3 * dz;
-                    continue;
+                    return;
                 }
-                if (s.idx == tidx) continue;
+                if (s.idx == tidx) return;
                 R F, P;
                 R c = R(0);   // extra term over r
                 if (s.gas) {
@@ -232,7 +238,7 @@ struct ForceEval {
                 by += k * dy;
                 bz += k * dz;
                 bp -= s.m * P;
-            }
+            });
         ax.fold(bx);
         ay.fold(by);
         az.fold(bz);
@@ -252,8 +258,9 @@ __device__ __forceinline__ bool group_target(const AdArgs<T> &a, Ev &ev, int g, 
         bhi[d] = a.gbox[6 * g + 3 + d];
         ev.cen[d] = a.gcen[3 * g + d];
     }
-    i = gf + (lane < gc ? lane : 0);
-    ev.on = lane < gc && a.order[i] < a.n_gas;
+    ev.sp.init((uint32_t)gc, (uint32_t)lane);
+    i = gf + ev.sp.tl;
+    ev.on = a.order[i] < a.n_gas;
     if (__ballot(ev.on) == 0ull) return false;
     ev.tx = (R)((double)a.xs[i] - (FormT<Ev::kForm>::rel ? ev.cen[0] : 0.0));
     ev.ty = (R)((double)a.ys[i] - (FormT<Ev::kForm>::rel ? ev.cen[1] : 0.0));
@@ -292,12 +299,14 @@ __global__ __launch_bounds__(64) void k_adaptive_sums(AdArgs<T> a) {
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
                          task_ag_group(a.nd, g), a.err, npc, npp, cks);
-        if (ev.on) {
+        double v[3] = {(double)ev.sW, (double)ev.sWh, (double)ev.sPh};
+        ev.sp.template reduce<3>(v, reinterpret_cast<double *>(&stage), (uint32_t)threadIdx.x);
+        if (ev.on && threadIdx.x < ev.sp.gc) {
             const double h = (double)a.hs[i];
-            const double n = (double)ev.sW;
+            const double n = v[0];
             const double dhdn = -h / (3.0 * n);
-            const double omega = 1.0 - dhdn * (double)ev.sWh;
-            const double zeta = dhdn * (double)ev.sPh;
+            const double omega = 1.0 - dhdn * v[1];
+            const double zeta = dhdn * v[2];
             a.z[i] = zeta / omega;
             if (a.aux) {
                 const int64_t o = a.order[i];
@@ -332,12 +341,14 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
                          task_ag_group(a.nd, g), a.err, npc, npp, cks);
-        if (ev.on) {
+        double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
+        ev.sp.template reduce<4>(v, reinterpret_cast<double *>(&stage), (uint32_t)threadIdx.x);
+        if (ev.on && threadIdx.x < ev.sp.gc) {
             const int64_t o = a.order[i];
-            a.acc[3 * o] = (T)(a.G * ev.ax.value());
-            a.acc[3 * o + 1] = (T)(a.G * ev.ay.value());
-            a.acc[3 * o + 2] = (T)(a.G * ev.az.value());
-            if (a.pot) a.pot[o] = (T)(a.G * ev.ap.value());
+            a.acc[3 * o] = (T)(a.G * v[0]);
+            a.acc[3 * o + 1] = (T)(a.G * v[1]);
+            a.acc[3 * o + 2] = (T)(a.G * v[2]);
+            if (a.pot) a.pot[o] = (T)(a.G * v[3]);
         }
     }
 }
@@ -353,8 +364,8 @@ template <typename T>
 sf_status adaptive_run(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, void *aux,
                        DevArena &ar) {
     hipStream_t s = t->stream;
-    // the ordinary walk first: sinks keep its fields, gas cells are rewritten
-    sf_status st = tree_accel(t, o, acc, pot, ar);
+    // sinks take their fields from the sink walk; gas cells from the walks below
+    sf_status st = tree_accel(t, o, acc, pot, ar, false);
     if (st != SF_OK) return st;
     int32_t *ctr;
     uint32_t *gstack;

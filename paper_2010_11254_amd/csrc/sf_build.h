@@ -103,8 +103,11 @@ sf_status tree_stats(sf_grav_tree_s *t, sf_grav_stats *out);
 struct WalkNodes;
 void set_relative(WalkNodes &nd, const sf_grav_tree_s *t, const EvalOpts &o);
 
-// A8-A10, A12: tree walk for gas targets, sink walk + FP64 sink-sink.
-sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar);
+// A8-A10, A12: tree walk for gas targets, sink walk + FP64 sink-sink.  With
+// groups false only the sinks' fields are written (the gas targets are left
+// to another evaluator), and no statistics or costs are recorded.
+sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar,
+                     bool groups = true);
 // Tidal tensor and jerk (and g, phi) in one tree walk; vel may be NULL when
 // jerk is NULL; pot/tid may be NULL.
 sf_status tidal_accel(sf_grav_tree_s *t, const EvalOpts &o, const void *vel, void *acc, void *pot,

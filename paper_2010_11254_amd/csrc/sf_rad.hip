@@ -11,10 +11,12 @@
 // centre of mass.  e_IR: sinks' luminosities, an accepted node as its total
 // sink luminosity at the luminosity-weighted centre, particles with the same
 // softened r^2.  The walk and its decisions are those of sf_grav_accel (node
-// moments over all particles); one lane per gas target.
+// moments over all particles).  Each target of a group holds
+// floor(64 / gc) lanes that share its batch entries (lane splitting).
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_split.h"
 #include "sf_walk.h"
 
 namespace sf {
@@ -65,6 +67,7 @@ struct RadEval {
     R tx, ty, tz;
     int32_t tidx;
     bool on;
+    Split sp;
     Acc<FORM> acc[kR];
 
     __device__ void fold(const R (&b)[kR]) {
@@ -76,7 +79,7 @@ struct RadEval {
     __device__ void run(uint32_t nb) {
         R b[kR] = {};
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const RadEntry<R> s = st[j];
                 if (s.mw > R(0)) {
                     const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
@@ -87,7 +90,7 @@ struct RadEval {
                     const R dx = s.lx - tx, dy = s.ly - ty, dz = s.lz - tz;
                     b[6] += s.lw / (dx * dx + dy * dy + dz * dz + s.e2);
                 }
-            }
+            });
         fold(b);
         __syncthreads();
     }
@@ -141,14 +144,14 @@ struct RadEval {
         // each lane skips its own target's entry (only near leaves hold it)
         R b[kR] = {};
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const RadEntry<R> s = st[j];
                 const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
                 const R r2 = dx * dx + dy * dy + dz * dz + s.e2;
                 const bool self = SOFT && L.slot[j] == tidx;
                 if (s.mw > R(0) && !self) add_col<R>(dx, dy, dz, s.mw / r2, b);
                 if (s.lw > R(0) && !self) b[6] += s.lw / r2;
-            }
+            });
         fold(b);
         __syncthreads();
     }
@@ -172,8 +175,9 @@ __global__ __launch_bounds__(64) void k_walk_rad(RadArgs<T> a) {
             bhi[d] = a.gbox[6 * g + 3 + d];
             ev.cen[d] = a.gcen[3 * g + d];
         }
-        const int64_t i = gf + (lane < gc ? lane : 0);
-        ev.on = lane < gc && a.order[i] < a.n_gas;
+        ev.sp.init((uint32_t)gc, (uint32_t)lane);
+        const int64_t i = gf + ev.sp.tl;
+        ev.on = a.order[i] < a.n_gas;
         if (__ballot(ev.on) == 0ull) continue;
         ev.tx = to_frame<FORM>(a.xs[i], ev.cen[0]);
         ev.ty = to_frame<FORM>(a.ys[i], ev.cen[1]);
@@ -184,11 +188,16 @@ __global__ __launch_bounds__(64) void k_walk_rad(RadArgs<T> a) {
         uint64_t cks;
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks);
-        if (ev.on) {
+        double v[kR];
+        for (int c = 0; c < kR; ++c) v[c] = ev.acc[c].value();
+        // the stage is free once the task's batches are done
+        ev.sp.template reduce<sizeof(stage) / (64 * sizeof(double))>(
+            v, reinterpret_cast<double *>(stage), (uint32_t)lane);
+        if (ev.on && (uint32_t)lane < ev.sp.gc) {
             const int64_t o = a.order[i];
             if (a.col)
-                for (int c = 0; c < 6; ++c) a.col[6 * o + c] = (T)(a.inv_omega * ev.acc[c].value());
-            if (a.eir) a.eir[o] = (T)(a.inv_4pic * ev.acc[6].value());
+                for (int c = 0; c < 6; ++c) a.col[6 * o + c] = (T)(a.inv_omega * v[c]);
+            if (a.eir) a.eir[o] = (T)(a.inv_4pic * v[6]);
         }
     }
 }

@@ -13,14 +13,15 @@
 // sinks, as for g.
 //
 // The walk (decisions, lists) is the group walk of sf_walk.h, so the lists
-// equal those of sf_grav_accel on the same handle and options.  The
-// evaluation is simpler than the force-only kernel: one lane per target of
-// the group (lanes past the group's size idle), batch entries staged in LDS
-// and read by every lane.
+// equal those of sf_grav_accel on the same handle and options.  Batch
+// entries are staged in LDS; each target of the group holds floor(64 / gc)
+// lanes that share its entries (lane splitting), and the copies' partial
+// sums are added in a fixed order at the end of the task.
 #include "sf_build.h"
 #include "sf_ext.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_split.h"
 #include "sf_walk.h"
 
 namespace sf {
@@ -103,7 +104,7 @@ __device__ __forceinline__ void node_term(const XNode<typename FormT<FORM>::R> &
     ext_term<R, JERK>(dx, dy, dz, s.vx - tvx, s.vy - tvy, s.vz - tvz, mF, mR, R(0), b, false);
 }
 
-// Group tasks: lane t holds target t of the group (t < gc).
+// Group tasks: lane t + gc*s holds copy s of target t of the group.
 template <typename T, int FORM, int ORDER, bool JERK>
 struct GroupEvalX {
     using R = typename FormT<FORM>::R;
@@ -113,6 +114,7 @@ struct GroupEvalX {
     R tx, ty, tz, th, tvx, tvy, tvz;
     int32_t tidx;
     bool on;                    // this lane holds a gas target
+    Split sp;
     Acc<FORM> acc[kX];
 
     __device__ void fold(const R (&b)[kX]) {
@@ -126,8 +128,9 @@ struct GroupEvalX {
         __syncthreads();
         R b[kX] = {};
         if (on)
-            for (uint32_t j = 0; j < nb; ++j)
+            sp.each(nb, [&](uint32_t j) {
                 node_term<T, FORM, ORDER, JERK>(st->nd[j], tx, ty, tz, tvx, tvy, tvz, b);
+            });
         fold(b);
         __syncthreads();
     }
@@ -155,11 +158,11 @@ struct GroupEvalX {
         __syncthreads();
         R b[kX] = {};
         if (on)
-            for (uint32_t j = 0; j < nb; ++j) {
+            sp.each(nb, [&](uint32_t j) {
                 const XPart<R> s = st->pp[j];
                 ext_pair<R, JERK>(s.x - tx, s.y - ty, s.z - tz, s.vx - tvx, s.vy - tvy, s.vz - tvz,
                                   s.m, s.h, th, SOFT && s.idx == tidx, b);
-            }
+            });
         fold(b);
         __syncthreads();
     }
@@ -196,8 +199,9 @@ __global__ __launch_bounds__(64) void k_walk_groups_x(WalkArgsX<T> a) {
             bhi[d] = a.gbox[6 * g + 3 + d];
             ev.cen[d] = a.gcen[3 * g + d];
         }
-        const int64_t i = gf + (lane < gc ? lane : 0);
-        ev.on = lane < gc && a.order[i] < a.n_gas;
+        ev.sp.init((uint32_t)gc, (uint32_t)lane);
+        const int64_t i = gf + ev.sp.tl;
+        ev.on = a.order[i] < a.n_gas;
         if (__ballot(ev.on) == 0ull) continue;   // sinks only: left to the sink walk
         ev.tx = to_frame<FORM>(a.xs[i], ev.cen[0]);
         ev.ty = to_frame<FORM>(a.ys[i], ev.cen[1]);
@@ -215,11 +219,12 @@ __global__ __launch_bounds__(64) void k_walk_groups_x(WalkArgsX<T> a) {
         uint64_t cks;
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks);
-        if (ev.on) {
-            double v[kX];
-            for (int c = 0; c < kX; ++c) v[c] = ev.acc[c].value();
-            write_out(a, a.order[i], v);
-        }
+        double v[kX];
+        for (int c = 0; c < kX; ++c) v[c] = ev.acc[c].value();
+        // the stage is free once the task's batches are done
+        ev.sp.template reduce<sizeof(XStage<R>) / (64 * sizeof(double))>(
+            v, reinterpret_cast<double *>(&stage), (uint32_t)lane);
+        if (ev.on && (uint32_t)lane < ev.sp.gc) write_out(a, a.order[i], v);
     }
 }
 

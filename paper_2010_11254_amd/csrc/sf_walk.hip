@@ -666,7 +666,8 @@ static WalkArgs<T> make_args(sf_grav_tree_s *t, const EvalOpts &o, int set, void
 // has its own task counter and stack area.
 template <typename T, int FORM, int ORDER>
 static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, int32_t *ctr,
-                         double *ss, uint32_t *gstack, uint32_t *sstack, hipStream_t side) {
+                         double *ss, uint32_t *gstack, uint32_t *sstack, hipStream_t side,
+                         bool groups) {
     const unsigned grid = (unsigned)walk_grid();
     if (t->n_sink > 0) {
         WalkArgs<T> as = make_args<T>(t, o, 1, acc, pot, ctr + kCtrSinks, ss, sstack);
@@ -676,6 +677,7 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
         hipLaunchKernelGGL((k_walk_sinks<T, FORM, ORDER>), dim3(gs), dim3(64), 0, side, as);
         phase_end(t, 6, side);
     }
+    if (!groups) return;
     WalkArgs<T> ag = make_args<T>(t, o, 0, acc, pot, ctr, ss, gstack);
     phase_begin(t, 5);
     if (o.stats)
@@ -688,8 +690,8 @@ static void launch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *
 template <typename T>
 static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
                            int32_t *ctr, double *ss, uint32_t *gstack, uint32_t *sstack,
-                           hipStream_t side) {
-#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss, gstack, sstack, side)
+                           hipStream_t side, bool groups) {
+#define SF_W(F, O) launch_walks<T, F, O>(t, o, acc, pot, ctr, ss, gstack, sstack, side, groups)
     if (o.order == 0) {
         if (o.form == SF_FP32C) SF_W(SF_FP32C, 0);
         else if (o.form == SF_FP32) SF_W(SF_FP32, 0);
@@ -702,14 +704,16 @@ static void dispatch_walks(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void
 #undef SF_W
 }
 
-sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar) {
+sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot, DevArena &ar,
+                     bool groups) {
+    if (!groups && t->n_sink == 0) return SF_OK;
     int32_t *ctr = nullptr;
     double *ss = nullptr, *srec = nullptr;
     uint32_t *gstack = nullptr, *sstack = nullptr;
     SF_ALLOC_TMP(ar, ctr, kCtrWords);
     SF_ALLOC_TMP(ar, gstack, (int64_t)walk_grid() * kStack);
     fill_u32((uint32_t *)ctr, kCtrWords, 0u, t->stream);
-    if (o.stats) {
+    if (groups && o.stats) {
         if (!t->gnpc) {
             HandleAlloc keep(t);
             int32_t *npc, *npp;
@@ -729,7 +733,7 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         fill_ranges_u32(zero, 0u, t->stream);
         t->have_stats = true;
     }
-    if (!t->gcost) {   // zero beyond the groups, so a cost order is a permutation of them
+    if (groups && !t->gcost) {   // zero beyond the groups, so a cost order is a permutation of them
         HandleAlloc keep(t);
         uint32_t *cost;
         SF_ALLOC(keep.ar, cost, t->groups_cap);
@@ -737,7 +741,7 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         t->gcost = cost;
         fill_u32(t->gcost, t->groups_cap, 0u, t->stream);
     }
-    t->have_cost = false;
+    if (groups) t->have_cost = false;
     // every allocation precedes the fork: no early return between the fork
     // and the join
     hipStream_t side = t->stream;
@@ -751,8 +755,8 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
         sink_sink_accel(t, o.G, ss, srec, side);
         phase_end(t, 4, side);
     }
-    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
-    else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack, sstack, side);
+    if (t->dt == SF_F32) dispatch_walks<float>(t, o, acc, pot, ctr, ss, gstack, sstack, side, groups);
+    else dispatch_walks<double>(t, o, acc, pot, ctr, ss, gstack, sstack, side, groups);
     if (t->n_sink > 0) {   // joined before any early return, so scratch outlives the side work
         sf_status st = side_join(t, side);
         if (st != SF_OK) return st;
@@ -763,7 +767,7 @@ sf_status tree_accel(sf_grav_tree_s *t, const EvalOpts &o, void *acc, void *pot,
     SF_HIP(hipStreamSynchronize(t->stream));
     if (herr)
         return sf_fail(SF_E_INTERNAL, "tree walk stopped by a capacity guard (code %d)", herr);
-    t->have_cost = true;
+    if (groups) t->have_cost = true;
     return SF_OK;
 }
 
