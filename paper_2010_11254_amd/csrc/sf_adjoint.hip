@@ -18,6 +18,7 @@
 #include "sf_build.h"
 #include "sf_math.h"
 #include "sf_prims.h"
+#include "sf_split.h"
 #include "sf_walk.h"
 
 namespace sf {
@@ -458,9 +459,14 @@ struct WalkArgsB {
     int64_t n_sink;
     const T *g_acc, *g_pot;     // caller order
     double *tgt;                // 5 per sorted particle: target side (x y z m h)
-    // Atomic arrays, component-major (value c of particle p at c n + p, of
-    // node k at c n_nodes + k) so that a batch's 64 adds to one component
-    // fall into a few cache lines; kXcd copies each.
+    // Atomic arrays, kXcd copies each.  Particle values component-major
+    // (value c of particle p at c n + p): a batch's particles come from a few
+    // leaves, so one add instruction over the batch touches a few cache
+    // lines.  Node values of the group walk node-major (value c of node k at
+    // 9 k + c): a batch's nodes are scattered, so its 9 values per node are
+    // added by consecutive lanes, which keeps each add instruction on a few
+    // lines.  The sink walk, one node per lane, adds component-major (value
+    // c at c n_nodes + k), so a lane's 9 adds do not queue on one line.
     double *scat;               // 5 per sorted particle: source side (x y z m h)
     double *nadj;               // 9 per node: M, c(3), dQ(5)
     int64_t scat_stride, nadj_stride;   // elements between copies
@@ -480,9 +486,6 @@ __device__ __forceinline__ void atomic_add_f64(double *p, double v) { unsafeAtom
 // FP32.
 constexpr float kFarB = 1e15f;
 constexpr float kFarT = -1e15f;
-
-// Gray code: consecutive values differ in exactly one bit.
-__device__ __forceinline__ uint32_t gray(uint32_t s) { return s ^ (s >> 1); }
 
 // FP64 LDS atomic add (ds_add_f64).
 __device__ __forceinline__ void lds_add(double *p, double v) { unsafeAtomicAdd(p, v); }
@@ -510,27 +513,29 @@ __device__ __forceinline__ double lane_take(int src, double v) {
 // once and split into its target side (kept in the registers of the lanes
 // that own the target) and its entry side.
 //
-// Lane splitting as in the forward walk: a group of gc targets uses W = next
-// power of two >= gc lanes per copy and k = 64 / W copies.  A batch of nb
-// entries is padded to 64 = k W entries and entry e is staged in slot
-// (e mod k) W + e / k, so copy `sub` owns the slots [sub W, sub W + W).  In
-// step s (of W) the lane of target t takes slot sub W + (t xor gray(s)): the
-// 64 lanes of a step sit on 64 different slots, and every lane meets every
-// slot of its copy once.  The entry-side sums live in registers and travel
-// with their slot: after step s the lane holding slot j hands it to the lane
-// that takes j in step s + 1, at lane distance gray(s) xor gray(s + 1) (one
-// bit, so it stays within the copy), by one lane shuffle per value.  After
-// the last step the sums are written to LDS by slot and flushed with one
-// FP64 global atomic add per entry and value.  (LDS atomic adds measured
-// slower on gfx950, FP32 ones by an order of magnitude; a read-add-write of
-// LDS records exposes the LDS latency in every step.)  The FP64 form keeps
-// FP64 LDS atomic adds instead: its hand-off needs two shuffles per value,
-// which measured slower than the adds.
+// Lane splitting as in the forward walk: a group of gc targets gets
+// k = floor(64 / gc) copies of each target, lane t + gc*c holding copy c of
+// target t.  A batch holds at most k gc entries (the walk is run with
+// batches of that size); entry e is staged in slot (e mod k) gc + e / k, so
+// copy c owns the gc slots [c gc, c gc + gc).  In step s (of gc) the lane of
+// target t takes slot c gc + (t + s) mod gc: the lanes of a step sit on
+// different slots, and every lane meets every slot of its copy once.  The
+// entry-side sums live in registers and travel with their slot: the slot a
+// lane takes in step s + 1 is the one its right-hand neighbour (cyclically,
+// within the copy) held in step s, so one lane shuffle per value hands all
+// of them on.  After the last step the sums are written to LDS by slot and
+// flushed with one FP64 global atomic add per entry and value.  (LDS atomic
+// adds measured slower on gfx950, FP32 ones by an order of magnitude; a
+// read-add-write of LDS records exposes the LDS latency in every step.)
+// The FP64 form keeps FP64 LDS atomic adds instead: its hand-off needs two
+// shuffles per value, which measured slower than the adds.
 //
-// Padding entries are zero-mass dummies far away; lanes without a target (or
-// with a sink target) sit far away on the other side with zero cotangents,
-// so both contribute exact zeros to every real sum, and no step needs a
-// predicate.
+// Padding entries are zero-mass dummies far away; lanes without a target (a
+// sink target, in the FP64 form the lanes past the group's size, or lanes
+// from k gc on) sit far away on the other side with
+// zero cotangents, so both contribute exact zeros to every real sum, and no
+// step needs a predicate.  Lanes from k gc on keep to slot = their lane,
+// which holds a dummy and is never flushed.
 template <typename T, int FORM, int ORDER>
 struct GroupEvalB {
     using R = typename FormT<FORM>::R;
@@ -546,13 +551,41 @@ struct GroupEvalB {
     double cen[3];
     TgtB<R> me;
     static constexpr bool kShuffle = sizeof(R) == 4;
-    uint32_t tl, sub, k;
+    uint32_t gc, k, nslot;      // copy width (the group size), copies, k gc slots in use
+    uint32_t tl, base;          // this lane's target and the first slot of its copy
+    bool inslot;                // lane < k gc
+    int src;                    // byte address of the lane that hands this lane its next slot
+    uint32_t held_last;         // slot this lane holds after a batch's last step
+    uint32_t stslot;            // slot of the entry this lane stages
     Acc<FORM> ox, oy, oz, oh;
 
+    // The FP64 form, whose entry sums are LDS atomic adds rather than a
+    // hand-off, takes gc rounded up to a power of two as the copy width (the
+    // lanes past the group's size hold no target), so that every batch holds
+    // 64 entries: with no hand-off, smaller batches would only add flushes.
+    __device__ void setup(uint32_t gcount, uint32_t lane) {
+        gc = gcount;
+        if constexpr (!kShuffle) {
+            gc = 1u;
+            while (gc < gcount) gc <<= 1;
+        }
+        k = 64u / gc;
+        nslot = k * gc;
+        tl = lane % gc;
+        const uint32_t c = lane / gc;
+        inslot = lane < nslot;
+        base = c * gc;
+        const uint32_t nxt = tl + 1u == gc ? 0u : tl + 1u;
+        src = (int)((inslot ? base + nxt : lane) << 2);
+        const uint32_t last = tl == 0u ? gc - 1u : tl - 1u;   // (tl + gc - 1) mod gc
+        held_last = inslot ? base + last : lane;
+        // lane e stages batch entry e: entries e < nslot fill the slots in
+        // use, the other lanes their own unused slot
+        stslot = inslot ? (lane % k) * gc + lane / k : lane;
+    }
+
     template <int NV>
-    __device__ __forceinline__ void pass_on(R (&acc)[NV], uint32_t s) const {
-        // byte address of lane (this lane xor d) for ds_bpermute
-        const int src = (int)((threadIdx.x ^ (gray(s) ^ gray(s + 1))) << 2);
+    __device__ __forceinline__ void pass_on(R (&acc)[NV]) const {
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = lane_take(src, acc[v]);
     }
@@ -560,8 +593,7 @@ struct GroupEvalB {
     __device__ void pc_batch(WalkLds &L, uint32_t head, uint32_t nb) {
         constexpr int NV = ORDER == 2 ? 9 : 4;
         const uint32_t e = threadIdx.x;
-        const uint32_t m = 64u / k;
-        const uint32_t slot = (e % k) * m + e / k;
+        const uint32_t slot = stslot;
         int node = -1;
         if (e < nb) {
             node = L.pc[(head + e) & 127];
@@ -576,13 +608,14 @@ struct GroupEvalB {
             for (int d = 3; d < 9; ++d) stg[d][slot] = R(0);
         }
         __syncthreads();
-        const uint32_t base = sub * m;
         R acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = R(0);
         R bx = 0, by = 0, bz = 0;
-        for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = base + (tl ^ gray(s));
+        uint32_t jj = tl;   // (tl + s) mod gc
+        for (uint32_t s = 0; s < gc; ++s) {
+            const uint32_t j = inslot ? base + jj : threadIdx.x;
+            jj = jj + 1u == gc ? 0u : jj + 1u;
             R q5[5] = {R(0), R(0), R(0), R(0), R(0)};
             if (ORDER == 2)
                 for (int d = 0; d < 5; ++d) q5[d] = stg[4 + d][j];
@@ -600,7 +633,7 @@ struct GroupEvalB {
                 acc[3] -= gz;
                 if (ORDER == 2)
                     for (int d = 0; d < 5; ++d) acc[4 + d] += gq[d];
-                if (s + 1 < m) pass_on<NV>(acc, s);
+                if (s + 1 < gc) pass_on<NV>(acc);
             } else {
                 lds_add(&bacc[0][j], (double)gM);
                 lds_add(&bacc[1][j], (double)-gx);
@@ -613,20 +646,52 @@ struct GroupEvalB {
         ox.fold(bx);
         oy.fold(by);
         oz.fold(bz);
-        flush<NV>(acc, base, nb, slot, nadj + node, a->nd.n_nodes);
+        flush_nodes<NV>(acc, L, head, nb);
+        (void)node;
+    }
+
+    // Node-side sums of a finished batch to the node-major FP64 array: the
+    // nb x NV values are taken in entry-major order, 64 consecutive ones per
+    // add instruction (value d of entry e at 9 node(e) + d).
+    template <int NV>
+    __device__ __forceinline__ void flush_nodes(const R (&acc)[NV], const WalkLds &L,
+                                                uint32_t head, uint32_t nb) {
+        const uint32_t e = threadIdx.x;
+        sidx[e] = (int32_t)stslot;   // slot of entry e (unused by node batches otherwise)
+        __syncthreads();   // every lane is done reading the staged entries
+        if constexpr (kShuffle) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) stg[v][held_last] = acc[v];
+            __syncthreads();
+        }
+        const uint32_t tot = nb * NV;
+        for (uint32_t q = e; q < tot; q += 64u) {
+            const uint32_t en = q / NV;
+            const uint32_t d = q - en * NV;
+            const int32_t sl = sidx[en];
+            const int nd = L.pc[(head + en) & 127];
+            double v;
+            if constexpr (kShuffle) v = (double)stg[d][sl];
+            else v = bacc[d][sl];
+            atomic_add_f64(nadj + (int64_t)nd * 9 + d, v);
+        }
+        __syncthreads();
+        if constexpr (!kShuffle) {
+            for (int d = 0; d < NV; ++d) bacc[d][e] = 0.0;
+            __syncthreads();
+        }
     }
 
     // Entry-side sums of a finished batch to the global FP64 arrays: value d
     // of entry e goes to out_e[d * stride] (out_e = base array + entry index).
     template <int NV>
-    __device__ __forceinline__ void flush(const R (&acc)[NV], uint32_t base, uint32_t nb,
-                                          uint32_t slot, double *out_e, int64_t stride) {
+    __device__ __forceinline__ void flush(const R (&acc)[NV], uint32_t nb, uint32_t slot,
+                                          double *out_e, int64_t stride) {
         const uint32_t e = threadIdx.x;
         __syncthreads();   // every lane is done reading the staged entries
         if constexpr (kShuffle) {
-            const uint32_t held = base + (tl ^ gray(64u / k - 1));
 #pragma unroll
-            for (int v = 0; v < NV; ++v) stg[v][held] = acc[v];
+            for (int v = 0; v < NV; ++v) stg[v][held_last] = acc[v];
             __syncthreads();
             if (e < nb) {
                 // all values read before the first add, so the LDS reads overlap
@@ -649,8 +714,7 @@ struct GroupEvalB {
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         constexpr int NV = SOFT ? 5 : 4;
         const uint32_t e = threadIdx.x;
-        const uint32_t m = 64u / k;
-        const uint32_t slot = (e % k) * m + e / k;
+        const uint32_t slot = stslot;
         int p = -1;
         if (e < nb) {
             p = L.slot[e];
@@ -668,13 +732,14 @@ struct GroupEvalB {
             sidx[slot] = -1;
         }
         __syncthreads();
-        const uint32_t base = sub * m;
         R acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = R(0);
         R bx = 0, by = 0, bz = 0, bh = 0;
-        for (uint32_t s = 0; s < m; ++s) {
-            const uint32_t j = base + (tl ^ gray(s));
+        uint32_t jj = tl;   // (tl + s) mod gc
+        for (uint32_t s = 0; s < gc; ++s) {
+            const uint32_t j = inslot ? base + jj : threadIdx.x;
+            jj = jj + 1u == gc ? 0u : jj + 1u;
             R Sx, Sy, Sz, Tm, Th, sh;
             const R hj2 = SOFT ? stg[4][j] : R(0), hj = SOFT ? stg[5][j] : R(0);
             const bool self = SOFT && sidx[j] == me.idx;
@@ -691,7 +756,7 @@ struct GroupEvalB {
                 acc[2] += Sz;
                 acc[3] += Tm;
                 if (SOFT) acc[NV - 1] += (R(1) - sh) * Th;
-                if (s + 1 < m) pass_on<NV>(acc, s);
+                if (s + 1 < gc) pass_on<NV>(acc);
             } else {
                 lds_add(&bacc[0][j], (double)Sx);
                 lds_add(&bacc[1][j], (double)Sy);
@@ -704,12 +769,12 @@ struct GroupEvalB {
         oy.fold(by);
         oz.fold(bz);
         if (SOFT) oh.fold(bh);
-        flush<NV>(acc, base, nb, slot, scat + p, a->n);
+        flush<NV>(acc, nb, slot, scat + p, a->n);
     }
 };
 
 template <typename T, int FORM, int ORDER>
-__global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
+__global__ __launch_bounds__(64, 3) void k_walk_groups_b(WalkArgsB<T> a) {
     using R = typename FormT<FORM>::R;
     __shared__ WalkLds L;
     __shared__ R stg[9][64];
@@ -738,14 +803,10 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
             ev.cen[d] = a.gcen[3 * g + d];
         }
         const double hg = a.ghmax[g];
-        uint32_t W = 1;
-        while (W < (uint32_t)gc) W <<= 1;
-        ev.k = 64u / W;
-        ev.tl = (uint32_t)lane & (W - 1);
-        ev.sub = (uint32_t)lane / W;
-        const bool has = ev.tl < (uint32_t)gc;
-        const int64_t i = gf + (has ? ev.tl : 0);
-        const bool active = has && a.order[i] < a.n_gas;
+        ev.setup((uint32_t)gc, (uint32_t)lane);
+        const bool has = ev.tl < (uint32_t)gc;   // false only past the group in the FP64 form
+        const int64_t i = gf + (has ? ev.tl : 0u);
+        const bool active = ev.inslot && has && a.order[i] < a.n_gas;
         if (__ballot(active) == 0ull) continue;
         const int64_t o = a.order[i];
         TgtB<R> &me = ev.me;
@@ -772,11 +833,17 @@ __global__ __launch_bounds__(64) void k_walk_groups_b(WalkArgsB<T> a) {
         uint32_t npc, npp;
         uint64_t cks;
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg, gf,
-                         gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks);
+                         gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks, ev.nslot,
+                         ev.nslot);
         double v[4] = {ev.ox.value(), ev.oy.value(), ev.oz.value(), ev.oh.value()};
-        for (uint32_t off = W; off < 64u; off <<= 1)
-            for (int d = 0; d < 4; ++d) v[d] += __shfl_xor(v[d], (int)off, 64);
-        if (active && ev.sub == 0) {
+        // sum the k copies of each target in a fixed order, through LDS (the
+        // stage is free once the task's batches are done)
+        Split sp;
+        sp.gc = ev.gc;
+        sp.k = ev.k;
+        sp.template reduce<sizeof(stg) / (64 * sizeof(double))>(
+            v, reinterpret_cast<double *>(&stg[0][0]), (uint32_t)lane);
+        if (active && (uint32_t)lane < ev.gc) {
             a.tgt[5 * i] = v[0];
             a.tgt[5 * i + 1] = v[1];
             a.tgt[5 * i + 2] = v[2];
@@ -822,6 +889,7 @@ struct SinkEvalB {
             bx = g0;
             by = g1;
             bz = g2;
+            // component-major (one node per lane: a lane's 9 adds go to 9 lines)
             const int64_t nn = a->nd.n_nodes;
             atomic_add_f64(nadj + node, (double)gM);
             atomic_add_f64(nadj + nn + node, -(double)g0);
@@ -988,7 +1056,8 @@ __global__ __launch_bounds__(256) void k_leaf_poly(
             const double Mn = Ms[nd];
             if (!(Mn > 0.0)) continue;
             double a9[9];
-            for (int c = 0; c < 9; ++c) a9[c] = ad[c * nn + nd];
+            // set 0 (group walk) node-major, set 1 (sink walk) component-major
+            for (int c = 0; c < 9; ++c) a9[c] = set ? ad[c * nn + nd] : ad[9 * nd + c];
             const double e0 = r[0] - cs[3 * nd], e1 = r[1] - cs[3 * nd + 1], e2 = r[2] - cs[3 * nd + 2];
             const double gxx = a9[4], gyy = a9[5], gxy = 0.5 * a9[6], gxz = 0.5 * a9[7],
                          gyz = 0.5 * a9[8];

@@ -298,10 +298,13 @@ __device__ __forceinline__ bool ring_gather_n(PPRing &R, uint32_t &h, uint32_t t
     return ring_gather(R, h, t, slot + 64, mark, want - 64u, err);
 }
 
-// Walk one task.  Ev supplies pc_batch(L, head, nb) (nb <= 64) and
+// Walk one task.  Ev supplies pc_batch(L, head, nb) (nb <= pcb <= 64) and
 // pp_batch<SOFT>(L, nb) (nb <= ppb <= 128; SOFT = false: every pair is
-// Newtonian and none is a self pair).  A range ring is drained before it
-// holds more than 64 entries, so the next step's (at most 64) new entries fit.
+// Newtonian and none is a self pair).  Full batches hold pcb nodes and ppb
+// particles; the last ones of a task may be shorter.  A range ring is
+// drained before it holds more than 64 entries, and fewer than pcb <= 64
+// accepted nodes wait between steps, so the next step's (at most 64) new
+// entries always fit.
 // Stack entries moved out of and back into LDS: device-scope relaxed
 // atomics, so the wave reads back exactly what it wrote (no stale L1 line).
 __device__ __forceinline__ void stack_out(uint32_t *p, uint32_t v) {
@@ -316,7 +319,7 @@ template <bool CKS, class Ev>
 __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev &ev,
                           const double blo[3], const double bhi[3], double hg, int64_t gf,
                           int64_t gl, double ag, int32_t *err, uint32_t &n_pc, uint32_t &n_pp,
-                          uint64_t &cks, uint32_t ppb = 64u) {
+                          uint64_t &cks, uint32_t ppb = 64u, uint32_t pcb = 64u) {
     const int lane = threadIdx.x;
     const uint64_t lt = lane_mask_lt();
     uint32_t sp = 1;     // stack positions [0, sp)
@@ -412,10 +415,10 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
         }
         sp += npush;
         __syncthreads();
-        while (pc_t - pc_h >= 64u) {
-            ev.pc_batch(L, pc_h, 64);
-            pc_h += 64;
-            n_pc += 64;
+        while (pc_t - pc_h >= pcb) {
+            ev.pc_batch(L, pc_h, pcb);
+            pc_h += pcb;
+            n_pc += pcb;
         }
         while (fpend >= ppb || ft - fh > 64u) {
             const uint32_t nb = fpend < ppb ? fpend : ppb;

@@ -295,9 +295,9 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             a.gcks[g] = cks;
         }
         if (lane == 0 && a.gcost) {
-            uint32_t w = 1;   // the adjoint's lanes per target: gc rounded up to a power of two
-            while (w < gcu) w <<= 1;
-            const uint64_t c = ((uint64_t)3 * npc + npp) * w;
+            // the adjoint's steps: each of its k = floor(64 / gc) copies of
+            // a target meets 1/k of the list
+            const uint64_t c = ((uint64_t)3 * npc + npp) * 64u / k;
             a.gcost[g] = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
         }
     }
