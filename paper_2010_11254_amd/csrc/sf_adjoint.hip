@@ -389,27 +389,31 @@ __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2
 }
 
 // Node term, r = x_i - c: g = dL/dr (the centre of mass gets -g), gM = dL/dM,
-// gq = dL/dQ as 5 numbers (zero for monopoles): Q is traceless, so dL/dQ
-// matters only up to a multiple of the identity, and with G = dL/dQ written
-// as (w r^T + r w^T) / 2, w = r^-5 a - k r, the numbers are
-// G_xx - G_zz, G_yy - G_zz, 2 G_xy, 2 G_xz, 2 G_yz.
-// With the forward term phi = -M/r - s/(2 r^5), a = -M r/r^3 + q/r^5
-// - 5 s r/(2 r^7) (q = Q r, s = r.q) and L = a_bar.a + phi_bar phi:
-//   g = c_r r + c_a a_bar + c_q q + Q a_bar / r^5.
+// gq = dL/dQ as 5 numbers (zero for monopoles).  With the forward term
+// phi = -M/r - s/(2 r^5), a = -M r/r^3 + q/r^5 - 5 s r/(2 r^7) (q = Q r,
+// s = r.q) and L = a_bar.a + phi_bar phi:
+//   g = c_r r + c_a a_bar + c_q q + Q a_bar / r^5,
+//   c_r = 3 M ra/r^5 + phi_bar M/r^3 + (35/2 s ra/r^2 + 5/2 phi_bar s
+//         - 5 a_bar.q)/r^7,  c_a = -M/r^3 - 5/2 s/r^7,
+//   c_q = -5 ra/r^7 - phi_bar/r^5,  ra = r.a_bar.
+// Q is traceless, so dL/dQ matters only up to a multiple of the identity;
+// written as G = (w r^T + r w^T)/2 with w = a_bar/r^5 + (c_q/2) r, the five
+// numbers are G_xx - G_zz, G_yy - G_zz, 2 G_xy, 2 G_xz, 2 G_yz.  Since
+// Q w = Q a_bar/r^5 + (c_q/2) q, the g above is also c_r r + c_a a_bar
+// + (c_q/2) q + Q w, which shares w with dL/dQ.
 template <typename R, int ORDER>
 __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz,
                                            R qyz, R gax, R gay, R gaz, R gp, R &gx, R &gy,
                                            R &gz, R &gM, R gq[5]) {
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R ri = rsq(r2);
-    const R ri2 = ri * ri;
-    const R ri3 = ri * ri2;
-    const R ri5 = ri3 * ri2;
+    const R u = ri * ri;                      // 1/r^2
+    const R ri3 = ri * u;
     const R ra = rx * gax + ry * gay + rz * gaz;
-    const R gpri = gp * ri;
-    gM = -fma(ra, ri3, gpri);
+    const R t = ra * u;                       // (r . a_bar)/r^2
+    gM = -ri * (t + gp);                      // -(ra/r^3 + phi/r)
     const R Mri3 = M * ri3;
-    const R cm = M * fma(R(3) * ra, ri5, gpri * ri2);   // monopole part of c_r
+    const R cm = Mri3 * fma(R(3), t, gp);     // monopole part of c_r: M (3 ra/r^5 + phi/r^3)
     if (ORDER != 2) {
         gx = fma(cm, rx, -Mri3 * gax);
         gy = fma(cm, ry, -Mri3 * gay);
@@ -421,24 +425,26 @@ __device__ __forceinline__ void bmultipole(R rx, R ry, R rz, R M, R qxx, R qyy, 
     const R qx = qxx * rx + qxy * ry + qxz * rz;
     const R qy = qxy * rx + qyy * ry + qyz * rz;
     const R qz = qxz * rx + qyz * ry + qzz * rz;
-    const R Qax = qxx * gax + qxy * gay + qxz * gaz;
-    const R Qay = qxy * gax + qyy * gay + qyz * gaz;
-    const R Qaz = qxz * gax + qyz * gay + qzz * gaz;
     const R sq = qx * rx + qy * ry + qz * rz;
     const R aQr = gax * qx + gay * qy + gaz * qz;
-    const R ri7 = ri5 * ri2;
-    const R gpri5 = gpri * ri2 * ri2;
-    // c_r = 3 M ra/r^5 + phi M/r^3 + (35/2 s ra/r^2 + 5/2 phi s - 5 aQr)/r^7
-    const R cr = fma(ri7, fma(R(17.5) * sq * ra, ri2, fma(R(2.5) * gp, sq, R(-5) * aQr)), cm);
-    const R ca = -fma(R(2.5) * sq, ri7, Mri3);   // -M/r^3 - 5/2 s/r^7
-    const R cq = -fma(R(5) * ra, ri7, gpri5);    // -5 ra/r^7 - phi/r^5
-    gx = fma(ri5, Qax, fma(cq, qx, fma(ca, gax, cr * rx)));
-    gy = fma(ri5, Qay, fma(cq, qy, fma(ca, gay, cr * ry)));
-    gz = fma(ri5, Qaz, fma(cq, qz, fma(ca, gaz, cr * rz)));
-    const R k = fma(R(2.5) * ra, ri7, R(0.5) * gpri5);
-    const R wx = fma(-k, rx, ri5 * gax);
-    const R wy = fma(-k, ry, ri5 * gay);
-    const R wz = fma(-k, rz, ri5 * gaz);
+    const R ri5 = ri3 * u;
+    const R ri7 = ri5 * u;
+    const R s5 = R(2.5) * sq;
+    // c_r = cm + (35/2 s ra/r^2 + 5/2 phi s - 5 aQr)/r^7 = cm + (s5 (7 t + phi) - 5 aQr)/r^7
+    const R cr = fma(ri7, fma(s5, fma(R(7), t, gp), R(-5) * aQr), cm);
+    const R ca = -fma(s5, ri7, Mri3);         // -(M/r^3 + 5/2 s/r^7)
+    // hc = c_q / 2 with c_q = -(5 ra/r^7 + phi/r^5); dL/dQ's vector is
+    // w = r^-5 a_bar + hc r, and c_q q + Q a_bar/r^5 = Q w + hc q
+    const R hc = R(-0.5) * ri5 * fma(R(5), t, gp);
+    const R wx = fma(hc, rx, ri5 * gax);
+    const R wy = fma(hc, ry, ri5 * gay);
+    const R wz = fma(hc, rz, ri5 * gaz);
+    const R Qwx = qxx * wx + qxy * wy + qxz * wz;
+    const R Qwy = qxy * wx + qyy * wy + qyz * wz;
+    const R Qwz = qxz * wx + qyz * wy + qzz * wz;
+    gx = fma(cr, rx, fma(ca, gax, fma(hc, qx, Qwx)));
+    gy = fma(cr, ry, fma(ca, gay, fma(hc, qy, Qwy)));
+    gz = fma(cr, rz, fma(ca, gaz, fma(hc, qz, Qwz)));
     const R pz = wz * rz;
     gq[0] = fma(wx, rx, -pz);
     gq[1] = fma(wy, ry, -pz);
