@@ -288,7 +288,9 @@ __global__ __launch_bounds__(64) void k_adaptive_sums(AdArgs<T> a) {
     SumsEvalF<T, FORM> ev;
     ev.a = &a;
     ev.st = &stage;
-    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+    XcdTasks tasks;
+    tasks.init(a.task_ctr, ng);
+    for (int g = tasks.next(); g < ng; g = tasks.next()) {
         int64_t i;
         double blo[3], bhi[3];
         if (!group_target(a, ev, g, i, blo, bhi)) continue;
@@ -326,7 +328,9 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
     ForceEvalF<T, FORM, ORDER> ev;
     ev.a = &a;
     ev.st = &stage;
-    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+    XcdTasks tasks;
+    tasks.init(a.task_ctr, ng);
+    for (int g = tasks.next(); g < ng; g = tasks.next()) {
         int64_t i;
         double blo[3], bhi[3];
         if (!group_target(a, ev, g, i, blo, bhi)) continue;

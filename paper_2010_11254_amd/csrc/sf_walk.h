@@ -204,12 +204,56 @@ __device__ __forceinline__ int xcd_id() {
     return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcd - 1);   // hwreg(XCC_ID, 0, 4)
 }
 
-// Task counters: the group-task counter, the sink-task counter and the error
-// word, 64 bytes apart.
+// Task counters: the group-task counter, the sink-task counter, the error
+// word and kXcd per-XCD group counters, 64 bytes apart.
 constexpr int kCtrStride = 16;
 constexpr int kCtrSinks = kCtrStride;
 constexpr int kCtrErr = kCtrSinks + kCtrStride;
-constexpr int kCtrWords = kCtrErr + kCtrStride;
+constexpr int kCtrXcd = kCtrErr + kCtrStride;
+constexpr int kCtrWords = kCtrXcd + kXcd * kCtrStride;
+
+// Group tasks placed by XCD: the groups (Morton order, so spatially compact
+// runs) are cut into chunks of kXcdChunk, dealt to the XCDs in turn (chunk q
+// to XCD q mod kXcd).  A wave takes the tasks of its own XCD's chunks in
+// order, then helps the other XCDs (its XCD + 1, + 2, ...) until all are
+// drained.  At any moment the waves of one XCD work on a run of neighbouring
+// groups, which read the same node and particle records, so that XCD's L2
+// holds one compact region instead of a slice of every region in flight; and
+// all XCDs move through the Morton order together, so their shares of dense
+// and sparse regions stay alike.  (One contiguous eighth per XCD measured 8%
+// slower: the eighths' costs differ.)  Every task is taken exactly once, as
+// offset t of one XCD's sequence, and a wave stops after finding all kXcd
+// sequences past the last group.
+constexpr int kXcdChunkLog = 10;
+constexpr int kXcdChunk = 1 << kXcdChunkLog;
+
+struct XcdTasks {
+    int32_t *xc;   // kXcd counters, kCtrStride words apart
+    int ng, xcd, probe;
+
+    __device__ __forceinline__ void init(int32_t *ctr, int n_groups) {
+        xc = ctr + kCtrXcd;
+        ng = n_groups;
+        xcd = xcd_id();
+        probe = 0;
+    }
+
+    // Next task for the whole wave (a scalar), or ng when none is left.
+    __device__ __forceinline__ int next() {
+        while (probe < kXcd) {
+            const int c = (xcd + probe) & (kXcd - 1);
+            int t = 0;
+            if ((threadIdx.x & 63) == 0) t = atomicAdd(xc + c * kCtrStride, 1);
+            t = __builtin_amdgcn_readfirstlane(t);
+            // offset t of XCD c's sequence: chunk (t / kXcdChunk) kXcd + c
+            const int64_t g = ((int64_t)(t >> kXcdChunkLog) * kXcd + c) * kXcdChunk +
+                              (t & (kXcdChunk - 1));
+            if (g < ng) return (int)g;
+            ++probe;
+        }
+        return ng;
+    }
+};
 
 // Prefix sums and totals over the wave (called with all 64 lanes active):
 // an inclusive scan by DPP, one VALU add per stage -- row shifts by 1, 2, 4

@@ -223,7 +223,9 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
     ev.a = &a;
     ev.spp = stage.pp;
     ev.spc = stage.pc;
-    for (int g = next_task(a.task_ctr); g < ng; g = next_task(a.task_ctr)) {
+    XcdTasks tasks;
+    tasks.init(a.task_ctr, ng);
+    for (int g = tasks.next(); g < ng; g = tasks.next()) {
         const int64_t gf = a.gfirst[g], gc = a.gcount[g];
         double blo[3], bhi[3];
 #pragma unroll
