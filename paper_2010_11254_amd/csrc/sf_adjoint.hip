@@ -779,6 +779,9 @@ struct GroupEvalB {
     }
 };
 
+// At least three waves per SIMD: binds only the FP64 form (the FP32 forms
+// fit four in their registers), which without it took more registers than
+// three waves allow.
 template <typename T, int FORM, int ORDER>
 __global__ __launch_bounds__(64, 3) void k_walk_groups_b(WalkArgsB<T> a) {
     using R = typename FormT<FORM>::R;
