@@ -51,6 +51,12 @@ if ROOT not in sys.path:
 # evaluation code: particle pair 20, quadrupole node 54, monopole node 20.
 FLOP_PP = 20
 FLOP_PC = {0: 20, 2: 54}
+# With the tidal tensor and jerk in the same walk: particle pair 63 (the
+# pair's g and phi, T from F and F'/r, j from the relative velocity);
+# quadrupole node 98 (its g and phi, 54, plus the monopole T and j terms,
+# sharing r and 1/r with them).
+FLOP_PP_TIDAL = 63
+FLOP_PC_TIDAL = 98
 PEAK_FP32_TFLOPS = 157.3          # MI355X vector FP32 (published, packed)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
@@ -397,9 +403,13 @@ def main():
         L.sf_grav_tree_free(t)
         keep("precision4m_tidal", "T", tid)
         keep("precision4m_tidal", "j", jerk)
+        # the same lists as the headline walk: its interaction totals apply
+        tf = (FLOP_PP_TIDAL * n_pp + FLOP_PC_TIDAL * n_pc) / (tms * 1e-3) / 1e12
         tidal = {"accel_ms": fwd, "tidal_jerk_ms": tms, "ratio": tms / fwd, "form": "fp32c",
-                 "alpha": alpha}
-        log(f"tidal+jerk fp32c: {tms:.2f} ms against accel {fwd:.2f} ms ({tms / fwd:.2f}x)")
+                 "alpha": alpha, "achieved_tflops": tf, "peak": PEAK_FP32_TFLOPS,
+                 "frac": tf / PEAK_FP32_TFLOPS, "frac_nonpacked": tf / PEAK_FP32_NONPACKED_TFLOPS}
+        log(f"tidal+jerk fp32c: {tms:.2f} ms against accel {fwd:.2f} ms ({tms / fwd:.2f}x), "
+            f"{tf:.1f} TFLOP/s")
         del tid, jerk
 
         # the other tree-pass evaluations on the same handle (times only:
