@@ -17,10 +17,11 @@
 // are taken to satisfy it).  Gas-sink and sink-sink pairs keep the
 // larger-radius rule.
 //
-// Two walks over the handle's groups with the same decisions as
-// sf_grav_accel: the first sums n, dW/dh and m dP/dh over each gas cell's
-// neighbours (only leaves that may hold softened pairs can hold them); the
-// second evaluates the forces with every source's z from the first.  Each
+// Two walks over the handle's groups: the first sums n, dW/dh and m dP/dh
+// over each gas cell's neighbours, walking only the nodes that can hold a
+// softened pair (the near leaves of sf_grav_accel's lists, reached without
+// the far traversal); the second, with sf_grav_accel's decisions, evaluates
+// the forces with every source's z from the first.  Each
 // target holds floor(64 / gc) lanes that share its batch entries (lane
 // splitting); sinks get their fields from the sink walk of sf_grav_accel.
 #include "sf_build.h"
@@ -298,9 +299,9 @@ __global__ __launch_bounds__(64) void k_adaptive_sums(AdArgs<T> a) {
         ev.sW = ev.sWh = ev.sPh = R(0);
         uint32_t npc, npp;
         uint64_t cks;
-        walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
-                         a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
-                         task_ag_group(a.nd, g), a.err, npc, npp, cks);
+        walk_task<false, SumsEvalF<T, FORM>, true>(
+            a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, a.ghmax[g],
+            a.gfirst[g], a.gfirst[g] + a.gcount[g], task_ag_group(a.nd, g), a.err, npc, npp, cks);
         double v[3] = {(double)ev.sW, (double)ev.sWh, (double)ev.sPh};
         ev.sp.template reduce<3>(v, reinterpret_cast<double *>(&stage), (uint32_t)threadIdx.x);
         if (ev.on && threadIdx.x < ev.sp.gc) {

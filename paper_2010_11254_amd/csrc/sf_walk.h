@@ -134,11 +134,16 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
 // as pairs).  All FP64 steps are separately rounded (no contraction).  The
 // node record is read once, whole, and the fields the walk needs next are
 // returned with the class, so a step costs one memory round trip per node.
+// NEAR_ONLY walks (neighbour sums) keep only what can hold a softened pair:
+// near nodes are opened as usual and every other node is dropped (class 0),
+// which reaches exactly the near leaves of the full walk, because every
+// ancestor of a near node is near.
 struct NodeHit {
     int cls;
     int32_t first, count, child, lvl_nch;
 };
 
+template <bool NEAR_ONLY = false>
 __device__ __forceinline__ NodeHit classify(const WalkNodes &nd, int node, const double blo[3],
                                             const double bhi[3], double hg, int64_t gf,
                                             int64_t gl, double ag) {
@@ -162,7 +167,8 @@ __device__ __forceinline__ NodeHit classify(const WalkNodes &nd, int node, const
     bool far_ok = !(L2 > dmul(nd.th2, r2)) && w.M > 0.0;
     if (nd.rel) far_ok = far_ok && !(dmul(dmul(nd.G, w.M), L2) > dmul(ag, dmul(r2, r2)));
     const bool near = open || meets || soft;
-    const int cls = (!near && far_ok) ? 1 : ((w.lvl_nch & 255) != 0 ? 3 : (near ? 2 : 4));
+    int cls = (!near && far_ok) ? 1 : ((w.lvl_nch & 255) != 0 ? 3 : (near ? 2 : 4));
+    if (NEAR_ONLY && !near) cls = 0;
     return {cls, w.first, w.count, w.child, w.lvl_nch};
 }
 
@@ -358,8 +364,10 @@ __device__ __forceinline__ uint32_t stack_in(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// With CKS, cks receives (on every lane) the task's list checksum.
-template <bool CKS, class Ev>
+// With CKS, cks receives (on every lane) the task's list checksum.  With
+// NEAR_ONLY only near nodes are walked (see classify): no accepted nodes and
+// no far leaves reach the evaluator.
+template <bool CKS, class Ev, bool NEAR_ONLY = false>
 __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev &ev,
                           const double blo[3], const double bhi[3], double hg, int64_t gf,
                           int64_t gl, double ag, int32_t *err, uint32_t &n_pc, uint32_t &n_pp,
@@ -415,7 +423,7 @@ __device__ void walk_task(const WalkNodes &nd, WalkLds &L, uint32_t *gstack, Ev 
                              ? (int)((ent_e >> 4) + ((uint32_t)lane - (incl_e - (ent_e & 15u))))
                              : -1;
         NodeHit hit{0, 0, 0, 0, 0};
-        if (node >= 0) hit = classify(nd, node, blo, bhi, hg, gf, gl, ag);
+        if (node >= 0) hit = classify<NEAR_ONLY>(nd, node, blo, bhi, hg, gf, gl, ag);
         const int cls = hit.cls;
         if (CKS && (cls == 1 || cls == 2 || cls == 4))
             lane_cks += list_mix((uint64_t)node + (cls == 1 ? 0ull : (1ull << 31)));
