@@ -147,7 +147,7 @@ struct ForceEval {
     const AdArgs<T> *a;
     AdStage<R> *st;
     double cen[3];
-    R tx, ty, tz, th, tm, tz_;   // tz_: the target's zeta / Omega
+    R tx, ty, tz, th, tminv, tz_;   // tminv = 1/m of the target; tz_: its zeta / Omega
     int32_t tidx;
     bool on;
     Split sp;
@@ -228,7 +228,7 @@ struct ForceEval {
                         Wri = Wrj = R(0);
                         if (r < th) m4<R>(r, rcp(th), W, Wri, Wh);
                         if (r < s.h) m4<R>(r, rcp(s.h), W, Wrj, Wh);
-                        c = R(0.5) * (tz_ * Wri + (s.m / tm) * s.zz * Wrj) * ri;
+                        c = R(0.5) * (tz_ * Wri + s.m * tminv * s.zz * Wrj) * ri;
                     }
                 } else {
                     R Ph;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         int64_t i;
         double blo[3], bhi[3];
         if (!group_target(a, ev, g, i, blo, bhi)) continue;
-        ev.tm = (R)a.ms[i];
+        ev.tminv = rcp((R)a.ms[i]);
         ev.tz_ = (R)a.z[i];
         ev.ax.zero();
         ev.ay.zero();

@@ -84,11 +84,11 @@ struct RadEval {
                 if (s.mw > R(0)) {
                     const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
                     const R r2 = dx * dx + dy * dy + dz * dz + s.e2;
-                    add_col<R>(dx, dy, dz, s.mw / r2, b);
+                    add_col<R>(dx, dy, dz, s.mw * rcp(r2), b);
                 }
                 if (s.lw > R(0)) {
                     const R dx = s.lx - tx, dy = s.ly - ty, dz = s.lz - tz;
-                    b[6] += s.lw / (dx * dx + dy * dy + dz * dz + s.e2);
+                    b[6] += s.lw * rcp(dx * dx + dy * dy + dz * dz + s.e2);
                 }
             });
         fold(b);
@@ -149,8 +149,8 @@ struct RadEval {
                 const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
                 const R r2 = dx * dx + dy * dy + dz * dz + s.e2;
                 const bool self = SOFT && L.slot[j] == tidx;
-                if (s.mw > R(0) && !self) add_col<R>(dx, dy, dz, s.mw / r2, b);
-                if (s.lw > R(0) && !self) b[6] += s.lw / r2;
+                if (s.mw > R(0) && !self) add_col<R>(dx, dy, dz, s.mw * rcp(r2), b);
+                if (s.lw > R(0) && !self) b[6] += s.lw * rcp(r2);
             });
         fold(b);
         __syncthreads();
