@@ -67,6 +67,11 @@ PEAK_HBM_GBS = 8000.0
 # 8 x 24) + gather (read index 4 and x, m, h 20, write 20) + sink positions
 # (flags 8, scan 8, compaction 8).
 SORT_BYTES_PER_PARTICLE = 12 + 24 + 8 + 8 * 24 + 44 + 24
+# Algorithmic HBM bytes per particle of the walk: one pass over the sorted
+# particles (x, m, h: 20), the node records (about 0.11 nodes per particle at
+# 128 + 48 bytes: 20), the groups (2 per 21.7 particles: negligible) and the
+# outputs (acc and pot: 16).
+WALK_BYTES_PER_PARTICLE = 20 + 20 + 16
 # Relative (acceleration-based) opening criterion tolerances: quadrupole
 # workloads, and the monopole uniform sphere.
 ALPHA = 0.003
@@ -191,6 +196,55 @@ class Gpu:
         return a.elapsed_time(b) / reps
 
 
+class ClockSampler:
+    """Samples the GPU's graphics clock with `amd-smi` in a background thread
+    while a leg runs (a child process, started and waited for; None when the
+    tool is missing).  The clock is recorded because the VALU peaks assume
+    2.4 GHz."""
+
+    def __init__(self):
+        import threading
+        self.mhz, self._stop = [], threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _sample(self):
+        import numpy as np
+        try:
+            out = subprocess.run(["amd-smi", "metric", "-c", "--json"], capture_output=True,
+                                 text=True, timeout=10).stdout
+            data = json.loads(out)
+            gpus = data["gpu_data"] if isinstance(data, dict) else data
+            clocks = gpus[0]["clock"]
+            vals = [c["clk"]["value"] for k, c in clocks.items()
+                    if k.startswith("gfx") and isinstance(c, dict) and isinstance(c.get("clk"), dict)
+                    and isinstance(c["clk"].get("value"), (int, float))]
+            return float(np.mean(vals)) if vals else None
+        except Exception:   # no tool, no permission, other output: no sample
+            return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._sample()
+            if v is None:
+                return
+            self.mhz.append(v)
+
+    def __enter__(self):
+        self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._thread.join(timeout=15)
+
+    def summary(self):
+        import numpy as np
+        if not self.mhz:
+            return None
+        return {"median": float(np.median(self.mhz)), "max": float(np.max(self.mhz)),
+                "samples": len(self.mhz), "tool": "amd-smi metric -c (mean over gfx domains)"}
+
+
 class TreeLeg:
     """Repeated tree steps on one workload: build, previous field (when the
     relative criterion is on), walk.  The field of step k is the output of
@@ -237,16 +291,22 @@ class TreeLeg:
         for _ in range(warmup):
             L.sf_grav_tree_free(self.step(o))
         torch.cuda.synchronize()
-        phase = {}
+        phase, per_step = {}, []
         t0 = time.perf_counter()
         for _ in range(steps):
+            s0 = time.perf_counter()
             t = self.step(o)
-            for k, v in L.sf_grav_get_timings(t).items():
+            for k, v in L.sf_grav_get_timings(t).items():   # synchronises the stream
                 if v is not None:
                     phase.setdefault(k, []).append(v)
+            per_step.append((time.perf_counter() - s0) * 1e3)
             L.sf_grav_tree_free(t)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
+        walk = phase.get("walk", [])
+        self.step_stats = {"ms_median": float(np.median(per_step)), "ms_min": float(np.min(per_step)),
+                           "walk_ms_median": float(np.median(walk)) if walk else None,
+                           "walk_ms_min": float(np.min(walk)) if walk else None}
         return wall, {k: float(np.mean(v)) for k, v in phase.items()}
 
     def stats(self):
@@ -357,7 +417,17 @@ def main():
     log(f"tree: {info['n_nodes']} nodes, {info['n_groups']} groups, max level {info['max_level']}; "
         f"interactions/target: {n_pc / ps.n_gas:.0f} node + {n_pp / ps.n_gas:.0f} particle")
     wall32, ph32 = head.timed(args.steps, args.warmup)
+    step_stats = head.step_stats
     keep("precision4m", "tree_fp32c", head.last)
+    clocks = {}
+    if not args.headline_only:
+        # the graphics clock while headline steps run (untimed, about 3 s)
+        with ClockSampler() as cs:
+            t_end = time.time() + 3.0
+            while time.time() < t_end:
+                L.sf_grav_tree_free(head.step(head.o()))
+            torch.cuda.synchronize()
+        clocks["tree_steps"] = cs.summary()
     walk32 = ph32["walk"]
     log(f"fp32c: {wall32 * 1e3:.2f} ms/step, walk kernel {walk32:.2f} ms, phases "
         + ", ".join(f"{k} {v:.2f}" for k, v in ph32.items()))
@@ -450,10 +520,13 @@ def main():
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            L.sf_grav_accel(None, x, m, h, o, acc=acc, pot=pot)
-            b.record()
-            torch.cuda.synchronize()
+            with ClockSampler() as cs:   # the graphics clock during the evaluation
+                a.record()
+                L.sf_grav_accel(None, x, m, h, o, acc=acc, pot=pot)
+                b.record()
+                torch.cuda.synchronize()
+            if form == "fp32c":
+                clocks["direct_fp32c"] = cs.summary()
             ms = a.elapsed_time(b)
             keep("precision4m", "direct_" + form, acc)
             tf = FLOP_PP * pairs / (ms * 1e-3) / 1e12
@@ -592,7 +665,16 @@ def main():
                      "n_pc": n_pc, "n_pp": n_pp},
         "cpu_baseline": cpu,
         "phases_ms": ph32,
+        # per timed step (each synchronised): median and minimum beside the mean
+        "step_stats": step_stats,
+        # the whole step against its ideal time at peak: algorithmic walk FLOP
+        # at the FP32 peak, build and walk bytes at the HBM peak (the larger)
+        "step_roofline_frac": max(walk_flop / (PEAK_FP32_TFLOPS * 1e12),
+                                  (SORT_BYTES_PER_PARTICLE + WALK_BYTES_PER_PARTICLE) * ps.n
+                                  / (PEAK_HBM_GBS * 1e9)) / wall32,
     }
+    if clocks:
+        line["gfx_clock_mhz"] = clocks
     sort_ms = ph32.get("sort")
     if sort_ms:
         gbs = SORT_BYTES_PER_PARTICLE * ps.n / (sort_ms * 1e-3) / 1e9
