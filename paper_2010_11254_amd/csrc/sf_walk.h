@@ -57,24 +57,34 @@ static_assert(sizeof(StageBuf<float>) >= 4 * 64 * sizeof(double), "stage too sma
 
 // Particle pair: d = source - target.  Accumulates a (F m d) and phi (-m P).
 // hjinv, tiinv are the reciprocals of the two softening lengths (the support's
-// reciprocal is the smaller one).
-template <typename R>
+// reciprocal is the smaller one).  SELF = false leaves the self pair in: its
+// force term is exactly zero (d = 0, F finite) and its potential term is
+// m (14/5) / h of the target, which the caller then takes out once
+// (self_P below).
+template <typename R, bool SELF = true>
 __device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R hjinv, R ti2, R ti,
                                      R tiinv, bool self, R &bx, R &by, R &bz, R &bp) {
     const R r2 = dx * dx + dy * dy + dz * dz;
     const R ri = rsq(r2);
     R P = ri;
     R F = ri * ri * ri;
-    const R hh2 = hj2 > ti2 ? hj2 : ti2;
+    const R hh2 = fmax(hj2, ti2);
     if (r2 < hh2) {
-        soft_FP_ri<R>(r2, ri, hj > ti ? hj : ti, hjinv < tiinv ? hjinv : tiinv, F, P);
-        if (self) { F = R(0); P = R(0); }
+        soft_FP_ri<R>(r2, ri, fmax(hj, ti), fmin(hjinv, tiinv), F, P);
+        if (SELF && self) { F = R(0); P = R(0); }
     }
     const R mF = m * F;
     bx += mF * dx;
     by += mF * dy;
     bz += mF * dz;
     bp -= m * P;
+}
+
+// The softened P at r = 0, (14/5) / h, rounded as pair<R, false> rounds it
+// for a target's own particle (whose potential term is m times this).
+template <typename R>
+__device__ __forceinline__ R self_P(R hinv) {
+    return R(14.0 / 5.0) * hinv;
 }
 
 // Newtonian particle pair (no softening possible, not a self pair).

@@ -124,9 +124,9 @@ struct GroupEval {
 
     template <bool SOFT>
     __device__ __forceinline__ void pp_one(const PPStage<R> &s, R &bx, R &by, R &bz, R &bp) const {
-        if (SOFT)
-            pair<R>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, s.hinv, th2, th, thinv,
-                    s.idx == tidx, bx, by, bz, bp);
+        if (SOFT)   // the self pair stays in; its potential term is taken out per target
+            pair<R, false>(s.x - tx, s.y - ty, s.z - tz, s.m, s.h2, s.h, s.hinv, th2, th, thinv,
+                           false, bx, by, bz, bp);
         else
             pair_newton<R>(s.x - tx, s.y - ty, s.z - tz, s.m, bx, by, bz, bp);
     }
@@ -288,7 +288,10 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
                 a.acc[3 * o] = (T)(a.G * v[0]);
                 a.acc[3 * o + 1] = (T)(a.G * v[1]);
                 a.acc[3 * o + 2] = (T)(a.G * v[2]);
-                if (a.pot) a.pot[o] = (T)(a.G * v[3]);
+                // take out the self pair's potential term (-m P(0), added in the
+                // softened loop), as the exact product of the values it used
+                const double sp = (double)(R)a.ms[i] * (double)self_P<R>(ev.thinv);
+                if (a.pot) a.pot[o] = (T)(a.G * (v[3] + sp));
             }
         }
         if (STATS && lane == 0) {
