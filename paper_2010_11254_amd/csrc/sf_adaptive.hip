@@ -172,7 +172,7 @@ struct ForceEval {
             sp.each(nb, [&](uint32_t j) {
                 const AdNode<R> s = st->nd[j];
                 multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.q[0], s.q[1], s.q[2],
-                                    s.q[3], s.q[4], bx, by, bz, bp);
+                                    s.q[3], s.q[4], -(s.q[0] + s.q[1]), bx, by, bz, bp);
             });
         ax.fold(bx);
         ay.fold(by);

@@ -140,7 +140,12 @@ __global__ __launch_bounds__(256) void k_direct(int64_t n, int64_t n_gas, int64_
         R bx = 0, by = 0, bz = 0, bp = 0;
         const SrcRec<R> *src = rec + sf0;
         if (!near) {
-            for (int64_t j = 0; j < sc; ++j) {
+            // unrolled so that the scalar loads of several source records are
+            // in flight together (a tile holds at most 64 sources)
+            const uint32_t nsrc = (uint32_t)sc;
+            constexpr int U = sizeof(R) == 4 ? 4 : 2;   // FP64: registers for 2 in flight
+#pragma unroll U
+            for (uint32_t j = 0; j < nsrc; ++j) {
                 const SrcRec<R> q = src[j];
                 const R dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
                 const R r2 = dx * dx + dy * dy + dz * dz;

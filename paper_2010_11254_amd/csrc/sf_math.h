@@ -18,6 +18,29 @@ __device__ __forceinline__ double rsq(double x) {
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
+// Larger and smaller of two positive numbers that are finite or +inf
+// (softening lengths, their squares and reciprocals, reciprocal distances).
+// For such floats the order of the bit patterns read as unsigned integers is
+// the order of the values, so one integer max or min returns exactly what
+// fmax or fmin returns, without the instructions that quiet NaN operands
+// first.  Doubles keep fmax and fmin.
+__device__ __forceinline__ float pos_max(float a, float b) {
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ float pos_min(float a, float b) {
+    return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ double pos_max(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double pos_min(double a, double b) { return fmin(a, b); }
+
+// r from r^2 and ri = rsq(r^2), 0 at r^2 = 0 (where ri is +inf): in FP32,
+// ri capped at the largest finite float, which leaves every finite ri as it
+// is and turns 0 * inf into 0.
+__device__ __forceinline__ float r_of(float r2, float ri) {
+    return r2 * pos_min(ri, __FLT_MAX__);
+}
+__device__ __forceinline__ double r_of(double r2, double ri) { return r2 > 0.0 ? r2 * ri : 0.0; }
+
 // Softened force and potential factors for r^2 < h^2 (M4 cubic spline with
 // support h): F = q(u)/r^3, P = psi(u)/h, u = r/h; both branches evaluated,
 // the inner one selected for u < 1/2.  Taken from quantities the pair
@@ -26,7 +49,7 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 // no further reciprocal or square root is needed.
 template <typename R>
 __device__ __forceinline__ void soft_FP_ri(R r2, R ri, R h, R hinv, R &F, R &P) {
-    const R r = r2 > R(0) ? r2 * ri : R(0);
+    const R r = r_of(r2, ri);
     const R u = r * hinv;
     const R u2 = u * u;
     const R hinv3 = hinv * hinv * hinv;

@@ -93,8 +93,8 @@ __device__ __forceinline__ void node_term(const XNode<typename FormT<FORM>::R> &
                                           typename FormT<FORM>::R (&b)[kX]) {
     using R = typename FormT<FORM>::R;
     // g and phi with the node expansion of ORDER (r = target - centre of mass)
-    multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz, s.qyz, b[0],
-                        b[1], b[2], b[3]);
+    multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz, s.qyz,
+                        -(s.qxx + s.qyy), b[0], b[1], b[2], b[3]);
     // T and j from the monopole (d = centre of mass - target)
     const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
     const R r2 = dx * dx + dy * dy + dz * dz;

@@ -44,7 +44,8 @@ struct WalkLds {
 };
 
 template <typename R> struct alignas(16) PPStage { R x, y, z, m, h2, h, hinv; int32_t idx; };
-template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz; };
+// qzz = -(qxx + qyy) (Q is traceless), formed once when the node is staged.
+template <typename R> struct alignas(16) PCStage { R x, y, z, M, qxx, qyy, qxy, qxz, qyz, qzz; };
 // One batch is staged at a time, so the particle and node stages share LDS.
 // Particle batches of the FP32 forms hold up to 128 entries.
 template <typename R> constexpr uint32_t kPPBatch = sizeof(R) == 4 ? 128u : 64u;
@@ -68,9 +69,9 @@ __device__ __forceinline__ void pair(R dx, R dy, R dz, R m, R hj2, R hj, R hjinv
     const R ri = rsq(r2);
     R P = ri;
     R F = ri * ri * ri;
-    const R hh2 = fmax(hj2, ti2);
+    const R hh2 = pos_max(hj2, ti2);
     if (r2 < hh2) {
-        soft_FP_ri<R>(r2, ri, fmax(hj, ti), fmin(hjinv, tiinv), F, P);
+        soft_FP_ri<R>(r2, ri, pos_max(hj, ti), pos_min(hjinv, tiinv), F, P);
         if (SELF && self) { F = R(0); P = R(0); }
     }
     const R mF = m * F;
@@ -100,10 +101,10 @@ __device__ __forceinline__ void pair_newton(R dx, R dy, R dz, R m, R &bx, R &by,
     bz += mri3 * dz;
 }
 
-// Multipole term: r = target - centre of mass.
+// Multipole term: r = target - centre of mass; qzz = -(qxx + qyy).
 template <typename R, int ORDER>
 __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R qxy, R qxz, R qyz,
-                                          R &bx, R &by, R &bz, R &bp) {
+                                          R qzz, R &bx, R &by, R &bz, R &bp) {
     const R r2 = rx * rx + ry * ry + rz * rz;
     const R ri = rsq(r2);
     const R ri2 = ri * ri;
@@ -115,7 +116,6 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
         bz += c * rz;
         bp -= Mri;
     } else {
-        const R qzz = -(qxx + qyy);
         const R qx = qxx * rx + qxy * ry + qxz * rz;
         const R qy = qxy * rx + qyy * ry + qyz * rz;
         const R qz = qxz * rx + qyz * ry + qzz * rz;

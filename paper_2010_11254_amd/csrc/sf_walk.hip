@@ -97,6 +97,7 @@ struct GroupEval {
                 s.qxz = (R)nd.q[node].q[3];
                 s.qyz = (R)nd.q[node].q[4];
             }
+            s.qzz = -(s.qxx + s.qyy);
             spc[e] = s;
         }
         __syncthreads();
@@ -108,12 +109,12 @@ struct GroupEval {
         for (uint32_t j = 0; j < mf; ++j) {
             const PCStage<R> s = src[j * k];
             multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
-                                s.qyz, bx, by, bz, bp);
+                                s.qyz, s.qzz, bx, by, bz, bp);
         }
         if (sub + mf * k < nb) {
             const PCStage<R> s = src[mf * k];
             multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz,
-                                s.qyz, bx, by, bz, bp);
+                                s.qyz, s.qzz, bx, by, bz, bp);
         }
         ax.fold(bx);
         ay.fold(by);
@@ -341,7 +342,7 @@ struct SinkEval {
                 qyz = (R)nd.q[node].q[4];
             }
             multipole<R, ORDER>(tx - cx, ty - cy, tz - cz, (R)nd.w[node].M, qxx, qyy, qxy, qxz, qyz,
-                                bx, by, bz, bp);
+                                -(qxx + qyy), bx, by, bz, bp);
         }
         ax.fold(bx);
         ay.fold(by);
