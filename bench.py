@@ -72,6 +72,7 @@ SORT_BYTES_PER_PARTICLE = 12 + 24 + 8 + 8 * 24 + 44 + 24
 # 128 + 48 bytes: 20), the groups (2 per 21.7 particles: negligible) and the
 # outputs (acc and pot: 16).
 WALK_BYTES_PER_PARTICLE = 20 + 20 + 16
+SIDE_PHASES = ("sinksink", "sinkwalk")   # timers of the library's second stream
 # Relative (acceleration-based) opening criterion tolerances: quadrupole
 # workloads, and the monopole uniform sphere.
 ALPHA = 0.003
@@ -304,6 +305,11 @@ class TreeLeg:
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         walk = phase.get("walk", [])
+        # the sink-sink sum and the sink walk run on the library's second
+        # stream beside the group walk: their event intervals include waiting
+        # for execution slots that the walk holds, so they are kept apart
+        # from the serial phases
+        self.side_spans = {k: float(np.mean(phase.pop(k))) for k in SIDE_PHASES if k in phase}
         self.step_stats = {"ms_median": float(np.median(per_step)), "ms_min": float(np.min(per_step)),
                            "walk_ms_median": float(np.median(walk)) if walk else None,
                            "walk_ms_min": float(np.min(walk)) if walk else None}
@@ -665,6 +671,9 @@ def main():
                      "n_pc": n_pc, "n_pp": n_pp},
         "cpu_baseline": cpu,
         "phases_ms": ph32,
+        # second-stream intervals, fork to join, waiting included (not kernel
+        # cost; the standalone sink work is tree_pass_extras.sinks_pass_ms)
+        "side_stream_span_ms": head.side_spans,
         # per timed step (each synchronised): median and minimum beside the mean
         "step_stats": step_stats,
         # the whole step against its ideal time at peak: algorithmic walk FLOP
