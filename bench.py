@@ -201,7 +201,11 @@ class ClockSampler:
     """Samples the GPU's graphics clock with `amd-smi` in a background thread
     while a leg runs (a child process, started and waited for; None when the
     tool is missing).  The clock is recorded because the VALU peaks assume
-    2.4 GHz."""
+    2.4 GHz.  Off in profiling runs (`--no-cpu`): a profiler preloads itself
+    into child programs too, and `amd-smi` is a script whose interpreter is
+    started by exec from such a child."""
+
+    enabled = True
 
     def __init__(self):
         import threading
@@ -231,12 +235,14 @@ class ClockSampler:
             self.mhz.append(v)
 
     def __enter__(self):
-        self._thread.start()
+        if ClockSampler.enabled:
+            self._thread.start()
         return self
 
     def __exit__(self, *exc):
         self._stop.set()
-        self._thread.join(timeout=15)
+        if self._thread.is_alive():
+            self._thread.join(timeout=15)
 
     def summary(self):
         import numpy as np
@@ -352,12 +358,15 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--alpha", type=float, default=ALPHA,
                     help="relative opening criterion of the headline (negative: off)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle and the clock sampler (profiling runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline FP32C steps (profiling runs)")
     ap.add_argument("--no-fractal", action="store_true", help="skip the 16M fractal workload")
     ap.add_argument("--with-adjoint", action="store_true",
                     help="with --headline-only: one FP32C adjoint on a headline handle (profiling)")
+    ap.add_argument("--with-direct", action="store_true",
+                    help="with --headline-only: the direct path in each form (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB elementwise copy first (calibrates HBM byte counters)")
     ap.add_argument("--leaf-cap", type=int, default=32)
@@ -383,6 +392,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     alpha = args.alpha if args.alpha >= 0 else None
+    ClockSampler.enabled = not args.no_cpu
     g = Gpu(np, torch, L)
 
     # the oracle runs beside the GPU legs, on all host threads but two
@@ -423,6 +433,7 @@ def main():
     log(f"tree: {info['n_nodes']} nodes, {info['n_groups']} groups, max level {info['max_level']}; "
         f"interactions/target: {n_pc / ps.n_gas:.0f} node + {n_pp / ps.n_gas:.0f} particle")
     wall32, ph32 = head.timed(args.steps, args.warmup)
+    side32 = head.side_spans
     step_stats = head.step_stats
     keep("precision4m", "tree_fp32c", head.last)
     clocks = {}
@@ -515,34 +526,9 @@ def main():
             f"{extra['sink_hermite_step_ms']:.3f} ms ({ps.n_sink} sinks)")
         del vel, lum, sx, sm_, sh, sv
 
-        # direct path: one evaluation per form over all pairs
-        pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
-        acc, pot = head.acc[0], head.pot
-        for form in ("fp32c", "fp32", "fp64"):
-            o = L.make_opts(form=form, n_gas=ps.n_gas)
-            k = 65536
-            L.sf_grav_accel(None, x[:k].contiguous(), m[:k].contiguous(), h[:k].contiguous(),
-                            L.make_opts(form=form, n_gas=k), acc=acc[:k], pot=pot[:k])  # warm
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            with ClockSampler() as cs:   # the graphics clock during the evaluation
-                a.record()
-                L.sf_grav_accel(None, x, m, h, o, acc=acc, pot=pot)
-                b.record()
-                torch.cuda.synchronize()
-            if form == "fp32c":
-                clocks["direct_fp32c"] = cs.summary()
-            ms = a.elapsed_time(b)
-            keep("precision4m", "direct_" + form, acc)
-            tf = FLOP_PP * pairs / (ms * 1e-3) / 1e12
-            peak = PEAK_FP64_TFLOPS if form == "fp64" else PEAK_FP32_TFLOPS
-            direct[form] = {"ms": ms, "value": ps.n / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
-                            "achieved_tflops": tf, "peak": peak, "frac": tf / peak}
-            if form != "fp64":
-                direct[form]["frac_nonpacked"] = tf / PEAK_FP32_NONPACKED_TFLOPS
-            log(f"direct {form}: {ms:.1f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, {tf:.1f} TFLOP/s")
-        direct["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+        direct = direct_leg(g, ps, x, m, h, head, keep, clocks)
+    if args.headline_only and args.with_direct:
+        direct = direct_leg(g, ps, x, m, h, head, keep, clocks)
     if args.headline_only and args.with_adjoint:
         ga, gp = (torch.as_tensor(v).to(g.dev) for v in cotangents(ps.n, seed=2, dtype=np.float32))
         t, o = head.handle()
@@ -673,7 +659,7 @@ def main():
         "phases_ms": ph32,
         # second-stream intervals, fork to join, waiting included (not kernel
         # cost; the standalone sink work is tree_pass_extras.sinks_pass_ms)
-        "side_stream_span_ms": head.side_spans,
+        "side_stream_span_ms": side32,
         # per timed step (each synchronised): median and minimum beside the mean
         "step_stats": step_stats,
         # the whole step against its ideal time at peak: algorithmic walk FLOP
@@ -714,6 +700,41 @@ def main():
 def make_workload_size(name):
     return {"uniform4k": 4096, "clustered1m": (1 << 20) + 256, "precision4m": (1 << 22) + 4096,
             "fractal16m": (1 << 24) + 10000}[name]
+
+
+def direct_leg(g, ps, x, m, h, head, keep, clocks):
+    """Direct path at the workload's full size: one evaluation per form over
+    all pairs, timed with HIP events, outputs kept for the error check."""
+    L, torch = g.L, g.torch
+    direct = {}
+    pairs = ps.n_gas * ps.n + ps.n_sink * ps.n_gas
+    acc, pot = head.acc[0], head.pot
+    for form in ("fp32c", "fp32", "fp64"):
+        o = L.make_opts(form=form, n_gas=ps.n_gas)
+        k = 65536
+        L.sf_grav_accel(None, x[:k].contiguous(), m[:k].contiguous(), h[:k].contiguous(),
+                        L.make_opts(form=form, n_gas=k), acc=acc[:k], pot=pot[:k])  # warm
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        with ClockSampler() as cs:   # the graphics clock during the evaluation
+            a.record()
+            L.sf_grav_accel(None, x, m, h, o, acc=acc, pot=pot)
+            b.record()
+            torch.cuda.synchronize()
+        if form == "fp32c":
+            clocks["direct_fp32c"] = cs.summary()
+        ms = a.elapsed_time(b)
+        keep("precision4m", "direct_" + form, acc)
+        tf = FLOP_PP * pairs / (ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if form == "fp64" else PEAK_FP32_TFLOPS
+        direct[form] = {"ms": ms, "value": ps.n / (ms * 1e-3), "pairs_per_s": pairs / (ms * 1e-3),
+                        "achieved_tflops": tf, "peak": peak, "frac": tf / peak}
+        if form != "fp64":
+            direct[form]["frac_nonpacked"] = tf / PEAK_FP32_NONPACKED_TFLOPS
+        log(f"direct {form}: {ms:.1f} ms, {pairs / (ms * 1e-3):.3e} pairs/s, {tf:.1f} TFLOP/s")
+    direct["fp32c_over_fp64"] = direct["fp64"]["ms"] / direct["fp32c"]["ms"]
+    return direct
 
 
 def fractal_leg(g, caps, alpha, keep):
