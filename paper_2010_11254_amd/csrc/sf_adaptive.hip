@@ -125,7 +125,7 @@ struct SumsEval {
                 const R r2 = dx * dx + dy * dy + dz * dz;
                 if (!s.gas || !(r2 < th * th)) return;
                 const R ri = rsq(r2);
-                const R r = r2 > R(0) ? r2 * ri : R(0);
+                const R r = r_of(r2, ri);
                 R W, Wr, Wh;
                 m4<R>(r, thinv, W, Wr, Wh);
                 sW += W;
@@ -222,7 +222,7 @@ struct ForceEval {
                     kern<R>(r2, ri, s.h, Fj, Pj, Phj);
                     F = R(0.5) * (Fi + Fj);
                     P = R(0.5) * (Pi + Pj);
-                    const R r = r2 > R(0) ? r2 * ri : R(0);
+                    const R r = r_of(r2, ri);
                     if (r > R(0)) {
                         R W, Wri, Wh, Wrj;
                         Wri = Wrj = R(0);

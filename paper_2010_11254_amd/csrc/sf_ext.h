@@ -33,19 +33,23 @@ __device__ __forceinline__ void ext_term(R dx, R dy, R dz, R wx, R wy, R wz, R m
     }
 }
 
-// Particle pair with softening test and self exclusion.
-template <typename R, bool JERK>
+// Particle pair with softening test and self exclusion.  SOFT = false:
+// the caller knows the pair is Newtonian (its source leaf lies at least the
+// larger softening length from the target box) and not a self pair.
+template <typename R, bool JERK, bool SOFT = true>
 __device__ __forceinline__ void ext_pair(R dx, R dy, R dz, R wx, R wy, R wz, R m, R hj, R ti,
                                          bool self, R (&b)[kX]) {
     const R r2 = dx * dx + dy * dy + dz * dz;
     const R ri = rsq(r2);
     R F = ri * ri * ri, P = ri, FrR = R(-3) * F * ri * ri;
-    const R hh = hj > ti ? hj : ti;
-    if (r2 < hh * hh) {
-        R dFh, dPh;
-        dsoft<R>(r2, hh, F, P, FrR, dFh, dPh);
+    if (SOFT) {
+        const R hh = pos_max(hj, ti);
+        if (r2 < hh * hh) {
+            R dFh, dPh;
+            dsoft<R>(r2, hh, F, P, FrR, dFh, dPh);
+        }
+        if (self) F = P = FrR = R(0);
     }
-    if (self) F = P = FrR = R(0);
     ext_term<R, JERK>(dx, dy, dz, wx, wy, wz, m * F, m * FrR, m * P, b, true);
 }
 

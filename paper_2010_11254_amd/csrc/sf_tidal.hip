@@ -160,8 +160,8 @@ struct GroupEvalX {
         if (on)
             sp.each(nb, [&](uint32_t j) {
                 const XPart<R> s = st->pp[j];
-                ext_pair<R, JERK>(s.x - tx, s.y - ty, s.z - tz, s.vx - tvx, s.vy - tvy, s.vz - tvz,
-                                  s.m, s.h, th, SOFT && s.idx == tidx, b);
+                ext_pair<R, JERK, SOFT>(s.x - tx, s.y - ty, s.z - tz, s.vx - tvx, s.vy - tvy,
+                                        s.vz - tvz, s.m, s.h, th, SOFT && s.idx == tidx, b);
             });
         fold(b);
         __syncthreads();
