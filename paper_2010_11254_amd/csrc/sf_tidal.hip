@@ -112,6 +112,7 @@ struct GroupEvalX {
     XStage<R> *st;
     double cen[3];
     R tx, ty, tz, th, tvx, tvy, tvz;
+    R bl[3], bh[3], hg2;        // group box in the form's frame, largest h squared
     int32_t tidx;
     bool on;                    // this lane holds a gas target
     Split sp;
@@ -135,12 +136,19 @@ struct GroupEvalX {
         __syncthreads();
     }
 
+    // Particle batches (nb <= 64).  A SOFT batch (leaves that may hold
+    // softened pairs) is split per source as in the force walk: a source
+    // farther from the group box than max(its h, the group's largest h), with
+    // a relative margin for the rounding of both distances, has only
+    // Newtonian pairs with the group; the others (the task's own particles
+    // among them) are staged first and take the softened form.
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const uint32_t e = threadIdx.x;
+        XPart<R> s;
+        bool soft = false;
         if (e < nb) {
             const int p = L.slot[e];
-            XPart<R> s;
             s.x = to_frame<FORM>(a->xs[p], cen[0]);
             s.y = to_frame<FORM>(a->ys[p], cen[1]);
             s.z = to_frame<FORM>(a->zs[p], cen[2]);
@@ -153,16 +161,39 @@ struct GroupEvalX {
                 s.vz = (R)a->vz[p];
             }
             s.idx = p;
+            if (SOFT) {
+                const R gx = fmax(fmax(bl[0] - s.x, s.x - bh[0]), R(0));
+                const R gy = fmax(fmax(bl[1] - s.y, s.y - bh[1]), R(0));
+                const R gz = fmax(fmax(bl[2] - s.z, s.z - bh[2]), R(0));
+                const R d2 = gx * gx + gy * gy + gz * gz;
+                soft = !(d2 > pos_max(s.h * s.h, hg2) * R(1.0001));
+            }
+        }
+        uint32_t ns = 0;   // entries [0, ns) may hold softened pairs
+        if (SOFT) {
+            const uint64_t msoft = __ballot(e < nb && soft);
+            const uint64_t mnewt = __ballot(e < nb && !soft);
+            const uint64_t lt = lane_mask_lt();
+            ns = (uint32_t)popc64(msoft);
+            if (e < nb) st->pp[soft ? popc64(msoft & lt) : ns + popc64(mnewt & lt)] = s;
+        } else if (e < nb) {
             st->pp[e] = s;
         }
         __syncthreads();
         R b[kX] = {};
-        if (on)
-            sp.each(nb, [&](uint32_t j) {
-                const XPart<R> s = st->pp[j];
-                ext_pair<R, JERK, SOFT>(s.x - tx, s.y - ty, s.z - tz, s.vx - tvx, s.vy - tvy,
-                                        s.vz - tvz, s.m, s.h, th, SOFT && s.idx == tidx, b);
+        if (on) {
+            sp.each(nb - ns, [&](uint32_t j) {
+                const XPart<R> q = st->pp[ns + j];
+                ext_pair<R, JERK, false>(q.x - tx, q.y - ty, q.z - tz, q.vx - tvx, q.vy - tvy,
+                                         q.vz - tvz, q.m, q.h, th, false, b);
             });
+            if (SOFT)
+                sp.each(ns, [&](uint32_t j) {
+                    const XPart<R> q = st->pp[j];
+                    ext_pair<R, JERK, true>(q.x - tx, q.y - ty, q.z - tz, q.vx - tvx, q.vy - tvy,
+                                            q.vz - tvz, q.m, q.h, th, q.idx == tidx, b);
+                });
+        }
         fold(b);
         __syncthreads();
     }
@@ -216,6 +247,14 @@ __global__ __launch_bounds__(64) void k_walk_groups_x(WalkArgsX<T> a) {
             ev.tvz = (R)a.vz[i];
         }
         ev.tidx = (int32_t)i;
+        for (int d = 0; d < 3; ++d) {
+            ev.bl[d] = dto_frame<FORM>(blo[d], ev.cen[d]);
+            ev.bh[d] = dto_frame<FORM>(bhi[d], ev.cen[d]);
+        }
+        {
+            const R hgr = (R)a.ghmax[g];
+            ev.hg2 = hgr * hgr;
+        }
         for (int c = 0; c < kX; ++c) ev.acc[c].zero();
         uint32_t npc, npp;
         uint64_t cks;
