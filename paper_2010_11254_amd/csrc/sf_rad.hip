@@ -50,12 +50,20 @@ struct alignas(16) RadEntry {
 
 template <typename R>
 __device__ __forceinline__ void add_col(R dx, R dy, R dz, R w, R (&b)[kR]) {
+    // dominant axis (ties to the lower axis), then the sign of d along it
+    // (-0 counts as positive); each bin's condition is formed from the
+    // comparisons as a lane mask, so a bin costs one select and one add
     const R ax = fabs(dx), ay = fabs(dy), az = fabs(dz);
-    const int axis = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-    const R s = axis == 0 ? dx : (axis == 1 ? dy : dz);
-    const int bin = 2 * axis + (s < R(0) ? 1 : 0);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) b[k] += bin == k ? w : R(0);
+    const bool xm = ax >= ay && ax >= az;
+    const bool ym = !xm && ay >= az;
+    const bool zm = !xm && !ym;
+    const bool nx = dx < R(0), ny = dy < R(0), nz = dz < R(0);
+    b[0] += (xm && !nx) ? w : R(0);
+    b[1] += (xm && nx) ? w : R(0);
+    b[2] += (ym && !ny) ? w : R(0);
+    b[3] += (ym && ny) ? w : R(0);
+    b[4] += (zm && !nz) ? w : R(0);
+    b[5] += (zm && nz) ? w : R(0);
 }
 
 template <typename T, int FORM>
