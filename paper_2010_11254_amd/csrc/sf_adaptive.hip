@@ -148,6 +148,7 @@ struct ForceEval {
     AdStage<R> *st;
     double cen[3];
     R tx, ty, tz, th, tminv, tz_;   // tminv = 1/m of the target; tz_: its zeta / Omega
+    R bl[3], bh[3], hg2;            // group box in the form's frame, largest h squared
     int32_t tidx;
     bool on;
     Split sp;
@@ -181,12 +182,20 @@ struct ForceEval {
         __syncthreads();
     }
 
+    // Particle batches (nb <= 64).  A SOFT batch (leaves that may hold
+    // softened pairs) is split per source as in the force walk: a source
+    // farther from the group box than max(its h, the group's largest h), with
+    // a relative margin for the rounding of both distances, is beyond both
+    // softening lengths of every pair it forms with the group, so its terms
+    // are Newtonian with no extra term; the others (the task's own particles
+    // among them) are staged first and take the symmetrised law.
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
         const uint32_t e = threadIdx.x;
+        AdPart<R> s;
+        bool soft = false;
         if (e < nb) {
             const int p = L.slot[e];
-            AdPart<R> s;
             s.x = to_frame<FORM>(a->xs[p], cen[0]);
             s.y = to_frame<FORM>(a->ys[p], cen[1]);
             s.z = to_frame<FORM>(a->zs[p], cen[2]);
@@ -195,51 +204,71 @@ struct ForceEval {
             s.zz = (R)a->z[p];
             s.idx = p;
             s.gas = a->order[p] < a->n_gas ? 1 : 0;
+            if (SOFT) {
+                const R gx = fmax(fmax(bl[0] - s.x, s.x - bh[0]), R(0));
+                const R gy = fmax(fmax(bl[1] - s.y, s.y - bh[1]), R(0));
+                const R gz = fmax(fmax(bl[2] - s.z, s.z - bh[2]), R(0));
+                const R d2 = gx * gx + gy * gy + gz * gz;
+                soft = !(d2 > pos_max(s.h * s.h, hg2) * R(1.0001));
+            }
+        }
+        uint32_t ns = 0;   // entries [0, ns) may hold softened pairs
+        if (SOFT) {
+            const uint64_t msoft = __ballot(e < nb && soft);
+            const uint64_t mnewt = __ballot(e < nb && !soft);
+            const uint64_t lt = lane_mask_lt();
+            ns = (uint32_t)popc64(msoft);
+            if (e < nb) st->pp[soft ? popc64(msoft & lt) : ns + popc64(mnewt & lt)] = s;
+        } else if (e < nb) {
             st->pp[e] = s;
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
-        if (on)
-            sp.each(nb, [&](uint32_t j) {
-                const AdPart<R> s = st->pp[j];
-                const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
-                const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ri = rsq(r2);
-                if (!SOFT) {   // both radii below r: Newtonian, no extra terms
-                    const R mri = s.m * ri, mri3 = mri * ri * ri;
-                    bp -= mri;
-                    bx += mri3 * dx;
-                    by += mri3 * dy;
-                    bz += mri3 * dz;
-                    return;
-                }
-                if (s.idx == tidx) return;
-                R F, P;
-                R c = R(0);   // extra term over r
-                if (s.gas) {
-                    R Fi, Pi, Phi, Fj, Pj, Phj;
-                    kern<R>(r2, ri, th, Fi, Pi, Phi);
-                    kern<R>(r2, ri, s.h, Fj, Pj, Phj);
-                    F = R(0.5) * (Fi + Fj);
-                    P = R(0.5) * (Pi + Pj);
-                    const R r = r_of(r2, ri);
-                    if (r > R(0)) {
-                        R W, Wri, Wh, Wrj;
-                        Wri = Wrj = R(0);
-                        if (r < th) m4<R>(r, rcp(th), W, Wri, Wh);
-                        if (r < s.h) m4<R>(r, rcp(s.h), W, Wrj, Wh);
-                        c = R(0.5) * (tz_ * Wri + s.m * tminv * s.zz * Wrj) * ri;
-                    }
-                } else {
-                    R Ph;
-                    kern<R>(r2, ri, th > s.h ? th : s.h, F, P, Ph);
-                }
-                const R k = s.m * F - c;
-                bx += k * dx;
-                by += k * dy;
-                bz += k * dz;
-                bp -= s.m * P;
+        if (on) {
+            sp.each(nb - ns, [&](uint32_t j) {   // both radii below r: Newtonian, no extra terms
+                const AdPart<R> q = st->pp[ns + j];
+                const R dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
+                const R ri = rsq(dx * dx + dy * dy + dz * dz);
+                const R mri = q.m * ri, mri3 = mri * ri * ri;
+                bp -= mri;
+                bx += mri3 * dx;
+                by += mri3 * dy;
+                bz += mri3 * dz;
             });
+            if (SOFT)
+                sp.each(ns, [&](uint32_t j) {
+                    const AdPart<R> q = st->pp[j];
+                    if (q.idx == tidx) return;
+                    const R dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const R ri = rsq(r2);
+                    R F, P;
+                    R c = R(0);   // extra term over r
+                    if (q.gas) {
+                        R Fi, Pi, Phi, Fj, Pj, Phj;
+                        kern<R>(r2, ri, th, Fi, Pi, Phi);
+                        kern<R>(r2, ri, q.h, Fj, Pj, Phj);
+                        F = R(0.5) * (Fi + Fj);
+                        P = R(0.5) * (Pi + Pj);
+                        const R r = r_of(r2, ri);
+                        if (r > R(0)) {
+                            R W, Wri, Wh, Wrj;
+                            Wri = Wrj = R(0);
+                            if (r < th) m4<R>(r, rcp(th), W, Wri, Wh);
+                            if (r < q.h) m4<R>(r, rcp(q.h), W, Wrj, Wh);
+                            c = R(0.5) * (tz_ * Wri + q.m * tminv * q.zz * Wrj) * ri;
+                        }
+                    } else {
+                        R Ph;
+                        kern<R>(r2, ri, th > q.h ? th : q.h, F, P, Ph);
+                    }
+                    const R k = q.m * F - c;
+                    bx += k * dx;
+                    by += k * dy;
+                    bz += k * dz;
+                    bp -= q.m * P;
+                });
+        }
         ax.fold(bx);
         ay.fold(by);
         az.fold(bz);
@@ -337,6 +366,14 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         if (!group_target(a, ev, g, i, blo, bhi)) continue;
         ev.tminv = rcp((R)a.ms[i]);
         ev.tz_ = (R)a.z[i];
+        for (int d = 0; d < 3; ++d) {
+            ev.bl[d] = dto_frame<FORM>(blo[d], ev.cen[d]);
+            ev.bh[d] = dto_frame<FORM>(bhi[d], ev.cen[d]);
+        }
+        {
+            const R hgr = (R)a.ghmax[g];
+            ev.hg2 = hgr * hgr;
+        }
         ev.ax.zero();
         ev.ay.zero();
         ev.az.zero();
