@@ -79,8 +79,10 @@ struct AdArgs {
 
 template <typename R> struct alignas(16) AdPart { R x, y, z, m, h, zz; int32_t idx, gas; };
 template <typename R> struct alignas(16) AdNode { R x, y, z, M, q[5]; };
+// Particle batches of the force pass hold up to kPPBatch<R> entries (128 in
+// the FP32 forms, as in the force walk); the neighbour sums use 64.
 template <typename R> union AdStage {
-    AdPart<R> pp[64];
+    AdPart<R> pp[kPPBatch<R>];
     AdNode<R> nd[64];
 };
 // the copies' partial sums (up to 4 per lane) go through the stage
@@ -182,45 +184,52 @@ struct ForceEval {
         __syncthreads();
     }
 
-    // Particle batches (nb <= 64).  A SOFT batch (leaves that may hold
-    // softened pairs) is split per source as in the force walk: a source
-    // farther from the group box than max(its h, the group's largest h), with
-    // a relative margin for the rounding of both distances, is beyond both
-    // softening lengths of every pair it forms with the group, so its terms
-    // are Newtonian with no extra term; the others (the task's own particles
-    // among them) are staged first and take the symmetrised law.
+    // Particle batches (nb <= kPPBatch<R>), staged 64 entries per round.  A
+    // SOFT batch (leaves that may hold softened pairs) is split per source as
+    // in the force walk: a source farther from the group box than max(its h,
+    // the group's largest h), with a relative margin for the rounding of both
+    // distances, is beyond both softening lengths of every pair it forms with
+    // the group, so its terms are Newtonian with no extra term; the others
+    // (the task's own particles among them) fill the stage from the start and
+    // take the symmetrised law, the Newtonian ones fill it from the end.
     template <bool SOFT>
     __device__ void pp_batch(WalkLds &L, uint32_t nb) {
-        const uint32_t e = threadIdx.x;
-        AdPart<R> s;
-        bool soft = false;
-        if (e < nb) {
-            const int p = L.slot[e];
-            s.x = to_frame<FORM>(a->xs[p], cen[0]);
-            s.y = to_frame<FORM>(a->ys[p], cen[1]);
-            s.z = to_frame<FORM>(a->zs[p], cen[2]);
-            s.m = (R)a->ms[p];
-            s.h = (R)a->hs[p];
-            s.zz = (R)a->z[p];
-            s.idx = p;
-            s.gas = a->order[p] < a->n_gas ? 1 : 0;
-            if (SOFT) {
-                const R gx = fmax(fmax(bl[0] - s.x, s.x - bh[0]), R(0));
-                const R gy = fmax(fmax(bl[1] - s.y, s.y - bh[1]), R(0));
-                const R gz = fmax(fmax(bl[2] - s.z, s.z - bh[2]), R(0));
-                const R d2 = gx * gx + gy * gy + gz * gz;
-                soft = !(d2 > pos_max(s.h * s.h, hg2) * R(1.0001));
+        uint32_t ns = 0, nn = 0;   // entries [0, ns) may hold softened pairs
+        for (uint32_t r = 0; r < nb; r += 64u) {
+            const uint32_t e = r + threadIdx.x;
+            AdPart<R> s;
+            bool soft = false;
+            if (e < nb) {
+                const int p = L.slot[e];
+                s.x = to_frame<FORM>(a->xs[p], cen[0]);
+                s.y = to_frame<FORM>(a->ys[p], cen[1]);
+                s.z = to_frame<FORM>(a->zs[p], cen[2]);
+                s.m = (R)a->ms[p];
+                s.h = (R)a->hs[p];
+                s.zz = (R)a->z[p];
+                s.idx = p;
+                s.gas = a->order[p] < a->n_gas ? 1 : 0;
+                if (SOFT) {
+                    const R gx = fmax(fmax(bl[0] - s.x, s.x - bh[0]), R(0));
+                    const R gy = fmax(fmax(bl[1] - s.y, s.y - bh[1]), R(0));
+                    const R gz = fmax(fmax(bl[2] - s.z, s.z - bh[2]), R(0));
+                    const R d2 = gx * gx + gy * gy + gz * gz;
+                    soft = !(d2 > pos_max(s.h * s.h, hg2) * R(1.0001));
+                }
             }
-        }
-        uint32_t ns = 0;   // entries [0, ns) may hold softened pairs
-        if (SOFT) {
-            const uint64_t msoft = __ballot(e < nb && soft);
-            const uint64_t mnewt = __ballot(e < nb && !soft);
-            const uint64_t lt = lane_mask_lt();
-            ns = (uint32_t)popc64(msoft);
-            if (e < nb) st->pp[soft ? popc64(msoft & lt) : ns + popc64(mnewt & lt)] = s;
-        } else if (e < nb) {
-            st->pp[e] = s;
+            if (SOFT) {
+                const uint64_t msoft = __ballot(e < nb && soft);
+                const uint64_t mnewt = __ballot(e < nb && !soft);
+                const uint64_t lt = lane_mask_lt();
+                if (e < nb) {
+                    if (soft) st->pp[ns + (uint32_t)popc64(msoft & lt)] = s;
+                    else st->pp[nb - 1u - (nn + (uint32_t)popc64(mnewt & lt))] = s;
+                }
+                ns += (uint32_t)popc64(msoft);
+                nn += (uint32_t)popc64(mnewt);
+            } else if (e < nb) {
+                st->pp[e] = s;
+            }
         }
         __syncthreads();
         R bx = 0, by = 0, bz = 0, bp = 0;
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         uint64_t cks;
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
-                         task_ag_group(a.nd, g), a.err, npc, npp, cks);
+                         task_ag_group(a.nd, g), a.err, npc, npp, cks, kPPBatch<R>);
         double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
         ev.sp.template reduce<4>(v, reinterpret_cast<double *>(&stage), (uint32_t)threadIdx.x);
         if (ev.on && threadIdx.x < ev.sp.gc) {
