@@ -79,3 +79,34 @@ def test_rad_sums_fp32c():
     assert np.median(e) < 1e-6 and e.max() < 1e-4
     ee = np.abs(eir[g] - eirr[g]) / eirr[g]
     assert np.median(ee) < 1e-6 and ee.max() < 1e-4
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_rad_columns_lattice_ties(form):
+    """Gas on an integer lattice: from every cell many directions lie exactly
+    on a boundary between faces, and the differences are exact in both forms
+    (in FP32C the group frames are centred on multiples of 1/2).  At theta 0
+    every bin of every cell must match the oracle's direct columns: the tie
+    rule (lower axis first, zero counted positive) is checked bin by bin."""
+    _say("rad lattice ties", form)
+    dt = np.float64 if form == "fp64" else np.float32
+    g = np.arange(5, dtype=np.float64)
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(dt)
+    n = x.shape[0]
+    m = np.full(n, 1.0, dt)
+    h = np.full(n, 0.7, dt)
+    L = _lib()
+    X, M, H = _dev(x, m, h)
+    o = L.make_opts(form=form, theta=0.0, order=2, leaf_cap=16, group_cap=32, n_gas=n)
+    t = L.sf_grav_build_tree(X, M, H, o)
+    col, _ = L.sf_grav_rad_sums(t, o, lum=torch.zeros(n, dtype=X.dtype, device=X.device),
+                                c_light=1.0)
+    torch.cuda.synchronize()
+    L.sf_grav_tree_free(t)
+    col = col.double().cpu().numpy()
+    ref = orad.columns_direct(x.astype(np.float64), m.astype(np.float64),
+                              h.astype(np.float64), n)
+    # every cell has mass in some bins and none in others; both must agree
+    assert np.array_equal(col > 0, ref > 0)
+    rtol = 1e-12 if form == "fp64" else 2e-6
+    assert np.max(np.abs(col - ref) / ref.sum(1, keepdims=True)) < rtol

@@ -23,6 +23,15 @@ def test_bins_are_cube_faces():
     assert list(rad.bin_of(d)) == [0, 1, 2, 3, 4, 5]
 
 
+def test_bins_on_face_boundaries():
+    # a direction on a boundary between faces goes to the lower axis, and a
+    # zero component along the chosen axis counts as positive (the reading
+    # the GPU walk uses too)
+    d = np.array([[1.0, 1.0, 0.0], [-1.0, 1.0, 0.0], [0.0, 1.0, 1.0], [0.0, -1.0, 1.0],
+                  [1.0, -1.0, -1.0], [-1.0, -1.0, -1.0], [0.0, 0.0, -2.0], [0.0, 0.0, 0.0]])
+    assert list(rad.bin_of(d)) == [0, 1, 2, 3, 0, 1, 5, 0]
+
+
 def test_uniform_sphere_centre_column():
     n = 200000
     rng = np.random.default_rng(3)
