@@ -1,0 +1,181 @@
+"""GPU parity of the tree passes beyond g and phi at the precision4m workload's
+full size (4,194,304 clustered gas + 2048 sink binaries, seed 2), in the
+benchmark's launch configuration (leaf 32, group 32, theta 0.5, quadrupole):
+the tidal tensor and jerk, and the radiation sums (6-bin columns, IR energy
+density), on the targets of sampled groups against the oracle's frozen-list
+evaluation of the same groups.  The GPU's opening decisions are checked equal
+to the oracle's first, through the per-group list counts of the force pass,
+which the other passes share.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rad as orad
+from oracle import tree as otree
+from synth import precision_cloud
+
+pytestmark = pytest.mark.gpu
+
+LEAF, GROUP = 32, 32   # the benchmark's capacities
+
+
+def _lib():
+    from paper_2010_11254_amd import _lib
+    return _lib
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(*arrs):
+    return [torch.as_tensor(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def _rowerr(a, ref):
+    return np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    _say("generating precision4m")
+    return precision_cloud(1 << 22, 2048, seed=2)
+
+
+@pytest.fixture(scope="module")
+def sampled(c2):
+    """Oracle lists of 6 random groups and 2 groups holding sinks."""
+    x64, m64, h64 = (v.astype(np.float64) for v in (c2.x, c2.m, c2.h))
+    _say("oracle tree", c2.n)
+    tree = otree.build_tree(x64, LEAF)
+    groups = otree.make_groups(tree, GROUP)
+    sink_sorted = tree.order >= c2.n_gas
+    rng = np.random.default_rng(5)
+    with_sink = [g for g in range(groups.shape[0])
+                 if sink_sorted[groups[g, 0]:groups[g, 0] + groups[g, 1]].any()]
+    sel = sorted(set(rng.choice(groups.shape[0], 6, replace=False).tolist())
+                 | set(rng.choice(with_sink, 2, replace=False).tolist()))
+    _say("oracle lists of groups", sel)
+    lists = otree.tree_lists(x64, m64, h64, c2.n_gas, 0.5, LEAF, GROUP, groups_sel=sel, lazy=True)
+    return lists, sel
+
+
+@pytest.fixture(scope="module")
+def tidal_ref(c2, sampled):
+    """Velocities (exact in FP32, so both forms take the same values) and the
+    oracle's T and j of the sampled groups."""
+    lists, _ = sampled
+    v = np.random.default_rng(6).standard_normal((c2.n, 3)).astype(np.float32).astype(np.float64)
+    x64, m64, h64 = (u.astype(np.float64) for u in (c2.x, c2.m, c2.h))
+    _say("oracle tidal terms")
+    Tr, Jr = otree.tree_tidal(x64, m64, h64, v, c2.n_gas, lists)
+    return v, Tr, Jr
+
+
+@pytest.fixture(scope="module")
+def rad_ref(c2, sampled):
+    """Sink luminosities (exact in FP32) and the oracle's radiation sums of
+    three of the sampled groups (the oracle sums every accepted node per
+    target); one of them holds sinks, whose luminosity nodes and pairs then
+    take part."""
+    lists, sel = sampled
+    sink_sorted = lists.is_sink_sorted
+    has_sink = [g for g in sel
+                if sink_sorted[lists.groups[g][0]:lists.groups[g][0] + lists.groups[g][1]].any()]
+    use = sorted(set([g for g in sel if g not in has_sink][:2] + has_sink[:1]))
+    sub = copy.copy(lists)
+    sub.gas_lists = {g: lists.gas_lists[g] for g in use if g in lists.gas_lists}
+    rng = np.random.default_rng(7)
+    lum = np.where(np.arange(c2.n) >= c2.n_gas, np.exp(rng.normal(0, 1, c2.n)), 0.0)
+    lum = lum.astype(np.float32).astype(np.float64)
+    x64, m64, h64 = (u.astype(np.float64) for u in (c2.x, c2.m, c2.h))
+    _say("oracle radiation sums of groups", use)
+    colr, eirr = orad.tree_rad(x64, m64, h64, lum, c2.n_gas, sub, 1.0)
+    return lum, use, sub, colr, eirr
+
+
+def _targets(lists, groups_sel, n_gas):
+    """Caller indices of the gas targets of the given groups."""
+    tree = lists.tree
+    out = []
+    for g in groups_sel:
+        f, c = lists.groups[g]
+        idx = tree.order[f:f + c]
+        out.append(idx[idx < n_gas])
+    return np.concatenate(out)
+
+
+def _handle(c2, form, lists):
+    """A tree handle of the form's inputs whose list counts equal the
+    oracle's for every sampled group."""
+    L = _lib()
+    arrs = (c2.x, c2.m, c2.h) if form != "fp64" else tuple(v.astype(np.float64)
+                                                            for v in (c2.x, c2.m, c2.h))
+    x, m, h = _dev(*arrs)
+    o = L.make_opts(form=form, n_gas=c2.n_gas, collect_stats=True, leaf_cap=LEAF, group_cap=GROUP)
+    t = L.sf_grav_build_tree(x, m, h, o)
+    L.sf_grav_accel(t, None, None, None, o)
+    torch.cuda.synchronize()
+    npc = L.sf_grav_tree_export(t, "group_npc").numpy()
+    npp = L.sf_grav_tree_export(t, "group_npp").numpy()
+    for g, (pc, pp) in lists.gas_lists.items():
+        assert npc[g] == pc.size and npp[g] == pp.size, (form, g)
+    return t, o, x.dtype
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_precision4m_tidal_sampled_groups(c2, sampled, tidal_ref, form):
+    _say("precision4m tidal tensor and jerk, sampled groups", form)
+    lists, sel = sampled
+    v, Tr, Jr = tidal_ref
+    L = _lib()
+    t, o, dt = _handle(c2, form, lists)
+    vv = torch.as_tensor(v).to(dtype=dt, device="cuda").contiguous()
+    _, _, tid, jerk = L.sf_grav_accel_tidal(t, o, vel=vv)
+    torch.cuda.synchronize()
+    L.sf_grav_tree_free(t)
+    tg = _targets(lists, sel, c2.n_gas)
+    eT = _rowerr(tid.double().cpu().numpy()[tg], Tr[tg])
+    eJ = _rowerr(jerk.double().cpu().numpy()[tg], Jr[tg])
+    print(f"{form}: {tg.size} targets; T err median {np.median(eT):.2e} p99 "
+          f"{np.quantile(eT, 0.99):.2e}; j err median {np.median(eJ):.2e} p99 "
+          f"{np.quantile(eJ, 0.99):.2e}", flush=True)
+    assert tg.size > 100
+    if form == "fp64":
+        assert np.quantile(eT, 0.99) < 1e-10 and np.quantile(eJ, 0.99) < 1e-10
+    else:
+        assert np.median(eT) < 1e-5 and np.median(eJ) < 1e-5
+        assert np.quantile(eT, 0.99) < 2e-4 and np.quantile(eJ, 0.99) < 2e-4
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_precision4m_rad_sums_sampled_groups(c2, sampled, rad_ref, form):
+    _say("precision4m radiation sums, sampled groups", form)
+    lists, _ = sampled
+    lum, use, sub, colr, eirr = rad_ref
+    L = _lib()
+    t, o, dt = _handle(c2, form, lists)
+    lu = torch.as_tensor(lum).to(dtype=dt, device="cuda").contiguous()
+    col, eir = L.sf_grav_rad_sums(t, o, lum=lu, c_light=1.0)
+    torch.cuda.synchronize()
+    L.sf_grav_tree_free(t)
+    tg = _targets(sub, use, c2.n_gas)
+    col, eir = col.double().cpu().numpy()[tg], eir.double().cpu().numpy()[tg]
+    cr, er = colr[tg], eirr[tg]
+    tot = cr.sum(1)
+    et = np.abs(col.sum(1) - tot) / tot
+    ee = np.abs(eir - er) / er
+    print(f"{form}: {tg.size} targets; column total err max {et.max():.2e}; "
+          f"e_IR err max {ee.max():.2e}", flush=True)
+    assert tg.size > 20
+    if form == "fp64":
+        assert et.max() < 1e-12 and ee.max() < 1e-12
+        # a direction on a face boundary may fall in either face
+        bad = np.abs(col - cr).max(1) / tot > 1e-12
+        assert bad.sum() <= 1, bad.sum()
+    else:
+        assert np.median(et) < 1e-6 and et.max() < 1e-4
+        assert np.median(ee) < 1e-6 and ee.max() < 1e-4
