@@ -121,3 +121,68 @@ def pm_energy(x, m, h, G=1.0):
     """Total potential energy -(G/2) sum m_i m_j (P(r,h_i) + P(r,h_j))/2 (all gas)."""
     _, pot = pm_accel(x, m, h, G=G)
     return 0.5 * np.sum(np.asarray(m) * pot)
+
+
+def omega_zeta_at(x, m, h, idx, kd=None):
+    """Omega_i and zeta_i of the gas cells idx (x, m, h over gas cells only),
+    from their neighbours within h_i found by a k-d tree: W, dW/dh and dP/dh
+    vanish at and beyond h, so these are the sums of `omega_zeta`."""
+    from scipy.spatial import cKDTree
+    x, m, h = (np.asarray(v, np.float64) for v in (x, m, h))
+    kd = cKDTree(x) if kd is None else kd
+    om = np.empty(len(idx))
+    ze = np.empty(len(idx))
+    for k, i in enumerate(idx):
+        nb = np.asarray(kd.query_ball_point(x[i], h[i]), dtype=np.int64)
+        r = np.sqrt(((x[nb] - x[i]) ** 2).sum(1))
+        W, _, Wh = kernel_W(r, h[i])
+        dhdn = -h[i] / (3.0 * W.sum())
+        om[k] = 1.0 - dhdn * Wh.sum()
+        dPdh = direct.kernel(r, np.full(r.shape, h[i]))[4]
+        dPdh[nb == i] = 0.0
+        ze[k] = dhdn * (dPdh * m[nb]).sum()
+    return om, ze
+
+
+def pm_change_at(x, m, h, n_gas, targets, G=1.0):
+    """For gas targets, pm_accel minus the larger-radius law of every pair
+    (direct.direct): the acceleration and potential changes, from neighbour
+    searches.  Only gas pairs closer than the larger of their two radii
+    differ (beyond it every kernel is Newtonian and W_r vanishes), so each
+    target looks at the gas cells within max(h_i, largest h); z_j = zeta_j /
+    Omega_j comes from `omega_zeta_at`."""
+    from scipy.spatial import cKDTree
+    x, m, h = (np.asarray(v, np.float64) for v in (x, m, h))
+    xg, mg, hg = x[:n_gas], m[:n_gas], h[:n_gas]
+    kd = cKDTree(xg)
+    hmax = hg.max()
+    zc = {}
+
+    def z_of(js):
+        need = [j for j in js if j not in zc]
+        if need:
+            om, ze = omega_zeta_at(xg, mg, hg, need, kd)
+            zc.update(zip(need, ze / om))
+        return np.array([zc[j] for j in js])
+
+    da = np.zeros((len(targets), 3))
+    dp = np.zeros(len(targets))
+    for k, i in enumerate(targets):
+        nb = np.asarray(kd.query_ball_point(xg[i], max(hg[i], hmax)), dtype=np.int64)
+        nb = nb[nb != i]
+        d = xg[nb] - xg[i]
+        r = np.sqrt((d * d).sum(1))
+        near = r < np.maximum(hg[i], hg[nb])
+        nb, d, r = nb[near], d[near], r[near]
+        hi, hj = np.full(r.shape, hg[i]), hg[nb]
+        Fi, Pi = direct.kernel(r, hi)[:2]
+        Fj, Pj = direct.kernel(r, hj)[:2]
+        Fm, Pm = direct.kernel(r, np.maximum(hi, hj))[:2]
+        da[k] = G * ((mg[nb] * (0.5 * (Fi + Fj) - Fm))[:, None] * d).sum(0)
+        dp[k] = -G * (mg[nb] * (0.5 * (Pi + Pj) - Pm)).sum()
+        _, Wri, _ = kernel_W(r, hi)
+        _, Wrj, _ = kernel_W(r, hj)
+        c = z_of([int(i)])[0] * Wri + (mg[nb] / mg[i]) * z_of(nb.tolist()) * Wrj
+        rs = np.where(r > 0, r, 1.0)
+        da[k] -= 0.5 * G * ((c / rs)[:, None] * d).sum(0)
+    return da, dp

@@ -3,9 +3,10 @@ full size (4,194,304 clustered gas + 2048 sink binaries, seed 2), in the
 benchmark's launch configuration (leaf 32, group 32, theta 0.5, quadrupole):
 the tidal tensor and jerk, and the radiation sums (6-bin columns, IR energy
 density), on the targets of sampled groups against the oracle's frozen-list
-evaluation of the same groups.  The GPU's opening decisions are checked equal
+evaluation of the same groups (the GPU's opening decisions are checked equal
 to the oracle's first, through the per-group list counts of the force pass,
-which the other passes share.
+which the other passes share); and the symmetrised adaptive softening on
+sampled gas targets against the oracle's neighbour-search evaluation.
 """
 import copy
 
@@ -13,9 +14,10 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import pm as opm
 from oracle import rad as orad
 from oracle import tree as otree
-from synth import precision_cloud
+from synth import precision_cloud, subsample
 
 pytestmark = pytest.mark.gpu
 
@@ -179,3 +181,42 @@ def test_precision4m_rad_sums_sampled_groups(c2, sampled, rad_ref, form):
     else:
         assert np.median(et) < 1e-6 and et.max() < 1e-4
         assert np.median(ee) < 1e-6 and ee.max() < 1e-4
+
+
+def test_precision4m_adaptive_sampled_targets(c2):
+    """FP64: on sampled gas targets the change from sf_grav_accel on the same
+    handle equals the oracle's change of pair law (node terms and far pairs
+    are the same in both walks), and Omega, zeta equal the oracle's neighbour
+    sums.  FP32C: the adaptive result against the FP64 larger-radius result
+    plus that change."""
+    _say("precision4m adaptive softening, sampled targets")
+    L = _lib()
+    ng = c2.n_gas
+    x64, m64, h64 = (v.astype(np.float64) for v in (c2.x, c2.m, c2.h))
+    out = {}
+    for form, arrs in (("fp64", (x64, m64, h64)), ("fp32c", (c2.x, c2.m, c2.h))):
+        x, m, h = _dev(*arrs)
+        o = L.make_opts(form=form, n_gas=ng, leaf_cap=LEAF, group_cap=GROUP)
+        t = L.sf_grav_build_tree(x, m, h, o)
+        a0, p0 = L.sf_grav_accel(t, None, None, None, o)
+        a, p, aux = L.sf_grav_accel_adaptive(t, o, want_aux=True)
+        torch.cuda.synchronize()
+        L.sf_grav_tree_free(t)
+        out[form] = [u.double().cpu().numpy() for u in (a0, p0, a, p, aux)]
+    tg = subsample(ng, 200, 8)
+    _say("oracle pair-law change at", tg.size, "targets")
+    da, dp = opm.pm_change_at(x64, m64, h64, ng, tg)
+    om, ze = opm.omega_zeta_at(x64[:ng], m64[:ng], h64[:ng], tg)
+    a0, p0, a, p, aux = (u[tg] for u in out["fp64"])
+    scale = np.linalg.norm(a0 + da, axis=1)
+    e = np.linalg.norm((a - a0) - da, axis=1) / scale
+    ep = np.abs((p - p0) - dp) / np.abs(p0 + dp)
+    print(f"fp64: change err max {e.max():.2e}, potential {ep.max():.2e}; change/|a| median "
+          f"{np.median(np.linalg.norm(da, axis=1) / scale):.2e}", flush=True)
+    assert e.max() < 1e-10 and ep.max() < 1e-12
+    assert np.allclose(aux[:, 0], om, rtol=1e-11, atol=0)
+    assert np.allclose(aux[:, 1], ze, rtol=1e-10, atol=1e-12 * np.abs(ze).max())
+    a32 = out["fp32c"][2][tg]
+    e32 = np.linalg.norm(a32 - (a0 + da), axis=1) / scale
+    print(f"fp32c: err median {np.median(e32):.2e} p99 {np.quantile(e32, 0.99):.2e}", flush=True)
+    assert np.median(e32) < 2e-6 and np.quantile(e32, 0.99) < 2e-5

@@ -102,3 +102,27 @@ def test_newtonian_beyond_radii_and_sinks_keep_max_rule():
     dd = far - x
     rr = np.linalg.norm(dd, axis=1)
     assert np.allclose(a2[:120], a + 0.3 * dd / rr[:, None] ** 3, rtol=1e-12, atol=1e-15)
+
+
+def test_neighbour_search_form_equals_dense_sums():
+    # the sampled form used at full size (k-d tree neighbours of chosen
+    # targets) against the dense O(N^2) sums it restates: Omega, zeta, and
+    # pm_accel minus the larger-radius law, with sinks and unequal radii
+    n, n_gas = 500, 470
+    x, m = _cloud(n, 21)
+    h = np.empty(n)
+    h[:n_gas] = pm.solve_h(x[:n_gas])
+    h[n_gas:] = 0.02
+    om, ze = pm.omega_zeta(x[:n_gas], m[:n_gas], h[:n_gas])
+    idx = [0, 7, 100, 250, 469]
+    om2, ze2 = pm.omega_zeta_at(x[:n_gas], m[:n_gas], h[:n_gas], idx)
+    assert np.allclose(om2, om[idx], rtol=1e-13, atol=0)
+    assert np.allclose(ze2, ze[idx], rtol=1e-12, atol=1e-14 * np.abs(ze).max())
+    ap, pp = pm.pm_accel(x, m, h, n_gas=n_gas)
+    ad, pd = direct.direct(x, m, h)
+    da, dp = pm.pm_change_at(x, m, h, n_gas, idx)
+    scale = np.linalg.norm(ap[idx], axis=1)
+    assert np.max(np.linalg.norm(da - (ap - ad)[idx], axis=1) / scale) < 1e-12
+    assert np.max(np.abs(dp - (pp - pd)[idx]) / np.abs(pp[idx])) < 1e-12
+    # the change is not trivially zero here
+    assert np.min(np.linalg.norm((ap - ad)[idx], axis=1) / scale) > 1e-6
