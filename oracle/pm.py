@@ -4,8 +4,9 @@ Adaptive gas-gas softening with symmetrised kernels and correction terms
 (Sec. 2.2.1: gas softening follows the cell's kernel radius H_i, set by the
 effective neighbour number N_NGB = 32 of Table 1, with the symmetrisation and
 extra terms that make the interaction conserve momentum and energy), in
-plain FP64 numpy, O(N^2).  Readings (the cited force-law equations are not
-in the paper):
+plain FP64 numpy: O(N^2) dense sums, and the same sums at chosen targets
+over neighbours found with scipy's k-d tree (for checks at full size).
+Readings (the cited force-law equations are not in the paper):
 
 * the kernel radius of a gas cell solves (4 pi / 3) h_i^3 n_i = N_NGB with the
   number density n_i = sum_j W(r_ij, h_i) over gas cells, self included, and
