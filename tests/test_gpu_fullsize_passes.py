@@ -5,8 +5,11 @@ the tidal tensor and jerk, and the radiation sums (6-bin columns, IR energy
 density), on the targets of sampled groups against the oracle's frozen-list
 evaluation of the same groups (the GPU's opening decisions are checked equal
 to the oracle's first, through the per-group list counts of the force pass,
-which the other passes share); and the symmetrised adaptive softening on
-sampled gas targets against the oracle's neighbour-search evaluation.
+which the other passes share); the tree adjoint with cotangents on those
+groups' targets only, against torch autograd of the oracle's evaluation of
+the same lists (the gradient reaches every particle through the node
+moments); and the symmetrised adaptive softening on sampled gas targets
+against the oracle's neighbour-search evaluation.
 """
 import copy
 
@@ -220,3 +223,47 @@ def test_precision4m_adaptive_sampled_targets(c2):
     e32 = np.linalg.norm(a32 - (a0 + da), axis=1) / scale
     print(f"fp32c: err median {np.median(e32):.2e} p99 {np.quantile(e32, 0.99):.2e}", flush=True)
     assert np.median(e32) < 2e-6 and np.quantile(e32, 0.99) < 2e-5
+
+
+@pytest.fixture(scope="module")
+def adjoint_ref(c2, sampled):
+    """Cotangents (exact in FP32) on the targets of the sampled groups, zero
+    elsewhere, and the oracle's gradient with respect to every position,
+    mass and softening length."""
+    lists, sel = sampled
+    tree = lists.tree
+    tgt = tree.order[np.concatenate([np.arange(lists.groups[g][0],
+                                               lists.groups[g][0] + lists.groups[g][1])
+                                     for g in sel])]
+    rng = np.random.default_rng(10)
+    ga = np.zeros((c2.n, 3))
+    gp = np.zeros(c2.n)
+    ga[tgt] = rng.standard_normal((tgt.size, 3)).astype(np.float32)
+    gp[tgt] = rng.standard_normal(tgt.size).astype(np.float32)
+    X, M, H = (torch.tensor(v.astype(np.float64), requires_grad=True) for v in (c2.x, c2.m, c2.h))
+    _say("oracle tree adjoint of groups", sel)
+    a, p = otree.tree_eval(X, M, H, c2.n_gas, lists, 1.0, 2, targets=tgt)
+    ((a * torch.tensor(ga[tgt])).sum() + (p * torch.tensor(gp[tgt])).sum()).backward()
+    return ga, gp, (X.grad.numpy(), M.grad.numpy(), H.grad.numpy())
+
+
+@pytest.mark.parametrize("form,rtol", [("fp64", 1e-8), ("fp32c", 2e-4)])
+def test_precision4m_tree_adjoint_sampled_groups(c2, sampled, adjoint_ref, form, rtol):
+    _say("precision4m tree adjoint, sampled groups", form)
+    lists, _ = sampled
+    ga, gp, ref = adjoint_ref
+    L = _lib()
+    t, o, dt = _handle(c2, form, lists)
+    g_a = torch.as_tensor(ga).to(dtype=dt, device="cuda").contiguous()
+    g_p = torch.as_tensor(gp).to(dtype=dt, device="cuda").contiguous()
+    got = L.sf_grav_accel_backward(t, None, None, None, o, g_a, g_p)
+    torch.cuda.synchronize()
+    L.sf_grav_tree_free(t)
+    for g, r, name in zip(got, ref, ("x", "m", "h")):
+        g = g.double().cpu().numpy()
+        scale = np.abs(r).max()
+        err = np.abs(g - r) / (np.abs(r) + 1e-3 * scale)
+        print(f"{form} d/d{name}: err median {np.median(err):.2e} p99 "
+              f"{np.quantile(err, 0.99):.2e} max {err.max():.2e}", flush=True)
+        assert np.quantile(err, 0.99) <= rtol and np.median(err) <= rtol / 10, name
+        assert err.max() <= 10 * rtol, name   # the targets' own and near entries
