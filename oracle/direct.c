@@ -219,6 +219,55 @@ void or_direct_vjp(int64_t n, const double *x, const double *m, const double *h,
     }
 }
 
+/* The same gradients when only the particles act[0..nact) carry nonzero
+ * cotangents: every term above is a multiple of a cotangent of i or of k, so
+ * a particle k outside act receives terms only from the i in act, and the
+ * terms skipped are exact zeros (checks at full size, O(nact * n)).  flag[k]
+ * is nonzero exactly for the k in act. */
+void or_direct_vjp_sparse(int64_t n, const double *x, const double *m, const double *h,
+                          double G, const double *ga, const double *gp, int64_t nact,
+                          const int64_t *act, const unsigned char *flag,
+                          double *gx, double *gm, double *gh)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < n; ++k) {
+        double xk = x[3 * k], yk = x[3 * k + 1], zk = x[3 * k + 2], hk = h[k];
+        double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0, sh = 0.0;
+        const int64_t cnt = flag[k] ? n : nact;
+        for (int64_t q = 0; q < cnt; ++q) {
+            const int64_t i = flag[k] ? q : act[q];
+            if (i == k) continue;
+            double dx = xk - x[3 * i], dy = yk - x[3 * i + 1], dz = zk - x[3 * i + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double hik = hk > h[i] ? hk : h[i];
+            double F, P, FrR, dFh, dPh;
+            kern(r, hik, &F, &P, &FrR, &dFh, &dPh);
+            double wx = m[k] * ga[3 * i] - m[i] * ga[3 * k];
+            double wy = m[k] * ga[3 * i + 1] - m[i] * ga[3 * k + 1];
+            double wz = m[k] * ga[3 * i + 2] - m[i] * ga[3 * k + 2];
+            double wd = wx * dx + wy * dy + wz * dz;
+            double c = (m[k] * gp[i] + m[i] * gp[k]) * F;
+            sx += wx * F + wd * FrR * dx + c * dx;
+            sy += wy * F + wd * FrR * dy + c * dy;
+            sz += wz * F + wd * FrR * dz + c * dz;
+            double gid = ga[3 * i] * dx + ga[3 * i + 1] * dy + ga[3 * i + 2] * dz;
+            sm += gid * F - gp[i] * P;
+            double share = (hk > h[i]) ? 1.0 : (hk == h[i] ? 0.5 : 0.0);
+            if (share > 0.0) {
+                double gkd = -(ga[3 * k] * dx + ga[3 * k + 1] * dy + ga[3 * k + 2] * dz);
+                double t_ik = m[k] * (gid * dFh - gp[i] * dPh);
+                double t_ki = m[i] * (gkd * dFh - gp[k] * dPh);
+                sh += share * (t_ik + t_ki);
+            }
+        }
+        gx[3 * k] = G * sx;
+        gx[3 * k + 1] = G * sy;
+        gx[3 * k + 2] = G * sz;
+        gm[k] = G * sm;
+        gh[k] = G * sh;
+    }
+}
+
 /* The part of L that depends on particle k: every ordered pair with k as
  * target or source.  Perturbing x_k, m_k or h_k changes L by exactly the
  * change of this sum, so central differences of it need no O(N^2) cancellation.

@@ -22,6 +22,9 @@ def lib():
                                 ctypes.c_int64, _L, _D, _D]
         L.or_direct_vjp.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
                                     _D, _D, _D, _D, _D]
+        L.or_direct_vjp_sparse.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                           _D, _D, ctypes.c_int64, _L,
+                                           ctypes.POINTER(ctypes.c_ubyte), _D, _D, _D]
         L.or_pair_loss.argtypes = [ctypes.c_int64, _D, _D, _D, ctypes.c_double,
                                    _D, _D, ctypes.c_int64, _D, ctypes.c_double,
                                    ctypes.c_double]
@@ -92,6 +95,22 @@ def direct_vjp(x, m, h, ga, gp, G=1.0):
     gx, gm, gh = np.empty((n, 3)), np.empty(n), np.empty(n)
     lib().or_direct_vjp(n, _p(x), _p(m), _p(h), float(G), _p(ga), _p(gp),
                         _p(gx), _p(gm), _p(gh))
+    return gx, gm, gh
+
+
+def direct_vjp_sparse(x, m, h, ga, gp, G=1.0):
+    """direct_vjp when few particles carry nonzero cotangents: the same
+    gradients, skipping the pairs whose terms are exact zeros (O(k n) for k
+    particles with cotangents)."""
+    x, m, h, ga, gp = _d(x), _d(m), _d(h), _d(ga), _d(gp)
+    n = x.shape[0]
+    flag = np.ascontiguousarray((np.abs(ga).sum(1) + np.abs(gp)) > 0, dtype=np.uint8)
+    act = np.ascontiguousarray(np.nonzero(flag)[0], dtype=np.int64)
+    gx, gm, gh = np.empty((n, 3)), np.empty(n), np.empty(n)
+    lib().or_direct_vjp_sparse(n, _p(x), _p(m), _p(h), float(G), _p(ga), _p(gp), act.size,
+                               act.ctypes.data_as(_L),
+                               flag.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                               _p(gx), _p(gm), _p(gh))
     return gx, gm, gh
 
 

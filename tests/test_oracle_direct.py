@@ -176,3 +176,23 @@ def test_adjoint_matches_central_differences():
         fd = direct.fd_gradient(x, m, h, ga, gp, k, eps=1e-6)
         an = np.array([gx[k, 0], gx[k, 1], gx[k, 2], gm[k], gh[k]])
         assert np.allclose(an, fd, rtol=2e-6, atol=2e-6 * np.abs(an).max()), (k, an, fd)
+
+
+def test_sparse_cotangent_vjp_equals_dense():
+    # the O(k n) form for cotangents on a few particles, used at full size,
+    # against the dense VJP: the skipped pairs' terms are exact zeros
+    rng = np.random.default_rng(31)
+    n = 700
+    x = rng.standard_normal((n, 3))
+    m = rng.uniform(0.5, 1.5, n)
+    h = rng.uniform(0.05, 0.4, n)
+    h[::7] = h[0]   # equal radii (the split tie of dL/dh)
+    ga, gp = np.zeros((n, 3)), np.zeros(n)
+    act = rng.choice(n, 23, replace=False)
+    ga[act] = rng.standard_normal((act.size, 3))
+    gp[act] = rng.standard_normal(act.size)
+    dense = direct.direct_vjp(x, m, h, ga, gp)
+    sparse = direct.direct_vjp_sparse(x, m, h, ga, gp)
+    for a, b in zip(dense, sparse):
+        assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(a).max())
+    assert np.count_nonzero(sparse[0]) > 3 * (n - act.size)   # every particle receives terms
