@@ -63,6 +63,32 @@ def test_sinks_pass_matches_oracle(n):
     assert np.allclose(t[:, 2], dt2, rtol=1e-13) and np.allclose(t[:, 3], dtt, rtol=1e-12)
 
 
+def test_sinks_pass_precision4m_sinks():
+    # the benchmark workload's 4096 sinks (2048 close binaries, separations
+    # log-uniform in [1e-5, 1e-3] around the sink softening), FP64
+    from synth import precision_cloud, velocities
+    _say("sinks pass, the 4096 sinks of precision4m")
+    ps = precision_cloud(1 << 22, 2048, seed=2)
+    sl = slice(ps.n_gas, ps.n)
+    x, m, h = (np.asarray(v[sl], dtype=np.float64) for v in (ps.x, ps.m, ps.h))
+    v = velocities(ps.n, seed=2, dtype=np.float64)[sl]
+    L = _lib()
+    X, V, M, H = _dev(x, v, m, h)
+    out = L.sf_grav_sinks(X, V, M, H, G=1.0, eta=0.01)
+    torch.cuda.synchronize()
+    got = {k: t.cpu().numpy() for k, t in out.items()}
+    ar, pr = odirect.direct(x, m, h)
+    Tr, Jr = odirect.direct_tidal(x, m, h, v)
+    for k, ref in (("acc", ar), ("pot", pr), ("tidal", Tr), ("jerk", Jr)):
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got[k] - ref)) <= 1e-12 * scale, k
+    tc, td = osinks.two_body_times(x, v, m, h)
+    dt2, dtt = osinks.timesteps(x, v, m, h, eta=0.01)
+    t = got["times"]
+    assert np.allclose(t[:, 0], tc, rtol=1e-13) and np.allclose(t[:, 1], td, rtol=1e-13)
+    assert np.allclose(t[:, 2], dt2, rtol=1e-13) and np.allclose(t[:, 3], dtt, rtol=1e-12)
+
+
 def test_hermite_step_matches_oracle():
     _say("hermite step")
     L = _lib()
