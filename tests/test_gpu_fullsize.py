@@ -4,7 +4,9 @@ oracle computes one by one (sampled groups and targets), plus properties that
 hold at any size: determinism of the forward pass and translation invariance.
 
 precision4m = 4,194,304 clustered gas + 2048 sink binaries (seed 2);
-clustered1m = 1,048,576 clustered gas + 256 sinks on gas positions (seed 1).
+clustered1m = 1,048,576 clustered gas + 256 sinks on gas positions (seed 1);
+fractal16m = 16,777,216 gas in a three-level Plummer-in-Plummer hierarchy +
+10,000 sinks (seed 4), the largest workload (742,488 groups).
 """
 import numpy as np
 import pytest
@@ -12,7 +14,7 @@ import torch
 
 from oracle import direct as odirect
 from oracle import tree as otree
-from synth import clustered_cloud, precision_cloud, subsample
+from synth import clustered_cloud, make_config, precision_cloud, subsample
 
 pytestmark = pytest.mark.gpu
 
@@ -241,3 +243,12 @@ def test_translation_invariance_fp32c():
     for k in range(2):
         e = _relerr(res[1][k], res[0][k])
         assert np.median(e) <= 1e-6 and np.quantile(e, 0.99) <= 1e-5, (k, np.median(e), e.max())
+
+
+# ---------------------------------------------------------------- fractal16m
+
+def test_fractal16m_tree_sampled_groups():
+    _say("generating fractal16m")
+    c4 = make_config("fractal16m")
+    _say("fractal16m tree, sampled groups")
+    assert _tree_sampled(c4, k_rand=4, k_sink=2, seed=4)[0] > 100
