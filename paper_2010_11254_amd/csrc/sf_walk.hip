@@ -271,9 +271,11 @@ __global__ __launch_bounds__(64) void k_walk_groups(WalkArgs<T> a) {
             ev.ay.zero();
             ev.az.zero();
             ev.ap.zero();
+            // full batches hold a multiple of k entries, so that none ends
+            // with a step in which only some of the copies have an entry
             walk_task<STATS>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi, hg,
                              gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks,
-                             kPPBatch<R>);
+                             kPPBatch<R> / k * k, 64u / k * k);
             double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
             // sum the k copies of each target in a fixed order, through LDS
             // (the stage is free once the task's batches are done)
