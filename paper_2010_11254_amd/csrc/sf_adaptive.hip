@@ -389,9 +389,11 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         ev.ap.zero();
         uint32_t npc, npp;
         uint64_t cks;
+        // full batches hold a multiple of the copy count (no partial last step)
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
                          a.ghmax[g], a.gfirst[g], a.gfirst[g] + a.gcount[g],
-                         task_ag_group(a.nd, g), a.err, npc, npp, cks, kPPBatch<R>);
+                         task_ag_group(a.nd, g), a.err, npc, npp, cks,
+                         kPPBatch<R> / ev.sp.k * ev.sp.k, 64u / ev.sp.k * ev.sp.k);
         double v[4] = {ev.ax.value(), ev.ay.value(), ev.az.value(), ev.ap.value()};
         ev.sp.template reduce<4>(v, reinterpret_cast<double *>(&stage), (uint32_t)threadIdx.x);
         if (ev.on && threadIdx.x < ev.sp.gc) {

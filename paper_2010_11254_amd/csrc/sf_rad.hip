@@ -196,8 +196,11 @@ __global__ __launch_bounds__(64) void k_walk_rad(RadArgs<T> a) {
         for (int c = 0; c < kR; ++c) ev.acc[c].zero();
         uint32_t npc, npp;
         uint64_t cks;
+        // full batches hold a multiple of the copy count (no partial last step)
+        const uint32_t kb = 64u / ev.sp.k * ev.sp.k;
         walk_task<false>(a.nd, L, a.gstack + (int64_t)blockIdx.x * kStack, ev, blo, bhi,
-                         a.ghmax[g], gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks);
+                         a.ghmax[g], gf, gf + gc, task_ag_group(a.nd, g), a.err, npc, npp, cks,
+                         kb, kb);
         double v[kR];
         for (int c = 0; c < kR; ++c) v[c] = ev.acc[c].value();
         // the stage is free once the task's batches are done
