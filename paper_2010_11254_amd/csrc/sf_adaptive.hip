@@ -62,6 +62,35 @@ __device__ __forceinline__ void kern(R r2, R ri, R h, R &F, R &P, R &Ph) {
     }
 }
 
+// Softened F and P of the M4 spline with support h (Newtonian at and beyond
+// h) and the spline's radial derivative W_r = dW/dr (zero beyond h), from
+// the pair's r^2, ri = rsq(r^2), r, h and 1/h.  Both spline pieces are
+// evaluated and one is selected, so lanes on different pieces follow one
+// instruction stream; the outer piece's 1/u is h ri (capped at 2, its value
+// at u = 1/2), so no further reciprocal or square root is needed.
+template <typename R>
+__device__ __forceinline__ void sym_soft(R r2, R ri, R r, R h, R hinv, R &F, R &P, R &Wr) {
+    const R u = r * hinv;
+    const R u2 = u * u;
+    const R hinv2 = hinv * hinv;
+    const R hinv3 = hinv2 * hinv;
+    const R us = u > R(0.5) ? u : R(0.5);
+    const R iu = pos_min(h * ri, R(2));
+    const R Fi = R(32.0 / 3.0) + u2 * (R(-192.0 / 5.0) + R(32.0) * u);
+    const R Pi = R(14.0 / 5.0) + u2 * (R(-16.0 / 3.0) + u2 * (R(48.0 / 5.0) + R(-32.0 / 5.0) * u));
+    const R Fo = R(64.0 / 3.0) + us * (R(-48.0) + us * (R(192.0 / 5.0) + us * R(-32.0 / 3.0))) -
+                 R(1.0 / 15.0) * iu * iu * iu;
+    const R Po = R(16.0 / 5.0) - R(1.0 / 15.0) * iu +
+                 us * us * (R(-32.0 / 3.0) + us * (R(16.0) + us * (R(-48.0 / 5.0) + us * R(32.0 / 15.0))));
+    const R om = R(1) - us;
+    const R dk = u < R(0.5) ? u * (R(-12) + R(18) * u) : R(-6) * om * om;
+    const bool inner = u < R(0.5);
+    const bool inside = r2 < h * h;
+    F = inside ? (inner ? Fi : Fo) * hinv3 : ri * ri * ri;
+    P = inside ? (inner ? Pi : Po) * hinv : ri;
+    Wr = inside ? R(8.0 / 3.14159265358979323846) * hinv2 * hinv2 * dk : R(0);
+}
+
 template <typename T>
 struct AdArgs {
     WalkNodes nd;
@@ -149,7 +178,7 @@ struct ForceEval {
     const AdArgs<T> *a;
     AdStage<R> *st;
     double cen[3];
-    R tx, ty, tz, th, tminv, tz_;   // tminv = 1/m of the target; tz_: its zeta / Omega
+    R tx, ty, tz, th, thinv, tminv, tz_;   // tminv = 1/m of the target; tz_: its zeta / Omega
     R bl[3], bh[3], hg2;            // group box in the form's frame, largest h squared
     int32_t tidx;
     bool on;
@@ -251,25 +280,22 @@ struct ForceEval {
                     const R dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
                     const R r2 = dx * dx + dy * dy + dz * dz;
                     const R ri = rsq(r2);
-                    R F, P;
-                    R c = R(0);   // extra term over r
-                    if (q.gas) {
-                        R Fi, Pi, Phi, Fj, Pj, Phj;
-                        kern<R>(r2, ri, th, Fi, Pi, Phi);
-                        kern<R>(r2, ri, q.h, Fj, Pj, Phj);
-                        F = R(0.5) * (Fi + Fj);
-                        P = R(0.5) * (Pi + Pj);
-                        const R r = r_of(r2, ri);
-                        if (r > R(0)) {
-                            R W, Wri, Wh, Wrj;
-                            Wri = Wrj = R(0);
-                            if (r < th) m4<R>(r, rcp(th), W, Wri, Wh);
-                            if (r < q.h) m4<R>(r, rcp(q.h), W, Wrj, Wh);
-                            c = R(0.5) * (tz_ * Wri + q.m * tminv * q.zz * Wrj) * ri;
+                    const R r = r_of(r2, ri);
+                    R F = ri * ri * ri, P = ri;   // Newtonian beyond both radii
+                    R c = R(0);                     // extra term over r
+                    const R hm = pos_max(th, q.h);
+                    if (r2 < hm * hm) {   // inside at least one radius: one branch for the wave
+                        if (q.gas) {
+                            R Fi, Pi, Wri, Fj, Pj, Wrj;
+                            sym_soft<R>(r2, ri, r, th, thinv, Fi, Pi, Wri);
+                            sym_soft<R>(r2, ri, r, q.h, rcp(q.h), Fj, Pj, Wrj);
+                            F = R(0.5) * (Fi + Fj);
+                            P = R(0.5) * (Pi + Pj);
+                            if (r > R(0)) c = R(0.5) * (tz_ * Wri + q.m * tminv * q.zz * Wrj) * ri;
+                        } else {
+                            R Wr;
+                            sym_soft<R>(r2, ri, r, hm, rcp(hm), F, P, Wr);
                         }
-                    } else {
-                        R Ph;
-                        kern<R>(r2, ri, th > q.h ? th : q.h, F, P, Ph);
                     }
                     const R k = q.m * F - c;
                     bx += k * dx;
@@ -373,6 +399,7 @@ __global__ __launch_bounds__(64) void k_adaptive_force(AdArgs<T> a) {
         int64_t i;
         double blo[3], bhi[3];
         if (!group_target(a, ev, g, i, blo, bhi)) continue;
+        ev.thinv = rcp(ev.th);
         ev.tminv = rcp((R)a.ms[i]);
         ev.tz_ = (R)a.z[i];
         for (int d = 0; d < 3; ++d) {
