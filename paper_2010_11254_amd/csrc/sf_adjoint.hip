@@ -374,7 +374,8 @@ __device__ __forceinline__ void bpair(R dx, R dy, R dz, R mj, R hj2, R hj, R hi2
         const R hh2 = hj2 > hi2 ? hj2 : hi2;
         const bool soft = r2 < hh2;
         if (soft) {
-            dsoft<R>(r2, hj > hi ? hj : hi, F, P, FrR, dFh, dPh);
+            const R hh = pos_max(hj, hi);
+            dsoft_ri<R>(r2, ri, hh, rcp(hh), F, P, FrR, dFh, dPh);
             if (self) { F = R(0); P = R(0); FrR = R(0); dFh = R(0); dPh = R(0); }
             Th = mj * (ad * dFh - gp * dPh);
         }

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void k_direct(int64_t n, int64_t n_gas, int64_
                 const R hh2 = q.h2 > me.h2 ? q.h2 : me.h2;
                 if (r2 < hh2) {
                     R FrR, dFh, dPh;
-                    dsoft<R>(r2, q.h > me.h ? q.h : me.h, F, P, FrR, dFh, dPh);
+                    const R hh = pos_max(q.h, me.h);
+                    dsoft_ri<R>(r2, ri, hh, rcp(hh), F, P, FrR, dFh, dPh);
                     if (q.idx == my_idx) { F = R(0); P = R(0); }
                 }
                 const R mF = q.m * F;

@@ -46,7 +46,7 @@ __device__ __forceinline__ void ext_pair(R dx, R dy, R dz, R wx, R wy, R wz, R m
         const R hh = pos_max(hj, ti);
         if (r2 < hh * hh) {
             R dFh, dPh;
-            dsoft<R>(r2, hh, F, P, FrR, dFh, dPh);
+            dsoft_ri<R>(r2, ri, hh, rcp(hh), F, P, FrR, dFh, dPh);
         }
         if (self) F = P = FrR = R(0);
     }

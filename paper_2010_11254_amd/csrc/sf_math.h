@@ -135,4 +135,41 @@ __device__ __forceinline__ void dsoft(R r2, R h, R &F, R &P, R &FrR, R &dFh, R &
     }
 }
 
+// The same five factors from quantities the pair evaluation already holds:
+// ri = rsq(r^2), h and 1/h.  Both spline pieces are evaluated and one is
+// selected (no divergent branch), and the outer piece's 1/u is h ri capped at
+// 2 (its value at u = 1/2), so no further square root or reciprocal is taken.
+template <typename R>
+__device__ __forceinline__ void dsoft_ri(R r2, R ri, R h, R hinv, R &F, R &P, R &FrR, R &dFh,
+                                         R &dPh) {
+    const R r = r_of(r2, ri);
+    const R u = r * hinv;
+    const R u2 = u * u;
+    const R hinv2 = hinv * hinv;
+    const R hinv3 = hinv2 * hinv;
+    const R us = u > R(0.5) ? u : R(0.5);
+    const R iu = pos_min(h * ri, R(2));
+    const R iu2 = iu * iu;
+    const R om = R(1) - us;
+    const R om2 = om * om;
+    const bool inner = u < R(0.5);
+    const R Fi = R(32.0 / 3.0) + u2 * (R(-192.0 / 5.0) + R(32.0) * u);
+    const R Fo = R(64.0 / 3.0) + us * (R(-48.0) + us * (R(192.0 / 5.0) + us * R(-32.0 / 3.0))) -
+                 R(1.0 / 15.0) * iu2 * iu;
+    const R Pi = R(14.0 / 5.0) + u2 * (R(-16.0 / 3.0) + u2 * (R(48.0 / 5.0) + R(-32.0 / 5.0) * u));
+    const R Po = R(16.0 / 5.0) - R(1.0 / 15.0) * iu +
+                 us * us * (R(-32.0 / 3.0) + us * (R(16.0) + us * (R(-48.0 / 5.0) + us * R(32.0 / 15.0))));
+    const R Ri = R(-384.0 / 5.0) + R(96.0) * u;
+    const R Ro = R(-48.0) * iu + R(384.0 / 5.0) - R(32.0) * us + R(0.2) * iu2 * iu2 * iu;
+    const R Dfi = R(-32.0) * (R(1) - R(6) * u2 + R(6) * u2 * u);
+    const R Dfo = R(-64.0) * om2 * om;
+    const R Dpi = -(R(14.0 / 5.0) + u2 * (R(-16.0) + u2 * (R(48.0) + R(-192.0 / 5.0) * u)));
+    const R Dpo = -(om2 * om2 * (R(16.0) - R(64.0 / 5.0) * om));
+    F = (inner ? Fi : Fo) * hinv3;
+    P = (inner ? Pi : Po) * hinv;
+    FrR = (inner ? Ri : Ro) * hinv3 * hinv2;
+    dFh = (inner ? Dfi : Dfo) * hinv2 * hinv2;
+    dPh = (inner ? Dpi : Dpo) * hinv2;
+}
+
 }  // namespace sf
