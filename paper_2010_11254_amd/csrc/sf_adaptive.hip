@@ -49,19 +49,6 @@ __device__ __forceinline__ void m4(R r, R hinv, R &W, R &Wr, R &Wh) {
     Wh = -c * hinv * (R(3) * k + u * dk);
 }
 
-// F, P and dP/dh of the softened kernel with support h (Newtonian beyond).
-template <typename R>
-__device__ __forceinline__ void kern(R r2, R ri, R h, R &F, R &P, R &Ph) {
-    if (r2 < h * h) {
-        R FrR, dFh;
-        dsoft<R>(r2, h, F, P, FrR, dFh, Ph);
-    } else {
-        F = ri * ri * ri;
-        P = ri;
-        Ph = R(0);
-    }
-}
-
 // Softened F and P of the M4 spline with support h (Newtonian at and beyond
 // h) and the spline's radial derivative W_r = dW/dr (zero beyond h), from
 // the pair's r^2, ri = rsq(r^2), r, h and 1/h.  Both spline pieces are
@@ -161,9 +148,9 @@ struct SumsEval {
                 m4<R>(r, thinv, W, Wr, Wh);
                 sW += W;
                 sWh += Wh;
-                if (s.idx != tidx) {
-                    R F, P, Ph;
-                    kern<R>(r2, ri, th, F, P, Ph);
+                if (s.idx != tidx) {   // r < h here: the softened factors, branch-free
+                    R F, P, FrR, dFh, Ph;
+                    dsoft_ri<R>(r2, ri, th, thinv, F, P, FrR, dFh, Ph);
                     sPh += s.m * Ph;
                 }
             });
