@@ -121,9 +121,9 @@ __device__ __forceinline__ void multipole(R rx, R ry, R rz, R M, R qxx, R qyy, R
         const R qz = qxz * rx + qyz * ry + qzz * rz;
         const R rqr = qx * rx + qy * ry + qz * rz;
         const R ri5 = ri2 * ri2 * ri;
-        const R t = R(0.5) * rqr * ri5;
-        bp -= Mri + t;
-        const R c = -(Mri + R(5) * t) * ri2;
+        const R t2 = rqr * ri5;                          // twice the quadrupole potential term
+        bp -= fma(R(0.5), t2, Mri);
+        const R c = -fma(R(2.5), t2, Mri) * ri2;
         bx = fma(c, rx, bx);
         by = fma(c, ry, by);
         bz = fma(c, rz, bz);
