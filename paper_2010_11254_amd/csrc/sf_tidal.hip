@@ -95,8 +95,11 @@ __device__ __forceinline__ void node_term(const XNode<typename FormT<FORM>::R> &
     // g and phi with the node expansion of ORDER (r = target - centre of mass)
     multipole<R, ORDER>(tx - s.x, ty - s.y, tz - s.z, s.M, s.qxx, s.qyy, s.qxy, s.qxz, s.qyz,
                         -(s.qxx + s.qyy), b[0], b[1], b[2], b[3]);
-    // T and j from the monopole (d = centre of mass - target)
-    const R dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+    // T and j from the monopole.  Every tidal and jerk term is even in the
+    // separation (products of two of its components, and (d.w) d), so the
+    // expansion's r = target - centre of mass serves for d = -r exactly, and
+    // r, r^2 and 1/r are the ones computed for the expansion.
+    const R dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
     const R ri = rsq(r2);
     const R mF = s.M * ri * ri * ri;
